@@ -1,0 +1,184 @@
+"""Seeded synthetic inputs for the SSH hot path.
+
+This module only draws inputs: series, queries, the random filter and the
+random numbers of consistent weighted sampling.  It holds none of the
+method's arithmetic (no sketching, shingling, hashing or DTW), so that the
+HIP path and the CPU oracle can both consume its outputs without sharing
+any code.
+
+The series follow the paper's evaluation protocol (Experiments, Datasets):
+every series is z-normalised.  The UCR random-walk and ECG recordings used
+by the paper are not available, so the generators below stand in for them:
+
+* random walk: x_t = x_{t-1} + N(0, 1), then z-normalised;
+* ECG-like: Gaussian pulses (sigma = 6 samples) every 200 +- 20 samples with
+  amplitude 1 +- 0.2, a 0.3 * sin baseline wander of period 2000 samples,
+  N(0, 0.05^2) noise, then z-normalised.
+
+Z-normalisation is done in float64 with the population standard deviation
+and the result is stored as float32.  A constant series becomes all zeros.
+
+Random numbers that the method itself draws are produced here and passed
+to both implementations as inputs:
+
+* the sketch filter r ~ N(0, 1)^W (Section 4.1), float32;
+* for weighted MinHash by Ioffe's improved consistent weighted sampling
+  (Section 4.3, cited work), one triple per (code, hash):
+  r ~ Gamma(2, 1), ln c with c ~ Gamma(2, 1), and beta ~ U[0, 1),
+  each a float64 array of shape [2**n, H] (code-major).
+
+Every stream comes from numpy's PCG64 seeded through SeedSequence, with a
+separate child stream per purpose so that changing one size never changes
+another stream.
+"""
+from __future__ import annotations
+
+import concurrent.futures as _fut
+import os
+
+import numpy as np
+
+# child-stream indices of SeedSequence(seed).spawn(...)
+_DATA, _FILTER, _CWS, _QUERY, _ARRIVAL, _LENGTHS = range(6)
+_N_CHILDREN = 8
+# series are drawn in blocks of this many, each block from its own stream,
+# so a sample of the first B series is identical whatever the total N is
+SERIES_BLOCK = 4096
+
+
+def _child(seed: int, which: int) -> np.random.SeedSequence:
+    return np.random.SeedSequence(seed).spawn(_N_CHILDREN)[which]
+
+
+def _rng(seed: int, which: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(_child(seed, which)))
+
+
+def znorm(a: np.ndarray) -> np.ndarray:
+    """Z-normalise the rows of ``a`` in float64 (population sigma)."""
+    a = np.asarray(a, dtype=np.float64)
+    mu = a.mean(axis=-1, keepdims=True)
+    sd = a.std(axis=-1, keepdims=True)
+    out = np.zeros_like(a)
+    np.divide(a - mu, sd, out=out, where=sd > 0)
+    return out
+
+
+def _rw_block(ss: np.random.SeedSequence, rows: int, m: int) -> np.ndarray:
+    g = np.random.Generator(np.random.PCG64(ss))
+    steps = g.standard_normal((rows, m))
+    return znorm(np.cumsum(steps, axis=1)).astype(np.float32)
+
+
+def _ecg_block(ss: np.random.SeedSequence, rows: int, m: int) -> np.ndarray:
+    g = np.random.Generator(np.random.PCG64(ss))
+    t = np.arange(m, dtype=np.float64)
+    out = np.empty((rows, m), dtype=np.float32)
+    npulse = m // 180 + 3
+    for i in range(rows):
+        tau0 = g.uniform(0.0, 200.0)
+        gaps = g.uniform(180.0, 220.0, size=npulse)
+        taus = tau0 + np.concatenate(([0.0], np.cumsum(gaps[:-1])))
+        amps = g.uniform(0.8, 1.2, size=npulse)
+        phi = g.uniform(0.0, 2.0 * np.pi)
+        sig = np.zeros(m)
+        for tau, a in zip(taus, amps):
+            lo, hi = int(max(0, tau - 40)), int(min(m, tau + 41))
+            if lo < hi:
+                tt = t[lo:hi]
+                sig[lo:hi] += a * np.exp(-((tt - tau) ** 2) / (2.0 * 36.0))
+        sig += 0.3 * np.sin(2.0 * np.pi * t / 2000.0 + phi)
+        sig += g.normal(0.0, 0.05, size=m)
+        out[i] = znorm(sig[None, :])[0].astype(np.float32)
+    return out
+
+
+def _blocks(seed: int, N: int, m: int, fn, threads: int | None) -> np.ndarray:
+    nblk = (N + SERIES_BLOCK - 1) // SERIES_BLOCK
+    kids = _child(seed, _DATA).spawn(nblk)
+    out = np.empty((N, m), dtype=np.float32)
+
+    def work(b):
+        lo = b * SERIES_BLOCK
+        hi = min(N, lo + SERIES_BLOCK)
+        out[lo:hi] = fn(kids[b], hi - lo, m)
+
+    threads = threads or min(16, os.cpu_count() or 1)
+    if nblk == 1 or threads == 1:
+        for b in range(nblk):
+            work(b)
+    else:
+        with _fut.ThreadPoolExecutor(threads) as ex:
+            list(ex.map(work, range(nblk)))
+    return out
+
+
+def random_walks(N: int, m: int, seed: int = 0, threads: int | None = None) -> np.ndarray:
+    """[N, m] float32 z-normalised random walks."""
+    return _blocks(seed, N, m, _rw_block, threads)
+
+
+def ecg_like(N: int, m: int, seed: int = 0, threads: int | None = None) -> np.ndarray:
+    """[N, m] float32 z-normalised ECG-like series."""
+    return _blocks(seed, N, m, _ecg_block, threads)
+
+
+def ragged_series(N: int, m_lo: int, m_hi: int, seed: int = 0):
+    """Series of lengths uniform in [m_lo, m_hi]; even ids random walk, odd ECG-like.
+
+    Returns (x: float32[sum m], x_off: int64[N + 1]).
+    """
+    g = _rng(seed, _LENGTHS)
+    lens = g.integers(m_lo, m_hi + 1, size=N).astype(np.int64)
+    off = np.zeros(N + 1, dtype=np.int64)
+    np.cumsum(lens, out=off[1:])
+    x = np.empty(int(off[-1]), dtype=np.float32)
+    kids = _child(seed, _DATA).spawn(N)
+    for i in range(N):
+        fn = _rw_block if i % 2 == 0 else _ecg_block
+        x[off[i]:off[i + 1]] = fn(kids[i], 1, int(lens[i]))[0]
+    return x, off
+
+
+def csr(series: np.ndarray):
+    """[N, m] array -> (flat float32 values, int64 offsets [N + 1])."""
+    series = np.ascontiguousarray(series, dtype=np.float32)
+    N, m = series.shape
+    return series.reshape(-1), np.arange(N + 1, dtype=np.int64) * m
+
+
+def perturbed_queries(db: np.ndarray, nq: int, noise_std: float = 0.1, seed: int = 0):
+    """Queries znorm(db[src] + N(0, noise_std^2)); returns (queries [nq, m] f32, src ids)."""
+    g = _rng(seed, _QUERY)
+    src = g.permutation(db.shape[0])[:nq].astype(np.int64)
+    noisy = db[src].astype(np.float64) + g.normal(0.0, noise_std, size=(nq, db.shape[1]))
+    return znorm(noisy).astype(np.float32), src
+
+
+def filter_r(W: int, seed: int = 0) -> np.ndarray:
+    """The sketch filter r ~ N(0, 1)^W as float32 (Section 4.1)."""
+    return _rng(seed, _FILTER).standard_normal(W).astype(np.float32)
+
+
+def cws_draws(n: int, H: int, seed: int = 0):
+    """ICWS random numbers for every (code, hash): r, ln c, beta; each float64 [2**n, H].
+
+    r and c are Gamma(2, 1) variates, drawn as -ln(u1 u2) from two uniforms;
+    beta is uniform on [0, 1).  The log of c is what the sampler consumes,
+    so it is drawn directly in that form.
+    """
+    g = _rng(seed, _CWS)
+    D = 1 << n
+    r = g.gamma(2.0, 1.0, size=(D, H))
+    c = g.gamma(2.0, 1.0, size=(D, H))
+    beta = g.random(size=(D, H))
+    # Gamma(2, 1) is positive with probability one; guard the measure-zero case
+    r = np.maximum(r, np.finfo(np.float64).tiny)
+    c = np.maximum(c, np.finfo(np.float64).tiny)
+    return r, np.log(c), beta
+
+
+def poisson_arrivals(rate: float, count: int, seed: int = 0) -> np.ndarray:
+    """Arrival times (s) of a Poisson stream with exponential gaps."""
+    g = _rng(seed, _ARRIVAL)
+    return np.cumsum(g.exponential(1.0 / rate, size=count))
