@@ -58,6 +58,8 @@ def sketch_series(x, r, W: int, delta: int) -> np.ndarray:
     r = np.asarray(r, dtype=np.float32).astype(np.float64)
     assert r.shape[0] == W
     nb = num_bits(x.shape[0], W, delta)
+    if nb == 0:
+        return np.zeros(0, dtype=np.uint8)
     s = np.zeros(nb, dtype=np.float64)
     for k in range(W):
         s = s + r[k] * x[k: k + delta * (nb - 1) + 1: delta]
@@ -69,6 +71,8 @@ def sketch_batch(X, r, W: int, delta: int) -> np.ndarray:
     X = np.asarray(X, dtype=np.float32).astype(np.float64)
     r = np.asarray(r, dtype=np.float32).astype(np.float64)
     nb = num_bits(X.shape[1], W, delta)
+    if nb == 0:
+        return np.zeros((X.shape[0], 0), dtype=np.uint8)
     s = np.zeros((X.shape[0], nb), dtype=np.float64)
     for k in range(W):
         s = s + r[k] * X[:, k: k + delta * (nb - 1) + 1: delta]

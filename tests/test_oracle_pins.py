@@ -42,7 +42,8 @@ def _exact_bits(x, r, W, delta):
 
 
 @pytest.mark.parametrize("m,W,delta", [(4, 2, 2), (9, 3, 1), (17, 5, 3), (40, 8, 4),
-                                       (33, 33, 2), (12, 13, 1), (64, 7, 5)])
+                                       (33, 33, 2), (12, 13, 1), (64, 7, 5), (3, 16, 4),
+                                       (0, 5, 3), (15, 16, 7)])
 def test_sketch_brute_force_exact_sign(m, W, delta):
     rng = np.random.default_rng(m * 131 + W * 7 + delta)
     for _ in range(5):
