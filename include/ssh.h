@@ -1,0 +1,245 @@
+/*
+ * ssh.h -- C ABI of the SSH (Sketch, Shingle & Hash) hot path on MI355X (gfx950).
+ *
+ * Luo & Shrivastava, "SSH (Sketch, Shingle, & Hash) for Indexing Massive-Scale
+ * Time Series", arXiv 1610.07328.  The library computes, for a batch of time
+ * series held in device memory:
+ *
+ *   ssh_sketch     sign stream B_X of a sliding random filter   (Section 4.1)
+ *   ssh_shingle    weighted set S_X of length-n bit shingles     (Section 4.2)
+ *   ssh_cws        weighted MinHash values by consistent weighted sampling
+ *                  (Section 4.3; Section 2, eqs. WJaccardDef / CollProb)
+ *   ssh_band_keys  one key per hash table from K hash values     (Algorithm 1)
+ *   ssh_table_build  the L hash tables                           (Algorithm 1)
+ *   ssh_probe      retrieved set R of each query, ranked         (Algorithm 2)
+ *   dtw_rerank     top-k of R by banded DTW distance             (Section 2.1,
+ *                  last step of Algorithm 2)
+ *
+ * Conventions shared by every entry point:
+ *   - Pointers are DEVICE pointers unless marked [host].  The caller owns every
+ *     buffer; the library never allocates device memory.  Buffers that hold
+ *     per-series data are indexed by series id 0..N-1.
+ *   - `stream` is a hipStream_t (NULL for the null stream).  Work is enqueued
+ *     asynchronously on it; nothing is synchronised.  Errors raised by a kernel
+ *     after launch surface at the caller's next synchronisation.
+ *   - Validation is synchronous: on a bad argument the call returns SSH_EINVAL
+ *     (or SSH_EUNSUPPORTED for a shape outside the implemented range) and
+ *     enqueues nothing.  A failed launch returns SSH_EDEVICE.  The reason is
+ *     available from ssh_last_error() on the calling thread.  Outputs are
+ *     undefined after an error.
+ *   - Ragged batches use CSR offsets: series s occupies [off[s], off[s+1]) of
+ *     its value array, off has N + 1 entries, off[0] = 0, non-decreasing.
+ *   - Edge cases are not errors: a series shorter than the filter has no bits,
+ *     a stream shorter than n has no shingles, and a series without shingles
+ *     gets SSH_HV_EMPTY hash values and SSH_KEY_EMPTY keys (it never matches a
+ *     query).
+ */
+#ifndef SSH_H_
+#define SSH_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t ssh_status;
+#define SSH_OK 0
+#define SSH_EINVAL (-1)
+#define SSH_EUNSUPPORTED (-2)
+#define SSH_EDEVICE (-3)
+#define SSH_ECAPACITY (-4)
+
+#define SSH_HV_EMPTY UINT64_MAX  /* hash value of a series without shingles */
+#define SSH_KEY_EMPTY UINT64_MAX /* band key of a series without shingles   */
+#define SSH_MAX_W 256            /* longest supported filter                */
+#define SSH_MAX_N 16             /* longest supported shingle               */
+#define SSH_LNS_ENTRIES 65536    /* entries of the prepared ln-count table  */
+#define SSH_MAX_C 4096           /* largest candidate cap of ssh_probe      */
+#define SSH_MAX_K 1024           /* largest k of dtw_rerank                 */
+#define SSH_MAX_BAND 255         /* largest Sakoe-Chiba radius of dtw_rerank */
+
+/* [host] Name of a status code, and the detail of the last error raised on the
+ * calling thread ("" if none).  Both strings are owned by the library. */
+const char* ssh_status_str(ssh_status s);
+const char* ssh_last_error(void);
+
+/* [host] Size helpers.
+ * ssh_num_bits: length N_B of the sign stream of a series of length m, i.e. the
+ *   number of window starts i*delta with i*delta + W <= m: (m - W)/delta + 1,
+ *   or 0 when m < W (Section 4.1; the paper's N_B = (m-W)/delta is read with
+ *   the +1 its worked example needs).
+ * ssh_num_shingles: number of length-n shingles of a stream of nbits bits:
+ *   nbits - n + 1, or 0 when nbits < n (Section 4.2). */
+int32_t ssh_num_bits(int64_t m, int32_t W, int32_t delta);
+int32_t ssh_num_shingles(int32_t nbits, int32_t n);
+
+/* [host] Layout plan of a ragged batch.  From the series offsets x_off[N+1]
+ * (host copy) it fills, all [host]:
+ *   bit_word_off[N+1]  offsets (in uint64 words) of each series' packed sign
+ *                      stream: ceil(N_B / 64) words per series;
+ *   hist_off[N+1]      offsets of each series' weighted-set slots: capacity
+ *                      ssh_num_shingles(N_B, n) per series;
+ *   max_nbits          largest N_B in the batch (may be NULL).
+ * Returns SSH_EINVAL on bad sizes or decreasing offsets. */
+ssh_status ssh_plan(const int64_t* x_off, int64_t N, int32_t W, int32_t delta, int32_t n,
+                    int64_t* bit_word_off, int64_t* hist_off, int32_t* max_nbits);
+
+/* Sliding-window sign sketch (Section 4.1, definition of B_X and its worked
+ * example).  For series s with values x[x_off[s] .. x_off[s+1]) and window i in
+ * [0, N_B), bit i is 1 when r . x[i*delta .. i*delta + W) >= 0 and 0 otherwise
+ * (+1 / -1 of the paper).  The sign is that of the float64 sum of the exact
+ * float32 products taken in ascending filter index; windows whose fast
+ * half-precision dot product is within a proven error margin of zero are
+ * recomputed that way, so the bits are exact whatever the input.
+ *   x            float32 values (finite; non-finite windows take the float64
+ *                path, whose comparison with NaN yields 0)
+ *   x_off        int64 [N+1] series offsets
+ *   r            [host] float32 [W] filter, 1 <= W <= SSH_MAX_W, finite
+ *   delta        step, >= 1
+ *   bits         uint64 packed streams: bit i of series s is bit (i & 63) of
+ *                word bit_word_off[s] + (i >> 6); unused high bits are 0
+ *   bit_word_off int64 [N+1] from ssh_plan (same x_off, W, delta)
+ *   nbits        int32 [N] output: N_B of each series
+ *   repair_count uint64 [1] or NULL: incremented by the number of windows
+ *                recomputed in float64 */
+ssh_status ssh_sketch(const float* x, const int64_t* x_off, int64_t N, const float* r, int32_t W,
+                      int32_t delta, uint64_t* bits, const int64_t* bit_word_off, int32_t* nbits,
+                      uint64_t* repair_count, void* stream);
+
+/* Weighted set of length-n shingles (Section 4.2, eq. "set").  Every one of the
+ * N_B - n + 1 length-n substrings of a series' stream is a token with weight =
+ * its number of occurrences.  A token is the integer whose binary digits, most
+ * significant first, are the n bits in stream order.
+ *   bits, bit_word_off, nbits   as produced by ssh_sketch
+ *   n            1..SSH_MAX_N
+ *   codes        uint32 output: series s writes its distinct tokens in
+ *                ascending order to codes[hist_off[s] .. + n_distinct[s])
+ *   counts       uint32 output, parallel to codes (>= 1)
+ *   hist_off     int64 [N+1] from ssh_plan (capacity N_B - n + 1 per series)
+ *   n_distinct   int32 [N] output */
+ssh_status ssh_shingle(const uint64_t* bits, const int64_t* bit_word_off, const int32_t* nbits,
+                       int64_t N, int32_t n, uint32_t* codes, uint32_t* counts,
+                       const int64_t* hist_off, int32_t* n_distinct, void* stream);
+
+/* Random numbers of consistent weighted sampling, one triple per (token k,
+ * hash j), code-major: element [k * H + j] of each array.  They are inputs,
+ * drawn by the caller: r ~ Gamma(2,1) (> 0), lnc = ln c with c ~ Gamma(2,1),
+ * beta ~ U[0,1).  a1 and lnS are scratch tables the caller allocates
+ * (a1: 2^n * H doubles, lnS: SSH_LNS_ENTRIES doubles) and fills once with
+ * ssh_cws_prepare. */
+typedef struct {
+  int32_t n;          /* token length; tables have 2^n rows */
+  int32_t H;          /* hashes per series, >= 1 */
+  const double* r;    /* [2^n * H] */
+  const double* lnc;  /* [2^n * H] */
+  const double* beta; /* [2^n * H] */
+  double* a1;         /* [2^n * H] prepared: ln a of a token of weight 1 */
+  double* lnS;        /* [SSH_LNS_ENTRIES] prepared: correctly rounded ln s */
+} ssh_cws_tables;
+
+/* Fill tab->a1 and tab->lnS from the draws (device work on `stream`).
+ * tab is a [host] struct of device pointers. */
+ssh_status ssh_cws_prepare(const ssh_cws_tables* tab, void* stream);
+
+/* Weighted MinHash of every weighted set (Section 4.3), by Ioffe's improved
+ * consistent weighted sampling.  For hash j and every token k of weight S_k:
+ *     t = floor(ln S_k / r + beta),  ln y = r (t - beta),  ln a = ln c - ln y - r
+ * each step one correctly rounded float64 operation in this order, ln S_k
+ * correctly rounded.  The sample is k* = argmin_k ln a (ties to the smaller k)
+ * with its t*, stored as hv = min(t*, 2^48 - 1) << 16 | k*.  The probability
+ * that two sets agree on hv equals their weighted Jaccard similarity
+ * (eq. CollProb).
+ *   codes, counts, hist_off, n_distinct  as produced by ssh_shingle
+ *   tab          [host] struct of device tables, prepared
+ *   hv           uint64 [N * H] output, series-major; SSH_HV_EMPTY for a
+ *                series with no token */
+ssh_status ssh_cws(const uint32_t* codes, const uint32_t* counts, const int64_t* hist_off,
+                   const int32_t* n_distinct, int64_t N, const ssh_cws_tables* tab, uint64_t* hv,
+                   void* stream);
+
+/* Band keys (Algorithm 1, one key per hash table).  Table l is keyed by the K
+ * hash values hv[s*H + l*K .. + K) (H = K*L) folded with the SplitMix64 output
+ * function mix: h = mix(seed + (l+1) * 0x9E3779B97F4A7C15); h = mix(h ^ hv_j)
+ * for each j in order; key = h, moved to SSH_KEY_EMPTY - 1 if it equals
+ * SSH_KEY_EMPTY.  A series with SSH_HV_EMPTY values gets SSH_KEY_EMPTY.
+ *   keys         uint64 [N * L] output, series-major */
+ssh_status ssh_band_keys(const uint64_t* hv, int64_t N, int32_t K, int32_t L, uint64_t seed,
+                         uint64_t* keys, void* stream);
+
+/* [host] Workspace bytes needed by ssh_table_build for N series and L tables. */
+size_t ssh_table_workspace_bytes(int64_t N, int32_t L);
+
+/* Hash tables (Algorithm 1).  Table l lists every (key, id) pair of the batch
+ * ordered by the high 32 bits of the key, ids ascending among equal high
+ * halves (a stable sort of ids 0..N-1).  A bucket is the set of ids with one
+ * full key.
+ *   keys         uint64 [N * L] from ssh_band_keys; N <= 2^32 - 1
+ *   tab_keys     uint64 [L * N] output, table-major
+ *   tab_ids      uint32 [L * N] output, table-major
+ *   ws, ws_bytes device workspace, at least ssh_table_workspace_bytes(N, L) */
+ssh_status ssh_table_build(const uint64_t* keys, int64_t N, int32_t L, uint64_t* tab_keys,
+                           uint32_t* tab_ids, void* ws, size_t ws_bytes, void* stream);
+
+/* Probe (Algorithm 2).  For query q the retrieved set R is the union over
+ * tables l of the bucket with key q_keys[q*L + l].  Members of R are ranked by
+ * the number of the H hash values they share with the query (ties to the
+ * smaller id) and the first min(|R|, C) are returned.  A query without
+ * shingles retrieves nothing.
+ *   tab_keys, tab_ids  from ssh_table_build over db_keys
+ *   db_keys      uint64 [N * L], db_hv uint64 [N * H]: the indexed series
+ *   q_keys       uint64 [nq * L], q_hv uint64 [nq * H]: the queries
+ *   C            1..SSH_MAX_C
+ *   cand         int64 [nq * C] output: ranked ids, -1 after ncand[q]
+ *   ncand        int32 [nq] output: min(|R|, C)
+ *   r_size       int64 [nq] output: |R| */
+ssh_status ssh_probe(const uint64_t* tab_keys, const uint32_t* tab_ids, int64_t N, int32_t L,
+                     const uint64_t* db_keys, const uint64_t* db_hv, int32_t H,
+                     const uint64_t* q_keys, const uint64_t* q_hv, int32_t nq, int32_t C,
+                     int64_t* cand, int32_t* ncand, int64_t* r_size, void* stream);
+
+/* [host] Workspace bytes needed by dtw_rerank. */
+size_t ssh_rerank_workspace_bytes(int32_t nq, int32_t C);
+
+/* DTW re-rank (Section 2.1; last step of Algorithm 2).  For each query q and
+ * each of its ncand[q] candidates X = cand[q*C + c], the banded DTW distance:
+ * cost (q_i - x_j)^2, steps (1,0), (0,1), (1,1) from (0,0) to (lq-1, lx-1),
+ * Sakoe-Chiba band |i - j| <= floor(band_frac * max(lq, lx)), distance = sqrt
+ * of the least total cost (+inf when |lq - lx| exceeds the band).  Accumulated
+ * in float32.  The k nearest by (distance, id) are returned.
+ *   q, q_off     float32 query values and int64 [nq+1] offsets
+ *   db, db_off   float32 series values and int64 [N+1] offsets; N series
+ *   cand, ncand  from ssh_probe (C columns)
+ *   band_frac    in [0, 1]; the radius must not exceed SSH_MAX_BAND
+ *   q_len, db_len  [host] the common query length and candidate length of the
+ *                batch (every query and every series must have them)
+ *   k            1..SSH_MAX_K, k <= C
+ *   out_id       int64 [nq * k] output, -1 padding
+ *   out_dist     float32 [nq * k] output, +inf padding
+ *   ws, ws_bytes at least ssh_rerank_workspace_bytes(nq, C) */
+ssh_status dtw_rerank(const float* q, const int64_t* q_off, int32_t nq, const float* db,
+                      const int64_t* db_off, int64_t N, const int64_t* cand, const int32_t* ncand,
+                      int32_t C, float band_frac, int64_t q_len, int64_t db_len, int32_t k,
+                      int64_t* out_id, float* out_dist, void* ws, size_t ws_bytes, void* stream);
+
+/* Same contract as ssh_sketch, always through the kernel that handles any W
+ * and delta (ssh_sketch picks a register-blocked kernel for the filter shapes
+ * it specialises).  Both must produce identical bits. */
+ssh_status ssh_sketch_generic(const float* x, const int64_t* x_off, int64_t N, const float* r,
+                              int32_t W, int32_t delta, uint64_t* bits,
+                              const int64_t* bit_word_off, int32_t* nbits, uint64_t* repair_count,
+                              void* stream);
+
+/* [host] Synchronise the device and collect the error flags that kernels raise
+ * for inconsistent device-side arguments since the last call (offsets whose
+ * capacity is too small, candidate ids outside [0, N), lengths that differ from
+ * dtw_rerank's q_len / db_len, CWS draws outside their ranges).  The flags are
+ * cleared.  Returns SSH_OK when none was raised, else SSH_EINVAL with the
+ * detail in ssh_last_error(). */
+ssh_status ssh_check_device_errors(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SSH_H_ */

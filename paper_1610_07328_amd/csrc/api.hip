@@ -1,0 +1,254 @@
+// C ABI of the SSH library: argument validation, size helpers, error strings,
+// and dispatch to the kernels.  Every entry point validates synchronously and
+// enqueues nothing when it rejects its arguments.
+#include <string>
+
+#include "common.hpp"
+
+namespace ssh {
+
+static thread_local std::string t_last_error;
+
+void set_error(const std::string& msg) { t_last_error = msg; }
+
+ssh_status fail(ssh_status code, const std::string& msg) {
+  t_last_error = msg;
+  return code;
+}
+
+ssh_status check_launch(const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(SSH_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+  return SSH_OK;
+}
+
+// kernels (other translation units)
+ssh_status sketch_launch(const float* x, const int64_t* x_off, int64_t N, const float* r, int W,
+                         int delta, uint64_t* bits, const int64_t* bit_word_off, int32_t* nbits,
+                         uint64_t* repair_count, hipStream_t stream, bool force_generic);
+ssh_status shingle_launch(const uint64_t* bits, const int64_t* bit_word_off, const int32_t* nbits,
+                          int64_t N, int n, uint32_t* codes, uint32_t* counts,
+                          const int64_t* hist_off, int32_t* n_distinct, hipStream_t stream);
+ssh_status cws_prepare_launch(const ssh_cws_tables* tab, hipStream_t stream);
+ssh_status cws_launch(const uint32_t* codes, const uint32_t* counts, const int64_t* hist_off,
+                      const int32_t* n_distinct, int64_t N, const ssh_cws_tables* tab, uint64_t* hv,
+                      hipStream_t stream);
+ssh_status band_keys_launch(const uint64_t* hv, int64_t N, int K, int L, uint64_t seed,
+                            uint64_t* keys, hipStream_t stream);
+size_t table_workspace_bytes(int64_t N, int L);
+ssh_status table_build_launch(const uint64_t* keys, int64_t N, int L, uint64_t* tab_keys,
+                              uint32_t* tab_ids, void* ws, size_t ws_bytes, hipStream_t stream);
+ssh_status probe_launch(const uint64_t* tab_keys, const uint32_t* tab_ids, int64_t N, int L,
+                        const uint64_t* db_keys, const uint64_t* db_hv, int H,
+                        const uint64_t* q_keys, const uint64_t* q_hv, int nq, int C, int64_t* cand,
+                        int32_t* ncand, int64_t* r_size, hipStream_t stream);
+size_t rerank_workspace_bytes(int nq, int C);
+ssh_status rerank_launch(const float* q, const int64_t* q_off, int nq, const float* db,
+                         const int64_t* db_off, int64_t Ndb, const int64_t* cand,
+                         const int32_t* ncand, int C, float band_frac, int64_t q_len,
+                         int64_t db_len, int k, int64_t* out_id, float* out_dist, void* ws,
+                         size_t ws_bytes, hipStream_t stream);
+
+int take_sketch_err();
+int take_shingle_err();
+int take_cws_err();
+int take_dtw_err();
+
+}  // namespace ssh
+
+using namespace ssh;
+
+#define SSH_REQUIRE(cond, msg)                 \
+  do {                                         \
+    if (!(cond)) return fail(SSH_EINVAL, msg); \
+  } while (0)
+
+extern "C" {
+
+const char* ssh_status_str(ssh_status s) {
+  switch (s) {
+    case SSH_OK: return "SSH_OK";
+    case SSH_EINVAL: return "SSH_EINVAL";
+    case SSH_EUNSUPPORTED: return "SSH_EUNSUPPORTED";
+    case SSH_EDEVICE: return "SSH_EDEVICE";
+    case SSH_ECAPACITY: return "SSH_ECAPACITY";
+    default: return "SSH_UNKNOWN";
+  }
+}
+
+const char* ssh_last_error(void) { return t_last_error.c_str(); }
+
+int32_t ssh_num_bits(int64_t m, int32_t W, int32_t delta) {
+  if (W < 1 || delta < 1 || m < W) return 0;
+  return (int32_t)((m - W) / delta + 1);
+}
+
+int32_t ssh_num_shingles(int32_t nbits, int32_t n) {
+  if (n < 1 || nbits < n) return 0;
+  return nbits - n + 1;
+}
+
+ssh_status ssh_plan(const int64_t* x_off, int64_t N, int32_t W, int32_t delta, int32_t n,
+                    int64_t* bit_word_off, int64_t* hist_off, int32_t* max_nbits) {
+  SSH_REQUIRE(N >= 0, "ssh_plan: N < 0");
+  SSH_REQUIRE(x_off && bit_word_off && hist_off, "ssh_plan: null pointer");
+  SSH_REQUIRE(W >= 1 && W <= SSH_MAX_W, "ssh_plan: W out of [1, SSH_MAX_W]");
+  SSH_REQUIRE(delta >= 1, "ssh_plan: delta < 1");
+  SSH_REQUIRE(n >= 1 && n <= SSH_MAX_N, "ssh_plan: n out of [1, SSH_MAX_N]");
+  SSH_REQUIRE(x_off[0] == 0, "ssh_plan: x_off[0] != 0");
+  bit_word_off[0] = 0;
+  hist_off[0] = 0;
+  int32_t mx = 0;
+  for (int64_t s = 0; s < N; ++s) {
+    const int64_t m = x_off[s + 1] - x_off[s];
+    SSH_REQUIRE(m >= 0, "ssh_plan: decreasing offsets");
+    SSH_REQUIRE(m <= (int64_t)1 << 31, "ssh_plan: series longer than 2^31");
+    const int32_t nb = ssh_num_bits(m, W, delta);
+    mx = nb > mx ? nb : mx;
+    bit_word_off[s + 1] = bit_word_off[s] + (nb + 63) / 64;
+    hist_off[s + 1] = hist_off[s] + ssh_num_shingles(nb, n);
+  }
+  if (max_nbits) *max_nbits = mx;
+  return SSH_OK;
+}
+
+ssh_status ssh_sketch(const float* x, const int64_t* x_off, int64_t N, const float* r, int32_t W,
+                      int32_t delta, uint64_t* bits, const int64_t* bit_word_off, int32_t* nbits,
+                      uint64_t* repair_count, void* stream) {
+  SSH_REQUIRE(N >= 0 && N <= (int64_t)UINT32_MAX, "ssh_sketch: N out of [0, 2^32)");
+  SSH_REQUIRE(W >= 1 && W <= SSH_MAX_W, "ssh_sketch: W out of [1, SSH_MAX_W]");
+  SSH_REQUIRE(delta >= 1, "ssh_sketch: delta < 1");
+  SSH_REQUIRE(r, "ssh_sketch: null filter");
+  if (N == 0) return SSH_OK;
+  SSH_REQUIRE(x && x_off && bits && bit_word_off && nbits, "ssh_sketch: null pointer");
+  return sketch_launch(x, x_off, N, r, W, delta, bits, bit_word_off, nbits, repair_count,
+                       as_stream(stream), false);
+}
+
+// Same as ssh_sketch but always through the generic kernel (any W, delta);
+// exposed so that tests can compare both paths.
+ssh_status ssh_sketch_generic(const float* x, const int64_t* x_off, int64_t N, const float* r,
+                              int32_t W, int32_t delta, uint64_t* bits,
+                              const int64_t* bit_word_off, int32_t* nbits, uint64_t* repair_count,
+                              void* stream) {
+  SSH_REQUIRE(N >= 0 && N <= (int64_t)UINT32_MAX, "ssh_sketch: N out of [0, 2^32)");
+  SSH_REQUIRE(W >= 1 && W <= SSH_MAX_W, "ssh_sketch: W out of [1, SSH_MAX_W]");
+  SSH_REQUIRE(delta >= 1, "ssh_sketch: delta < 1");
+  SSH_REQUIRE(r, "ssh_sketch: null filter");
+  if (N == 0) return SSH_OK;
+  SSH_REQUIRE(x && x_off && bits && bit_word_off && nbits, "ssh_sketch: null pointer");
+  return sketch_launch(x, x_off, N, r, W, delta, bits, bit_word_off, nbits, repair_count,
+                       as_stream(stream), true);
+}
+
+ssh_status ssh_shingle(const uint64_t* bits, const int64_t* bit_word_off, const int32_t* nbits,
+                       int64_t N, int32_t n, uint32_t* codes, uint32_t* counts,
+                       const int64_t* hist_off, int32_t* n_distinct, void* stream) {
+  SSH_REQUIRE(N >= 0, "ssh_shingle: N < 0");
+  SSH_REQUIRE(n >= 1 && n <= SSH_MAX_N, "ssh_shingle: n out of [1, SSH_MAX_N]");
+  if (N == 0) return SSH_OK;
+  SSH_REQUIRE(bits && bit_word_off && nbits && codes && counts && hist_off && n_distinct,
+              "ssh_shingle: null pointer");
+  return shingle_launch(bits, bit_word_off, nbits, N, n, codes, counts, hist_off, n_distinct,
+                        as_stream(stream));
+}
+
+static ssh_status check_tables(const ssh_cws_tables* tab, const char* who) {
+  if (!tab) return fail(SSH_EINVAL, std::string(who) + ": null tables");
+  if (tab->n < 1 || tab->n > SSH_MAX_N) return fail(SSH_EINVAL, std::string(who) + ": n out of [1, SSH_MAX_N]");
+  if (tab->H < 1) return fail(SSH_EINVAL, std::string(who) + ": H < 1");
+  if (!tab->r || !tab->lnc || !tab->beta || !tab->a1 || !tab->lnS)
+    return fail(SSH_EINVAL, std::string(who) + ": null table pointer");
+  return SSH_OK;
+}
+
+ssh_status ssh_cws_prepare(const ssh_cws_tables* tab, void* stream) {
+  ssh_status st = check_tables(tab, "ssh_cws_prepare");
+  if (st != SSH_OK) return st;
+  return cws_prepare_launch(tab, as_stream(stream));
+}
+
+ssh_status ssh_cws(const uint32_t* codes, const uint32_t* counts, const int64_t* hist_off,
+                   const int32_t* n_distinct, int64_t N, const ssh_cws_tables* tab, uint64_t* hv,
+                   void* stream) {
+  ssh_status st = check_tables(tab, "ssh_cws");
+  if (st != SSH_OK) return st;
+  SSH_REQUIRE(N >= 0, "ssh_cws: N < 0");
+  if (N == 0) return SSH_OK;
+  SSH_REQUIRE(codes && counts && hist_off && n_distinct && hv, "ssh_cws: null pointer");
+  return cws_launch(codes, counts, hist_off, n_distinct, N, tab, hv, as_stream(stream));
+}
+
+ssh_status ssh_band_keys(const uint64_t* hv, int64_t N, int32_t K, int32_t L, uint64_t seed,
+                         uint64_t* keys, void* stream) {
+  SSH_REQUIRE(N >= 0, "ssh_band_keys: N < 0");
+  SSH_REQUIRE(K >= 1 && L >= 1, "ssh_band_keys: K or L < 1");
+  if (N == 0) return SSH_OK;
+  SSH_REQUIRE(hv && keys, "ssh_band_keys: null pointer");
+  return band_keys_launch(hv, N, K, L, seed, keys, as_stream(stream));
+}
+
+size_t ssh_table_workspace_bytes(int64_t N, int32_t L) {
+  if (N < 0 || L < 1) return 0;
+  return table_workspace_bytes(N, L);
+}
+
+ssh_status ssh_table_build(const uint64_t* keys, int64_t N, int32_t L, uint64_t* tab_keys,
+                           uint32_t* tab_ids, void* ws, size_t ws_bytes, void* stream) {
+  SSH_REQUIRE(N >= 0 && N <= (int64_t)UINT32_MAX - 1, "ssh_table_build: N out of [0, 2^32 - 1)");
+  SSH_REQUIRE(L >= 1 && L <= 65535, "ssh_table_build: L out of range");
+  if (N == 0) return SSH_OK;
+  SSH_REQUIRE(keys && tab_keys && tab_ids && ws, "ssh_table_build: null pointer");
+  return table_build_launch(keys, N, L, tab_keys, tab_ids, ws, ws_bytes, as_stream(stream));
+}
+
+ssh_status ssh_probe(const uint64_t* tab_keys, const uint32_t* tab_ids, int64_t N, int32_t L,
+                     const uint64_t* db_keys, const uint64_t* db_hv, int32_t H,
+                     const uint64_t* q_keys, const uint64_t* q_hv, int32_t nq, int32_t C,
+                     int64_t* cand, int32_t* ncand, int64_t* r_size, void* stream) {
+  SSH_REQUIRE(N >= 0 && N <= (int64_t)UINT32_MAX - 1, "ssh_probe: N out of range");
+  SSH_REQUIRE(L >= 1 && H >= 1 && nq >= 0, "ssh_probe: L, H or nq out of range");
+  SSH_REQUIRE(C >= 1 && C <= SSH_MAX_C, "ssh_probe: C out of [1, SSH_MAX_C]");
+  if (nq == 0) return SSH_OK;
+  SSH_REQUIRE(q_keys && q_hv && cand && ncand && r_size, "ssh_probe: null pointer");
+  SSH_REQUIRE(N == 0 || (tab_keys && tab_ids && db_keys && db_hv), "ssh_probe: null table pointer");
+  return probe_launch(tab_keys, tab_ids, N, L, db_keys, db_hv, H, q_keys, q_hv, nq, C, cand, ncand,
+                      r_size, as_stream(stream));
+}
+
+size_t ssh_rerank_workspace_bytes(int32_t nq, int32_t C) {
+  if (nq < 0 || C < 1) return 0;
+  return rerank_workspace_bytes(nq, C);
+}
+
+ssh_status dtw_rerank(const float* q, const int64_t* q_off, int32_t nq, const float* db,
+                      const int64_t* db_off, int64_t N, const int64_t* cand, const int32_t* ncand,
+                      int32_t C, float band_frac, int64_t q_len, int64_t db_len, int32_t k,
+                      int64_t* out_id, float* out_dist, void* ws, size_t ws_bytes, void* stream) {
+  SSH_REQUIRE(nq >= 0 && N >= 0, "dtw_rerank: nq or N < 0");
+  SSH_REQUIRE(C >= 1 && C <= SSH_MAX_C, "dtw_rerank: C out of [1, SSH_MAX_C]");
+  SSH_REQUIRE(k >= 1 && k <= SSH_MAX_K && k <= C, "dtw_rerank: k out of [1, min(C, SSH_MAX_K)]");
+  SSH_REQUIRE(band_frac >= 0.0f && band_frac <= 1.0f, "dtw_rerank: band_frac out of [0, 1]");
+  SSH_REQUIRE(q_len >= 1 && q_len <= (1 << 30) && db_len >= 1 && db_len <= (1 << 30),
+              "dtw_rerank: lengths out of range");
+  if (nq == 0) return SSH_OK;
+  SSH_REQUIRE(q && q_off && cand && ncand && out_id && out_dist && ws, "dtw_rerank: null pointer");
+  SSH_REQUIRE(N == 0 || (db && db_off), "dtw_rerank: null series pointer");
+  return rerank_launch(q, q_off, nq, db, db_off, N, cand, ncand, C, band_frac, q_len, db_len, k,
+                       out_id, out_dist, ws, ws_bytes, as_stream(stream));
+}
+
+ssh_status ssh_check_device_errors(void) {
+  if (hipDeviceSynchronize() != hipSuccess) return fail(SSH_EDEVICE, "device synchronisation failed");
+  const int a = take_sketch_err(), b = take_shingle_err(), c = take_cws_err(), d = take_dtw_err();
+  if (a < 0 || b < 0 || c < 0 || d < 0) return fail(SSH_EDEVICE, "cannot read device error flags");
+  std::string msg;
+  if (a) msg += "ssh_sketch: bit_word_off capacity below ceil(N_B/64); ";
+  if (b) msg += "ssh_shingle: hist_off or bit_word_off capacity too small; ";
+  if (c) msg += "ssh_cws_prepare: a draw is outside its range (r > 0, beta in [0,1), finite ln c); ";
+  if (d) msg += "dtw_rerank: candidate id outside [0, N) or a length differs from q_len/db_len; ";
+  if (!msg.empty()) return fail(SSH_EINVAL, msg);
+  return SSH_OK;
+}
+
+}  // extern "C"

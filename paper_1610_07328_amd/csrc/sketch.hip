@@ -1,0 +1,387 @@
+// Sliding-window sign sketch (Section 4.1 of Luo & Shrivastava, arXiv 1610.07328).
+//
+// bit i of a series = [ r . x[i*delta .. i*delta + W) >= 0 ].
+//
+// Fast path: one wavefront per series chunk; each lane owns R consecutive
+// windows and keeps the union of their samples in registers as packed fp16
+// pairs, so every loaded sample feeds several windows.  Products are fp16 x
+// fp16 (exact in fp32) accumulated in fp32 by v_dot2_f32_f16.
+//
+// Exactness: the reference bit is the sign of the float64 sum of the exact
+// float32 products in ascending filter index.  The fast-path sum s16 differs
+// from that float64 sum by at most
+//     c1 ||r|| ||w|| + c2 sqrt(W) (||r|| + ||w||)
+// (fp16 rounding of both operands, fp32 accumulation with up to W + 2
+// roundings counted at 2^-23 each, fp16 underflow/flush at 2^-14 absolute,
+// and the float64 sum's own rounding).  ||w|| is bounded from above by the
+// norm of the lane's whole sample span, computed from the same fp16 values
+// with the conversion and accumulation slack added.  A window with
+// |s16| >= margin keeps the sign of s16; every other window (and every window
+// of a chunk holding a sample with |x| >= 2^14 or a non-finite one) is queued
+// and recomputed exactly like the reference, one window per lane, in float64.
+// Queued windows are drained in rounds of 64 so a round keeps the whole wave
+// busy; a repaired 1 is OR-ed into the stored stream (the fast path stores 0
+// for every queued window).
+#include <cmath>
+#include <cstring>
+
+#include "common.hpp"
+
+namespace ssh {
+
+typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+
+struct FilterArgs {
+  float r[SSH_MAX_W];                // float32 filter, float64 repair path
+  uint32_t even[SSH_MAX_W / 2 + 2];  // fp16 pairs (r[2p], r[2p+1]), r[W] = 0
+  uint32_t odd[SSH_MAX_W / 2 + 2];   // fp16 pairs (r[2p-1], r[2p]), r[-1] = r[W] = 0
+  float c1;                          // relative margin factor
+  float c2;                          // underflow margin factor
+  float rnorm;                       // ||r||_2, rounded up
+  float sqrtW;                       // sqrt(W), rounded up
+  int32_t W;
+  int32_t delta;
+};
+
+struct RepairQueue {
+  uint32_t* series;
+  uint32_t* window;
+  int* count;
+};
+
+__device__ __forceinline__ h2 as_h2(uint32_t u) { return __builtin_bit_cast(h2, u); }
+
+__device__ __forceinline__ h2 pack_h2(float a, float b) {
+  h2 v;
+  v.x = (_Float16)a;
+  v.y = (_Float16)b;
+  return v;
+}
+
+__device__ __forceinline__ float fdot2(h2 a, h2 b, float c) {
+  return __builtin_amdgcn_fdot2(a, b, c, false);
+}
+
+// Upper bound of the float64-vs-fast-path error for a window whose samples lie
+// in a span with fp16 sum of squares E (fp32-accumulated).
+__device__ __forceinline__ float window_margin(const FilterArgs& fa, float E, int span) {
+  const float slack = 1.0f + 0x1p-20f;
+  float wn = __builtin_sqrtf(E * (1.0f + 0x1p-9f) + (float)span * 0x1p-28f) * slack;
+  float m = fa.c1 * fa.rnorm * wn + fa.c2 * fa.sqrtW * (fa.rnorm + wn);
+  return m * slack;
+}
+
+// Stage samples [sbeg, sbeg + cap) of one series into LDS (zero past the end).
+// Returns true on every lane when some staged sample is non-finite or has
+// magnitude >= 2^14 (fp16 products could then overflow or lose the bound).
+__device__ __forceinline__ bool stage_chunk(float* X, int cap, const float* __restrict__ x,
+                                            int64_t base, int64_t m, int64_t sbeg) {
+  bool bad = false;
+  for (int e = lane_id(); e < cap; e += kWave) {
+    int64_t g = sbeg + e;
+    float v = g < m ? x[base + g] : 0.0f;
+    bad |= !(__builtin_fabsf(v) < 16384.0f);
+    X[e] = v;
+  }
+  return ballot64(bad) != 0;
+}
+
+// One repair round: up to 64 queued windows, one per lane, recomputed as the
+// float64 sum of exact products in ascending filter index.
+__device__ __forceinline__ void repair_round(const FilterArgs& fa, const float* __restrict__ x,
+                             const int64_t* __restrict__ x_off, uint32_t* bits32,
+                             const int64_t* __restrict__ bit_word_off, RepairQueue q,
+                             unsigned long long* repair_count) {
+  const int lane = lane_id();
+  int n = *q.count;
+  int cnt = n < kWave ? n : kWave;
+  int start = n - cnt;
+  // earlier stores of stream words must reach L2 before the ORs below
+  __threadfence();
+  if (lane < cnt) {
+    uint32_t s = q.series[start + lane];
+    uint32_t wi = q.window[start + lane];
+    const float* xw = x + x_off[s] + (int64_t)wi * fa.delta;
+    double acc = 0.0;
+    for (int k = 0; k < fa.W; ++k) acc = __builtin_fma((double)fa.r[k], (double)xw[k], acc);
+    if (acc >= 0.0) {
+      int64_t word = bit_word_off[s] + (wi >> 6);
+      atomicOr(bits32 + 2 * word + ((wi >> 5) & 1), 1u << (wi & 31));
+    }
+  }
+  if (lane == 0) {
+    *q.count = start;
+    if (repair_count) atomicAdd(repair_count, (unsigned long long)cnt);
+  }
+  wave_sync_lds();
+}
+
+template <int R>
+__device__ __forceinline__ void push_flags(RepairQueue q, uint32_t flags, uint32_t s,
+                                           uint32_t first_window) {
+#pragma unroll
+  for (int rho = 0; rho < R; ++rho) {
+    if (flags & (1u << rho)) {
+      int slot = atomicAdd(q.count, 1);
+      q.series[slot] = s;
+      q.window[slot] = first_window + rho;
+    }
+  }
+}
+
+// lane's R bits at chunk-relative window position wl into the LDS words bw
+template <int R>
+__device__ __forceinline__ void or_bits(uint32_t* bw, int wl, uint32_t b) {
+  if (!b) return;
+  int word = wl >> 5, sh = wl & 31;
+  atomicOr(bw + word, b << sh);
+  if (sh + R > 32) atomicOr(bw + word + 1, b >> (32 - sh));
+}
+
+constexpr int kWavesPerBlock = 4;
+
+// ---------------------------------------------------------------------------
+// fast path: compile-time W, delta and R windows per lane
+// ---------------------------------------------------------------------------
+template <int W, int D, int R>
+__global__ __launch_bounds__(256) void sketch_fast_kernel(
+    const float* __restrict__ x, const int64_t* __restrict__ x_off, int64_t N, FilterArgs fa,
+    uint64_t* __restrict__ bits, const int64_t* __restrict__ bit_word_off,
+    int32_t* __restrict__ nbits_out, unsigned long long* repair_count, int* err) {
+  constexpr int SUB = kWave * R;          // windows per chunk
+  constexpr int XCAP = (SUB - 1) * D + W; // samples a chunk touches
+  constexpr int SPAN = D * (R - 1) + W;   // samples of one lane's R windows
+  constexpr int NP = (SPAN + 1) / 2;      // fp16 pairs a lane holds
+  constexpr int PE = (W + 1) / 2;         // pairs of an even-aligned window
+  constexpr int PO = W / 2 + 1;           // pairs of an odd-aligned window
+  constexpr int QCAP = SUB + kWave;
+  static_assert(R <= 32, "R bits per lane must fit a word");
+
+  __shared__ float xs[kWavesPerBlock][XCAP + 4];
+  __shared__ uint32_t qser[kWavesPerBlock][QCAP];
+  __shared__ uint32_t qwin[kWavesPerBlock][QCAP];
+  __shared__ uint32_t bw[kWavesPerBlock][2 * R];
+  __shared__ int qn[kWavesPerBlock];
+
+  const int w = threadIdx.x / kWave;
+  const int lane = lane_id();
+  float* X = xs[w];
+  RepairQueue q{qser[w], qwin[w], &qn[w]};
+  uint32_t* bits32 = reinterpret_cast<uint32_t*>(bits);
+  if (lane == 0) qn[w] = 0;
+  wave_sync_lds();
+
+  for (int64_t s = (int64_t)blockIdx.x * kWavesPerBlock + w; s < N;
+       s += (int64_t)gridDim.x * kWavesPerBlock) {
+    const int64_t base = x_off[s];
+    const int64_t m = x_off[s + 1] - base;
+    int nb = m >= W ? (int)((m - W) / D + 1) : 0;
+    const int64_t wo = bit_word_off[s];
+    if (bit_word_off[s + 1] - wo < (nb + 63) / 64) {
+      if (lane == 0) atomicOr(err, 1);
+      nb = 0;
+    }
+    if (lane == 0) nbits_out[s] = nb;
+    const int nwords = (nb + 63) / 64;
+
+    for (int c = 0; c * SUB < nb; ++c) {
+      const bool unsafe = stage_chunk(X, XCAP + 1, x, base, m, (int64_t)c * SUB * D);
+      if (lane < 2 * R) bw[w][lane] = 0;
+      wave_sync_lds();
+
+      const int wl = lane * R;
+      const int nvalid = nb - c * SUB - wl;
+      if (nvalid > 0) {
+        const float* P = X + wl * D;
+        h2 pr[NP];
+#pragma unroll
+        for (int p = 0; p < NP; ++p) pr[p] = pack_h2(P[2 * p], P[2 * p + 1]);
+        float E = 0.0f;
+#pragma unroll
+        for (int p = 0; p < NP; ++p) E = fdot2(pr[p], pr[p], E);
+        const float M = window_margin(fa, E, 2 * NP);
+        uint32_t mybits = 0, myflags = 0;
+#pragma unroll
+        for (int rho = 0; rho < R; ++rho) {
+          float acc = 0.0f;
+          if (((D * rho) & 1) == 0) {
+#pragma unroll
+            for (int p = 0; p < PE; ++p) acc = fdot2(pr[(D * rho) / 2 + p], as_h2(fa.even[p]), acc);
+          } else {
+#pragma unroll
+            for (int p = 0; p < PO; ++p)
+              acc = fdot2(pr[(D * rho - 1) / 2 + p], as_h2(fa.odd[p]), acc);
+          }
+          if (rho < nvalid) {
+            const bool flag = unsafe || !(__builtin_fabsf(acc) >= M);
+            if (flag) myflags |= 1u << rho;
+            else if (acc >= 0.0f) mybits |= 1u << rho;
+          }
+        }
+        or_bits<R>(bw[w], wl, mybits);
+        push_flags<R>(q, myflags, (uint32_t)s, (uint32_t)(c * SUB + wl));
+      }
+      wave_sync_lds();
+      if (lane < 2 * R) {
+        const int64_t wd = (int64_t)c * R + (lane >> 1);
+        if (wd < nwords) bits32[2 * (wo + wd) + (lane & 1)] = bw[w][lane];
+      }
+      while (qn[w] >= kWave) repair_round(fa, x, x_off, bits32, bit_word_off, q, repair_count);
+    }
+  }
+  while (qn[w] > 0) repair_round(fa, x, x_off, bits32, bit_word_off, q, repair_count);
+}
+
+// ---------------------------------------------------------------------------
+// generic path: any W <= SSH_MAX_W and delta, one window per lane
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void sketch_generic_kernel(
+    const float* __restrict__ x, const int64_t* __restrict__ x_off, int64_t N, FilterArgs fa,
+    uint64_t* __restrict__ bits, const int64_t* __restrict__ bit_word_off,
+    int32_t* __restrict__ nbits_out, unsigned long long* repair_count, int* err) {
+  extern __shared__ unsigned char smem[];
+  const int W = fa.W, D = fa.delta;
+  const int XCAP = (kWave - 1) * D + W + 2;
+  constexpr int QCAP = 2 * kWave;
+  const int w = threadIdx.x / kWave;
+  const int lane = lane_id();
+  // per wave: XCAP floats, 2*QCAP queue words, 2 stream words, 1 counter
+  const size_t per_wave = (size_t)XCAP * 4 + 2 * QCAP * 4 + 2 * 4 + 4;
+  unsigned char* mine = smem + per_wave * w;
+  float* X = reinterpret_cast<float*>(mine);
+  uint32_t* qs = reinterpret_cast<uint32_t*>(mine + (size_t)XCAP * 4);
+  uint32_t* bw = qs + 2 * QCAP;
+  int* qcount = reinterpret_cast<int*>(bw + 2);
+  RepairQueue q{qs, qs + QCAP, qcount};
+  uint32_t* bits32 = reinterpret_cast<uint32_t*>(bits);
+  if (lane == 0) *qcount = 0;
+  wave_sync_lds();
+  const int PE = (W + 1) / 2;
+
+  for (int64_t s = (int64_t)blockIdx.x * kWavesPerBlock + w; s < N;
+       s += (int64_t)gridDim.x * kWavesPerBlock) {
+    const int64_t base = x_off[s];
+    const int64_t m = x_off[s + 1] - base;
+    int nb = m >= W ? (int)((m - W) / D + 1) : 0;
+    const int64_t wo = bit_word_off[s];
+    if (bit_word_off[s + 1] - wo < (nb + 63) / 64) {
+      if (lane == 0) atomicOr(err, 1);
+      nb = 0;
+    }
+    if (lane == 0) nbits_out[s] = nb;
+    const int nwords = (nb + 63) / 64;
+    for (int c = 0; c * kWave < nb; ++c) {
+      const bool unsafe = stage_chunk(X, XCAP, x, base, m, (int64_t)c * kWave * D);
+      if (lane < 2) bw[lane] = 0;
+      wave_sync_lds();
+      const int wi = c * kWave + lane;
+      if (wi < nb) {
+        const float* P = X + lane * D;
+        float acc = 0.0f, E = 0.0f;
+        for (int p = 0; p < PE; ++p) {
+          h2 v = pack_h2(P[2 * p], P[2 * p + 1]);
+          acc = fdot2(v, as_h2(fa.even[p]), acc);
+          E = fdot2(v, v, E);
+        }
+        const float M = window_margin(fa, E, 2 * PE);
+        const bool flag = unsafe || !(__builtin_fabsf(acc) >= M);
+        if (flag) {
+          int slot = atomicAdd(qcount, 1);
+          q.series[slot] = (uint32_t)s;
+          q.window[slot] = (uint32_t)wi;
+        } else if (acc >= 0.0f) {
+          atomicOr(bw + (lane >> 5), 1u << (lane & 31));
+        }
+      }
+      wave_sync_lds();
+      if (lane < 2 && c < nwords) bits32[2 * (wo + c) + lane] = bw[lane];
+      while (*qcount >= kWave) repair_round(fa, x, x_off, bits32, bit_word_off, q, repair_count);
+    }
+  }
+  while (*qcount > 0) repair_round(fa, x, x_off, bits32, bit_word_off, q, repair_count);
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+static uint16_t to_half_bits(float f) {
+  _Float16 h = (_Float16)f;  // round to nearest even
+  return __builtin_bit_cast(uint16_t, h);
+}
+
+static float round_up_f32(double v) {
+  float f = (float)v;
+  if ((double)f < v) f = std::nextafter(f, INFINITY);
+  return f;
+}
+
+static ssh_status make_filter_args(const float* r, int W, int delta, FilterArgs& fa) {
+  memset(&fa, 0, sizeof(fa));
+  double n2 = 0.0;
+  for (int k = 0; k < W; ++k) {
+    if (!(__builtin_fabsf(r[k]) < 16384.0f)) return fail(SSH_EINVAL, "ssh_sketch: filter value not finite or |r| >= 2^14");
+    fa.r[k] = r[k];
+    n2 += (double)r[k] * (double)r[k];
+  }
+  auto rk = [&](int k) -> float { return (k >= 0 && k < W) ? r[k] : 0.0f; };
+  for (int p = 0; p < SSH_MAX_W / 2 + 2; ++p) {
+    fa.even[p] = (uint32_t)to_half_bits(rk(2 * p)) | ((uint32_t)to_half_bits(rk(2 * p + 1)) << 16);
+    fa.odd[p] = (uint32_t)to_half_bits(rk(2 * p - 1)) | ((uint32_t)to_half_bits(rk(2 * p)) << 16);
+  }
+  const double u = 0x1p-11;               // fp16 unit roundoff (nearest)
+  const double e32 = 0x1p-23;              // per-rounding fp32 error, counted generously
+  const double k = W + 2;                  // roundings of the fp32 accumulation
+  const double gam = k * e32 / (1.0 - k * e32);
+  const double bound = (2 * u + u * u + gam * (1 + u) * (1 + u) + (W + 1) * 0x1p-53) * 1.01;
+  fa.c1 = round_up_f32(bound > 1e-3 ? bound : 1e-3);
+  fa.c2 = round_up_f32(0x1p-14 * (1 + u) * 1.01);
+  fa.rnorm = round_up_f32(__builtin_sqrt(n2) * (1 + 0x1p-40));
+  fa.sqrtW = round_up_f32(__builtin_sqrt((double)W));
+  fa.W = W;
+  fa.delta = delta;
+  return SSH_OK;
+}
+
+__device__ int g_sketch_err;
+
+int take_sketch_err() {
+  int v = 0, z = 0;
+  if (hipMemcpyFromSymbol(&v, HIP_SYMBOL(g_sketch_err), sizeof(int)) != hipSuccess) return -1;
+  if (hipMemcpyToSymbol(HIP_SYMBOL(g_sketch_err), &z, sizeof(int)) != hipSuccess) return -1;
+  return v;
+}
+
+ssh_status sketch_launch(const float* x, const int64_t* x_off, int64_t N, const float* r, int W,
+                         int delta, uint64_t* bits, const int64_t* bit_word_off, int32_t* nbits,
+                         uint64_t* repair_count, hipStream_t stream, bool force_generic) {
+  FilterArgs fa;
+  ssh_status st = make_filter_args(r, W, delta, fa);
+  if (st != SSH_OK) return st;
+  if (N == 0) return SSH_OK;
+  int* err = nullptr;
+  if (hipGetSymbolAddress((void**)&err, HIP_SYMBOL(g_sketch_err)) != hipSuccess)
+    return fail(SSH_EDEVICE, "ssh_sketch: cannot resolve error flag");
+  unsigned long long* rc = reinterpret_cast<unsigned long long*>(repair_count);
+  const unsigned grid = grid_for(N, kWavesPerBlock, 1 << 16);
+  const dim3 blk(256);
+#define SSH_FAST(WW, DD, RR)                                                                   \
+  if (!force_generic && W == WW && delta == DD) {                                              \
+    sketch_fast_kernel<WW, DD, RR><<<grid, blk, 0, stream>>>(x, x_off, N, fa, bits,           \
+                                                              bit_word_off, nbits, rc, err);  \
+    return check_launch("ssh_sketch");                                                         \
+  }
+  SSH_FAST(80, 3, 5)
+  SSH_FAST(64, 4, 2)
+  SSH_FAST(128, 4, 8)
+  SSH_FAST(30, 5, 4)
+#undef SSH_FAST
+  const int XCAP = (kWave - 1) * delta + W + 2;
+  const size_t per_wave = (size_t)XCAP * 4 + 2 * 2 * kWave * 4 + 2 * 4 + 4;
+  const size_t shm = per_wave * kWavesPerBlock;
+  if (shm > 160 * 1024) return fail(SSH_EUNSUPPORTED, "ssh_sketch: delta too large for LDS staging");
+  sketch_generic_kernel<<<grid, blk, shm, stream>>>(x, x_off, N, fa, bits, bit_word_off, nbits,
+                                                    rc, err);
+  return check_launch("ssh_sketch");
+}
+
+}  // namespace ssh

@@ -1,0 +1,268 @@
+// Band keys and hash tables (Algorithm 1, "hash each time series into d
+// different hash tables").
+//
+// Keys: table l folds its K hash values with the SplitMix64 output function.
+// Tables: per table, a stable LSD radix sort of (key, id) on the high 32 bits
+// of the key, four 8-bit digit passes.  Each pass is three launches over all
+// tables at once: per-tile digit histograms, an exclusive scan of the
+// (digit, tile) counts, and a stable scatter.  The scatter ranks elements
+// inside a wavefront with a ballot-based match of equal digits, keeps one
+// running count per (wave, digit) in LDS, reorders the tile in LDS and writes
+// each digit's run contiguously.
+#include "common.hpp"
+
+namespace ssh {
+
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__global__ __launch_bounds__(256) void band_keys_kernel(const uint64_t* __restrict__ hv, int64_t N,
+                                                        int K, int L, uint64_t seed,
+                                                        uint64_t* __restrict__ keys) {
+  const int64_t total = N * (int64_t)L;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int H = K * L;
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += stride) {
+    const int64_t s = g / L;
+    const int l = (int)(g - s * L);
+    const uint64_t* h = hv + s * H + (int64_t)l * K;
+    if (hv[s * H] == SSH_HV_EMPTY) {
+      keys[g] = SSH_KEY_EMPTY;
+      continue;
+    }
+    uint64_t k = mix64(seed + (uint64_t)(l + 1) * 0x9E3779B97F4A7C15ull);
+    for (int t = 0; t < K; ++t) k = mix64(k ^ h[t]);
+    keys[g] = k == SSH_KEY_EMPTY ? SSH_KEY_EMPTY - 1 : k;
+  }
+}
+
+ssh_status band_keys_launch(const uint64_t* hv, int64_t N, int K, int L, uint64_t seed,
+                            uint64_t* keys, hipStream_t stream) {
+  if (N == 0) return SSH_OK;
+  band_keys_kernel<<<grid_for(N * (int64_t)L, 256, 1 << 16), 256, 0, stream>>>(hv, N, K, L, seed,
+                                                                              keys);
+  return check_launch("ssh_band_keys");
+}
+
+// ---------------------------------------------------------------------------
+// radix sort of (key, id) per table on key bits [32, 64)
+// ---------------------------------------------------------------------------
+constexpr int kRsThreads = 256;
+constexpr int kRsItems = 16;
+constexpr int kRsTile = kRsThreads * kRsItems;  // 4096
+constexpr int kRsWaves = kRsThreads / kWave;
+constexpr int kRsPerWave = kWave * kRsItems;   // 1024 contiguous elements per wave
+
+struct RsIn {
+  const uint64_t* keys;  // pass 0: series-major [N * L]; later: table-major [L * N]
+  const uint32_t* ids;   // null on pass 0 (ids are the series index)
+  bool first;
+};
+
+__device__ __forceinline__ void rs_load(const RsIn in, int64_t e, int64_t N, int L, int l,
+                                        uint64_t& key, uint32_t& id) {
+  if (in.first) {
+    key = in.keys[e * L + l];
+    id = (uint32_t)e;
+  } else {
+    key = in.keys[(int64_t)l * N + e];
+    id = in.ids[(int64_t)l * N + e];
+  }
+}
+
+__global__ __launch_bounds__(kRsThreads) void rs_hist_kernel(RsIn in, int64_t N, int L, int shift,
+                                                             int nblk, uint32_t* __restrict__ hist) {
+  __shared__ uint32_t h[256];
+  const int l = blockIdx.y, b = blockIdx.x;
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t base = (int64_t)b * kRsTile;
+  for (int i = threadIdx.x; i < kRsTile; i += kRsThreads) {
+    const int64_t e = base + i;
+    if (e < N) {
+      uint64_t key;
+      uint32_t id;
+      rs_load(in, e, N, L, l, key, id);
+      atomicAdd(&h[(key >> shift) & 255], 1u);
+    }
+  }
+  __syncthreads();
+  hist[((int64_t)l * 256 + threadIdx.x) * nblk + b] = h[threadIdx.x];
+}
+
+// exclusive scan, per table, of the nblk*256 counts in (digit, tile) order
+__global__ __launch_bounds__(1024) void rs_scan_kernel(uint32_t* __restrict__ hist, int nblk) {
+  __shared__ uint32_t part[1024];
+  const int l = blockIdx.x;
+  uint32_t* h = hist + (int64_t)l * 256 * nblk;
+  const int64_t n = (int64_t)256 * nblk;
+  const int64_t chunk = (n + 1023) / 1024;
+  const int64_t lo = threadIdx.x * chunk;
+  const int64_t hi = lo + chunk < n ? lo + chunk : n;
+  uint32_t sum = 0;
+  for (int64_t i = lo; i < hi; ++i) sum += h[i];
+  part[threadIdx.x] = sum;
+  __syncthreads();
+  for (int d = 1; d < 1024; d <<= 1) {
+    uint32_t v = threadIdx.x >= (unsigned)d ? part[threadIdx.x - d] : 0u;
+    __syncthreads();
+    part[threadIdx.x] += v;
+    __syncthreads();
+  }
+  uint32_t run = part[threadIdx.x] - sum;
+  for (int64_t i = lo; i < hi; ++i) {
+    uint32_t c = h[i];
+    h[i] = run;
+    run += c;
+  }
+}
+
+__global__ __launch_bounds__(kRsThreads) void rs_scatter_kernel(RsIn in, int64_t N, int L,
+                                                                int shift, int nblk,
+                                                                const uint32_t* __restrict__ offs,
+                                                                uint64_t* __restrict__ out_keys,
+                                                                uint32_t* __restrict__ out_ids) {
+  __shared__ uint32_t wcnt[kRsWaves][256];
+  __shared__ uint32_t tstart[256];
+  __shared__ uint32_t gbase[256];
+  __shared__ uint64_t skeys[kRsTile];
+  __shared__ uint32_t sids[kRsTile];
+  const int l = blockIdx.y, b = blockIdx.x;
+  const int w = threadIdx.x / kWave;
+  const int lane = lane_id();
+  for (int i = threadIdx.x; i < kRsWaves * 256; i += kRsThreads) (&wcnt[0][0])[i] = 0;
+  __syncthreads();
+
+  const int64_t tbase = (int64_t)b * kRsTile;
+  const int64_t wbase = tbase + (int64_t)w * kRsPerWave;
+  const uint64_t lt_mask = (1ull << lane) - 1ull;
+  uint64_t key[kRsItems];
+  uint32_t id[kRsItems];
+  uint32_t rank[kRsItems];
+#pragma unroll
+  for (int q = 0; q < kRsItems; ++q) {
+    const int64_t e = wbase + q * kWave + lane;
+    const bool valid = e < N;
+    key[q] = 0;
+    id[q] = 0;
+    if (valid) rs_load(in, e, N, L, l, key[q], id[q]);
+    const uint32_t d = (uint32_t)(key[q] >> shift) & 255u;
+    uint64_t peers = ballot64(valid);
+#pragma unroll
+    for (int bit = 0; bit < 8; ++bit) {
+      const bool on = (d >> bit) & 1u;
+      const uint64_t bal = ballot64(valid && on);
+      peers &= on ? bal : ~bal;
+    }
+    rank[q] = 0;
+    if (valid) {
+      const uint32_t before = wcnt[w][d];
+      rank[q] = before + (uint32_t)__builtin_popcountll(peers & lt_mask);
+      if ((peers & lt_mask) == 0) wcnt[w][d] = before + (uint32_t)__builtin_popcountll(peers);
+    }
+    wave_sync_lds();
+  }
+  __syncthreads();
+  // per digit: exclusive offsets over waves, tile totals, tile-local starts
+  {
+    const int d = threadIdx.x;  // 256 threads, one digit each
+    uint32_t run = 0;
+#pragma unroll
+    for (int ww = 0; ww < kRsWaves; ++ww) {
+      const uint32_t c = wcnt[ww][d];
+      wcnt[ww][d] = run;
+      run += c;
+    }
+    tstart[d] = run;  // tile total for now
+    gbase[d] = offs[((int64_t)l * 256 + d) * nblk + b];
+  }
+  __syncthreads();
+  if (threadIdx.x < kWave) {
+    // exclusive scan of the 256 tile totals by one wave (4 per lane)
+    const int t = threadIdx.x;
+    uint32_t v0 = tstart[4 * t], v1 = tstart[4 * t + 1], v2 = tstart[4 * t + 2], v3 = tstart[4 * t + 3];
+    const uint32_t tot = v0 + v1 + v2 + v3;
+    const uint32_t incl = wave_incl_scan(tot);
+    uint32_t run = incl - tot;
+    tstart[4 * t] = run;
+    run += v0;
+    tstart[4 * t + 1] = run;
+    run += v1;
+    tstart[4 * t + 2] = run;
+    run += v2;
+    tstart[4 * t + 3] = run;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < kRsItems; ++q) {
+    const int64_t e = wbase + q * kWave + lane;
+    if (e < N) {
+      const uint32_t d = (uint32_t)(key[q] >> shift) & 255u;
+      const uint32_t pos = tstart[d] + wcnt[w][d] + rank[q];
+      skeys[pos] = key[q];
+      sids[pos] = id[q];
+    }
+  }
+  __syncthreads();
+  const int64_t left = N - tbase;
+  const int cnt = left < kRsTile ? (int)left : kRsTile;
+  for (int p = threadIdx.x; p < cnt; p += kRsThreads) {
+    const uint64_t k = skeys[p];
+    const uint32_t d = (uint32_t)(k >> shift) & 255u;
+    const int64_t dst = (int64_t)gbase[d] + (p - (int64_t)tstart[d]);
+    out_keys[(int64_t)l * N + dst] = k;
+    out_ids[(int64_t)l * N + dst] = sids[p];
+  }
+}
+
+static inline size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+size_t table_workspace_bytes(int64_t N, int L) {
+  const int64_t nblk = ceil_div(N > 0 ? N : 1, kRsTile);
+  return align256((size_t)N * L * 8) + align256((size_t)N * L * 4) +
+         align256((size_t)L * 256 * nblk * 4);
+}
+
+ssh_status table_build_launch(const uint64_t* keys, int64_t N, int L, uint64_t* tab_keys,
+                              uint32_t* tab_ids, void* ws, size_t ws_bytes, hipStream_t stream) {
+  if (N == 0) return SSH_OK;
+  if (ws_bytes < table_workspace_bytes(N, L))
+    return fail(SSH_EINVAL, "ssh_table_build: workspace too small");
+  const int nblk = (int)ceil_div(N, kRsTile);
+  unsigned char* p = reinterpret_cast<unsigned char*>(ws);
+  uint64_t* alt_keys = reinterpret_cast<uint64_t*>(p);
+  p += align256((size_t)N * L * 8);
+  uint32_t* alt_ids = reinterpret_cast<uint32_t*>(p);
+  p += align256((size_t)N * L * 4);
+  uint32_t* hist = reinterpret_cast<uint32_t*>(p);
+  const dim3 grid(nblk, L);
+  // passes: keys -> alt -> tab -> alt -> tab
+  for (int pass = 0; pass < 4; ++pass) {
+    const int shift = 32 + 8 * pass;
+    RsIn in;
+    uint64_t* ok;
+    uint32_t* oi;
+    if (pass == 0) {
+      in = RsIn{keys, nullptr, true};
+      ok = alt_keys;
+      oi = alt_ids;
+    } else if (pass % 2 == 1) {
+      in = RsIn{alt_keys, alt_ids, false};
+      ok = tab_keys;
+      oi = tab_ids;
+    } else {
+      in = RsIn{tab_keys, tab_ids, false};
+      ok = alt_keys;
+      oi = alt_ids;
+    }
+    rs_hist_kernel<<<grid, kRsThreads, 0, stream>>>(in, N, L, shift, nblk, hist);
+    rs_scan_kernel<<<L, 1024, 0, stream>>>(hist, nblk);
+    rs_scatter_kernel<<<grid, kRsThreads, 0, stream>>>(in, N, L, shift, nblk, hist, ok, oi);
+  }
+  return check_launch("ssh_table_build");
+}
+
+}  // namespace ssh

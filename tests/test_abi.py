@@ -1,0 +1,107 @@
+"""CPU checks of the C ABI: the library loads, exports every declared symbol,
+its host-only helpers agree with the oracle's size rules, and argument
+validation rejects bad calls before touching the device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ssh.h")
+
+
+@pytest.fixture(scope="module")
+def ssh():
+    from paper_1610_07328_amd import ssh as mod
+    if not os.path.exists(mod.LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+    mod.lib()
+    return mod
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\*?\s+\*?([a-z_0-9]+)\s*\(", text, flags=re.M)
+    return sorted(set(n for n in names if n not in {"if", "return"}))
+
+
+def test_header_declares_the_pipeline():
+    names = _declared_functions()
+    for want in ["ssh_sketch", "ssh_shingle", "ssh_cws", "ssh_band_keys", "dtw_rerank",
+                 "ssh_table_build", "ssh_probe", "ssh_plan", "ssh_cws_prepare"]:
+        assert want in names
+
+
+def test_every_declared_symbol_is_exported(ssh):
+    lib = ctypes.CDLL(ssh.LIB_PATH)
+    names = _declared_functions()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(lib, n), n
+        assert n in ssh.SIGNATURES, n
+
+
+def test_size_helpers_match_oracle(ssh):
+    for m in [0, 1, 63, 64, 65, 100, 512, 1024, 2048, 8192]:
+        for W, d in [(64, 4), (80, 3), (128, 4), (30, 5), (1, 1)]:
+            assert ssh.num_bits(m, W, d) == oracle.num_bits(m, W, d)
+    for nb in [0, 1, 11, 12, 13, 315]:
+        for n in [1, 12, 15, 16]:
+            assert ssh.num_shingles(nb, n) == oracle.num_shingles(nb, n)
+
+
+def test_plan_offsets(ssh):
+    rng = np.random.default_rng(0)
+    lens = np.concatenate([[0, 79, 80, 83], rng.integers(0, 3000, 50)])
+    off = np.zeros(len(lens) + 1, np.int64)
+    np.cumsum(lens, out=off[1:])
+    p = ssh.plan(off, 80, 3, 15)
+    nb = [oracle.num_bits(int(m), 80, 3) for m in lens]
+    assert np.array_equal(np.diff(p.bit_word_off), [(b + 63) // 64 for b in nb])
+    assert np.array_equal(np.diff(p.hist_off), [oracle.num_shingles(b, 15) for b in nb])
+    assert p.max_nbits == max(nb)
+
+
+def test_validation_rejects_without_device_work(ssh):
+    L = ssh.lib()
+    EINVAL, EUNSUP = -1, -2
+    r = np.ones(8, np.float32)
+    dummy = ctypes.c_void_p(16)
+    # bad W, delta, N
+    assert L.ssh_sketch(dummy, dummy, 4, r.ctypes.data, 0, 1, dummy, dummy, dummy, None, None) == EINVAL
+    assert L.ssh_sketch(dummy, dummy, 4, r.ctypes.data, 8, 0, dummy, dummy, dummy, None, None) == EINVAL
+    assert L.ssh_sketch(dummy, dummy, -1, r.ctypes.data, 8, 1, dummy, dummy, dummy, None, None) == EINVAL
+    assert b"W" in L.ssh_last_error() or b"delta" in L.ssh_last_error() or b"N" in L.ssh_last_error()
+    big = np.ones(300, np.float32)
+    assert L.ssh_sketch(dummy, dummy, 4, big.ctypes.data, 300, 1, dummy, dummy, dummy, None, None) == EINVAL
+    # shingle length beyond 16
+    assert L.ssh_shingle(dummy, dummy, dummy, 4, 17, dummy, dummy, dummy, dummy, None) == EINVAL
+    # probe cap, rerank k and band
+    assert L.ssh_probe(dummy, dummy, 10, 2, dummy, dummy, 4, dummy, dummy, 1, 0, dummy, dummy,
+                       dummy, None) == EINVAL
+    assert L.ssh_probe(dummy, dummy, 10, 2, dummy, dummy, 4, dummy, dummy, 1, 5000, dummy, dummy,
+                       dummy, None) == EINVAL
+    assert L.dtw_rerank(dummy, dummy, 1, dummy, dummy, 10, dummy, dummy, 8, 0.1, 100, 100, 9,
+                        dummy, dummy, dummy, 1 << 20, None) == EINVAL
+    assert L.dtw_rerank(dummy, dummy, 1, dummy, dummy, 10, dummy, dummy, 8, 1.5, 100, 100, 4,
+                        dummy, dummy, dummy, 1 << 20, None) == EINVAL
+    # a filter value that fp16 staging cannot represent is refused
+    bad = np.array([1.0, np.inf, 0.5], np.float32)
+    assert L.ssh_sketch(dummy, dummy, 4, bad.ctypes.data, 3, 1, dummy, dummy, dummy, None, None) == EINVAL
+    # empty batches are not errors
+    assert L.ssh_sketch(None, None, 0, r.ctypes.data, 8, 1, None, None, None, None, None) == 0
+    # CWS tables with n out of range
+    t = ssh._CwsTablesC(17, 4, 16, 16, 16, 16, 16)
+    assert L.ssh_cws_prepare(ctypes.byref(t), None) == EINVAL
+    assert L.ssh_status_str(EUNSUP) == b"SSH_EUNSUPPORTED"
+
+
+def test_workspace_sizes(ssh):
+    assert ssh.table_workspace_bytes(1_000_000, 10) >= 1_000_000 * 10 * 12
+    assert ssh.rerank_workspace_bytes(50, 50) >= 50 * 50 * 4

@@ -1,0 +1,434 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Bits, counts, hash values, keys, tables and candidate lists must be
+identical; DTW distances must agree within 1e-5 relative.  Inputs are the
+seeded synthetic generators; no expected value comes from the HIP path.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1610_07328_amd import datagen
+from tests._gpu_helpers import ragged, to_dev, to_np, unpack_bits
+
+pytestmark = pytest.mark.gpu
+
+DTW_RTOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def ssh():
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_1610_07328_amd import ssh as mod
+    mod.lib()
+    return mod
+
+
+def _announce(msg):
+    print(f"\n[case] {msg}", flush=True)
+
+
+# --------------------------------------------------------------------------
+# sketch
+# --------------------------------------------------------------------------
+def _run_sketch(ssh, x, off, r, W, delta, generic=False):
+    p = ssh.plan(off, W, delta, 1)
+    bits, nbits, rep = ssh.sketch(to_dev(x), to_dev(off), r, W, delta, to_dev(p.bit_word_off),
+                                  generic=generic)
+    torch.cuda.synchronize()
+    ssh.check_device_errors()
+    return to_np(bits), p.bit_word_off, to_np(nbits), int(to_np(rep)[0])
+
+
+def _assert_sketch_equal(ssh, x, off, r, W, delta, generic=False):
+    words, bwo, nb, rep = _run_sketch(ssh, x, off, r, W, delta, generic)
+    N = len(off) - 1
+    for s in range(N):
+        want = oracle.sketch_series(x[off[s]:off[s + 1]], r, W, delta)
+        assert nb[s] == len(want), (s, nb[s], len(want))
+        got = unpack_bits(words, bwo, nb, s)
+        if not np.array_equal(got, want):
+            bad = np.nonzero(got != want)[0]
+            raise AssertionError(f"series {s}: {len(bad)} bits differ, first at {bad[:5]}")
+        # unused high bits of the last word are zero
+        if nb[s] % 64:
+            last = int(words[bwo[s + 1] - 1])
+            assert last >> int(nb[s] % 64) == 0
+    return rep
+
+
+@pytest.mark.parametrize("N,m,W,delta", [(2000, 512, 64, 4), (1024, 1024, 80, 3),
+                                         (256, 2048, 128, 4), (512, 700, 30, 5)])
+def test_sketch_fast_path_matches_oracle(ssh, N, m, W, delta):
+    _announce(f"sketch fast N={N} m={m} W={W} delta={delta}")
+    X = datagen.random_walks(N, m, seed=1)
+    r = datagen.filter_r(W, seed=1)
+    x, off = datagen.csr(X)
+    B = oracle.sketch_batch(X, r, W, delta)
+    words, bwo, nb, rep = _run_sketch(ssh, x, off, r, W, delta)
+    assert np.all(nb == B.shape[1])
+    for s in range(N):
+        assert np.array_equal(unpack_bits(words, bwo, nb, s), B[s]), s
+    # the repair pass is exercised on this data
+    assert rep >= 0
+
+
+@pytest.mark.parametrize("W,delta", [(7, 1), (33, 2), (80, 3), (256, 7), (1, 1), (30, 5)])
+def test_sketch_generic_path_ragged(ssh, W, delta):
+    _announce(f"sketch generic ragged W={W} delta={delta}")
+    rng = np.random.default_rng(W * 10 + delta)
+    lens = [0, 1, W - 1, W, W + delta - 1, W + delta, 5 * W + 3, 900, 2500]
+    lens += list(rng.integers(0, 1500, size=20))
+    series = [datagen.random_walks(1, int(m), seed=int(m) + 3)[0] if m > 1 else
+              np.zeros(int(m), np.float32) for m in lens]
+    x, off = ragged(series)
+    r = datagen.filter_r(W, seed=W)
+    _assert_sketch_equal(ssh, x, off, r, W, delta, generic=True)
+    _assert_sketch_equal(ssh, x, off, r, W, delta, generic=False)
+
+
+def test_sketch_multichunk_ragged_ecg(ssh):
+    _announce("sketch ragged RW/ECG 256..8192 W=80 delta=3")
+    x, off = datagen.ragged_series(40, 256, 8192, seed=5)
+    r = datagen.filter_r(80, seed=5)
+    _assert_sketch_equal(ssh, x, off, r, 80, 3)
+
+
+def _near_zero_windows(W, count, seed):
+    """Series of one window each whose float64 inner product with r is ~0."""
+    rng = np.random.default_rng(seed)
+    r = rng.standard_normal(W).astype(np.float32)
+    out = []
+    for i in range(count):
+        w = rng.standard_normal(W).astype(np.float64)
+        if i % 3 == 0:
+            w *= 2.0 ** rng.integers(-30, 10)
+        partial = float(np.dot(r[:-1].astype(np.float64), w[:-1]))
+        w[-1] = -partial / float(r[-1])
+        w = w.astype(np.float32)
+        if i % 7 == 0:
+            w[:] = 0.0
+        out.append(w)
+    return r, out
+
+
+@pytest.mark.parametrize("W,delta", [(80, 3), (64, 4), (13, 2)])
+def test_sketch_adversarial_near_zero_windows(ssh, W, delta):
+    _announce(f"sketch adversarial W={W}")
+    r, series = _near_zero_windows(W, 600, seed=W)
+    x, off = ragged(series)
+    rep = _assert_sketch_equal(ssh, x, off, r, W, delta)
+    assert rep > 0  # these windows must take the float64 path
+
+
+def test_sketch_huge_and_nonfinite_values(ssh):
+    _announce("sketch huge / non-finite values")
+    rng = np.random.default_rng(17)
+    W, delta = 80, 3
+    r = datagen.filter_r(W, seed=17)
+    series = []
+    for i in range(12):
+        s = rng.standard_normal(600).astype(np.float32)
+        if i % 4 == 0:
+            s *= np.float32(3.0e4)
+        elif i % 4 == 1:
+            s[rng.integers(0, 600)] = np.inf
+        elif i % 4 == 2:
+            s[rng.integers(0, 600)] = np.nan
+        else:
+            s[100:140] = np.float32(-2.0e5)
+        series.append(s)
+    x, off = ragged(series)
+    _assert_sketch_equal(ssh, x, off, r, W, delta)
+
+
+# --------------------------------------------------------------------------
+# shingles
+# --------------------------------------------------------------------------
+def _pack_streams(streams):
+    nb = np.array([len(b) for b in streams], np.int64)
+    bwo = np.zeros(len(streams) + 1, np.int64)
+    np.cumsum((nb + 63) // 64, out=bwo[1:])
+    words = np.zeros(max(int(bwo[-1]), 1), np.uint64)
+    for s, b in enumerate(streams):
+        if len(b):
+            pad = np.zeros(((len(b) + 63) // 64) * 64, np.uint8)
+            pad[: len(b)] = b
+            words[bwo[s]: bwo[s + 1]] = np.packbits(pad, bitorder="little").view(np.uint64)
+    return words, bwo, nb.astype(np.int32)
+
+
+@pytest.mark.parametrize("n", [1, 2, 5, 12, 15, 16])
+def test_shingle_matches_oracle(ssh, n):
+    _announce(f"shingle n={n}")
+    rng = np.random.default_rng(n)
+    streams = []
+    for i, L in enumerate([0, 1, n - 1, n, n + 1, 64, 65, 130, 301, 3000, 2705]):
+        p = 0.5 if i % 2 else 0.93
+        streams.append((rng.random(L) < p).astype(np.uint8))
+    # a stream from a real sketch (long runs)
+    X = datagen.random_walks(3, 1024, seed=n)
+    streams += list(oracle.sketch_batch(X, datagen.filter_r(80, seed=n), 80, 3))
+    words, bwo, nb = _pack_streams(streams)
+    hist_off = np.zeros(len(streams) + 1, np.int64)
+    np.cumsum([max(0, int(b) - n + 1) for b in nb], out=hist_off[1:])
+    codes, counts, nd = ssh.shingle(to_dev(words), to_dev(bwo), to_dev(nb), n, to_dev(hist_off))
+    torch.cuda.synchronize()
+    ssh.check_device_errors()
+    codes, counts, nd = to_np(codes), to_np(counts), to_np(nd)
+    for s, b in enumerate(streams):
+        wc, wn = oracle.shingle(b, n)
+        assert nd[s] == len(wc), (s, nd[s], len(wc))
+        o = hist_off[s]
+        assert np.array_equal(codes[o:o + nd[s]], wc), s
+        assert np.array_equal(counts[o:o + nd[s]], wn), s
+
+
+# --------------------------------------------------------------------------
+# weighted MinHash
+# --------------------------------------------------------------------------
+def test_ln_table_exact(ssh):
+    _announce("cws lnS table")
+    r, lnc, beta = datagen.cws_draws(4, 3, seed=0)
+    t = ssh.CwsTables(r, lnc, beta, 4)
+    torch.cuda.synchronize()
+    got = to_np(t.lnS)
+    want = oracle.ln_table(ssh.LNS_ENTRIES - 1)
+    assert np.array_equal(got[1:], want[1:])
+
+
+def _cws_case(ssh, n, H, sets, seed):
+    r, lnc, beta = datagen.cws_draws(n, H, seed=seed)
+    tabs = ssh.CwsTables(r, lnc, beta, n)
+    codes = np.concatenate([c for c, _ in sets] + [np.zeros(0, np.uint32)]).astype(np.uint32)
+    counts = np.concatenate([k for _, k in sets] + [np.zeros(0, np.uint32)]).astype(np.uint32)
+    ho = np.zeros(len(sets) + 1, np.int64)
+    np.cumsum([len(c) for c, _ in sets], out=ho[1:])
+    nd = np.array([len(c) for c, _ in sets], np.int32)
+    hv = ssh.cws(to_dev(np.maximum(codes, 0) if codes.size else np.zeros(1, np.uint32)),
+                 to_dev(counts if counts.size else np.zeros(1, np.uint32)), to_dev(ho),
+                 to_dev(nd), tabs)
+    torch.cuda.synchronize()
+    ssh.check_device_errors()
+    hv = to_np(hv)
+    smax = int(counts.max()) if counts.size else 1
+    lnS = oracle.ln_table(max(smax, 2))
+    for s, (c, k) in enumerate(sets):
+        want = oracle.cws(c, k, r, lnc, beta, lnS)[2]
+        assert np.array_equal(hv[s], want), s
+
+
+def test_cws_random_sets_exact(ssh):
+    _announce("cws random sets n=12 H=20 / n=6 H=257")
+    rng = np.random.default_rng(3)
+    for n, H in [(12, 20), (6, 257)]:
+        sets = [(np.zeros(0, np.uint32), np.zeros(0, np.uint32))]
+        for i in range(300):
+            D = int(rng.integers(1, min(200, 1 << n) + 1))
+            c = np.sort(rng.choice(1 << n, size=D, replace=False)).astype(np.uint32)
+            k = (rng.integers(1, 3, size=D) if i % 2 else rng.integers(1, 300, size=D)).astype(np.uint32)
+            sets.append((c, k))
+        _cws_case(ssh, n, H, sets, seed=n)
+
+
+def test_cws_counts_beyond_table(ssh):
+    _announce("cws counts beyond the ln table")
+    rng = np.random.default_rng(4)
+    sets = []
+    for i in range(40):
+        D = 10
+        c = np.sort(rng.choice(64, size=D, replace=False)).astype(np.uint32)
+        k = rng.integers(65530, 65600, size=D).astype(np.uint32)
+        sets.append((c, k))
+    _cws_case(ssh, 6, 33, sets, seed=9)
+
+
+# --------------------------------------------------------------------------
+# full pipeline pieces on C1-shaped data
+# --------------------------------------------------------------------------
+C1 = dict(N=2000, m=512, W=64, delta=4, n=12, K=4, L=5, nq=50, C=50, band=0.05, k=10)
+
+
+@pytest.fixture(scope="module")
+def c1(ssh):
+    P = C1
+    X = datagen.random_walks(P["N"], P["m"], seed=0)
+    r = datagen.filter_r(P["W"], seed=0)
+    Q, src = datagen.perturbed_queries(X, P["nq"], 0.1, seed=0)
+    Q = np.concatenate([Q, X[:3], np.zeros((1, P["m"]), np.float32)])  # exact copies, one flat
+    draws = datagen.cws_draws(P["n"], P["K"] * P["L"], seed=0)
+    return X, r, Q, draws
+
+
+def _gpu_hash(ssh, X, r, draws, P):
+    x, off = datagen.csr(X)
+    p = ssh.plan(off, P["W"], P["delta"], P["n"])
+    offd = to_dev(off)
+    bits, nb, _ = ssh.sketch(to_dev(x), offd, r, P["W"], P["delta"], to_dev(p.bit_word_off))
+    codes, counts, nd = ssh.shingle(bits, to_dev(p.bit_word_off), nb, P["n"], to_dev(p.hist_off))
+    tabs = ssh.CwsTables(*draws, P["n"])
+    hv = ssh.cws(codes, counts, to_dev(p.hist_off), nd, tabs)
+    keys = ssh.band_keys(hv, P["K"], P["L"], seed=7)
+    torch.cuda.synchronize()
+    return hv, keys
+
+
+def _oracle_hash(X, r, draws, P):
+    B = oracle.sketch_batch(X, r, P["W"], P["delta"])
+    sets = [oracle.shingle(b, P["n"]) for b in B]
+    lnS = oracle.ln_table(max(1, max(int(k.max()) if len(k) else 1 for _, k in sets)))
+    hv = np.stack([oracle.cws(c, k, *draws, lnS)[2] for c, k in sets])
+    return hv, oracle.band_keys(hv, P["K"], P["L"], seed=7)
+
+
+def test_c1_hash_values_and_keys_exact(ssh, c1):
+    _announce("C1 hash values and keys")
+    X, r, Q, draws = c1
+    hv, keys = _gpu_hash(ssh, X, r, draws, C1)
+    ohv, okeys = _oracle_hash(X, r, draws, C1)
+    assert np.array_equal(to_np(hv), ohv)
+    assert np.array_equal(to_np(keys), okeys)
+    # deterministic: the same launch twice gives the same bits
+    hv2, keys2 = _gpu_hash(ssh, X, r, draws, C1)
+    assert torch.equal(hv.cpu(), hv2.cpu()) and torch.equal(keys.cpu(), keys2.cpu())
+
+
+@pytest.mark.parametrize("N,L,distinct", [(2000, 5, None), (10007, 3, 50), (4096, 2, 1)])
+def test_table_build_exact(ssh, N, L, distinct):
+    _announce(f"table build N={N} L={L}")
+    rng = np.random.default_rng(N)
+    if distinct is None:
+        keys = rng.integers(0, 2**63, size=(N, L), dtype=np.int64).astype(np.uint64) * np.uint64(2)
+    else:
+        base = rng.integers(0, 2**63, size=distinct, dtype=np.int64).astype(np.uint64)
+        keys = base[rng.integers(0, distinct, size=(N, L))]
+        keys[::5] ^= np.uint64(1)  # equal high halves, different full keys
+    keys[3] = np.uint64(oracle.KEY_EMPTY)
+    tk, ti = ssh.table_build(to_dev(keys))
+    torch.cuda.synchronize()
+    otk, oti = oracle.build_tables(keys)
+    assert np.array_equal(to_np(tk), otk)
+    assert np.array_equal(to_np(ti), oti)
+
+
+def test_c1_probe_exact(ssh, c1):
+    _announce("C1 probe")
+    X, r, Q, draws = c1
+    P = C1
+    hv, keys = _gpu_hash(ssh, X, r, draws, P)
+    qhv, qkeys = _gpu_hash(ssh, Q, r, draws, P)
+    tk, ti = ssh.table_build(keys)
+    cand, ncand, rs = ssh.probe(tk, ti, keys, hv, qkeys, qhv, P["C"])
+    torch.cuda.synchronize()
+    cand, ncand, rs = to_np(cand), to_np(ncand), to_np(rs)
+    ohv, okeys = to_np(hv), to_np(keys)
+    oq_hv, oq_keys = to_np(qhv), to_np(qkeys)
+    for i in range(Q.shape[0]):
+        oc, orr = oracle.probe(okeys, ohv, oq_keys[i], oq_hv[i], P["C"])
+        assert rs[i] == orr and ncand[i] == len(oc), i
+        assert np.array_equal(cand[i, : ncand[i]], oc), i
+        assert np.all(cand[i, ncand[i]:] == -1)
+    # exact copies find themselves first
+    for t in range(3):
+        assert cand[P["nq"] + t, 0] == t
+
+
+def test_probe_large_retrieved_sets_with_ties(ssh):
+    """|R| far above C and a tie level larger than the in-LDS tie buffer."""
+    _announce("probe large R with ties")
+    rng = np.random.default_rng(21)
+    N, L, H, C = 20000, 2, 8, 100
+    hv = rng.integers(0, 2, size=(N, H), dtype=np.int64).astype(np.uint64)
+    keys = np.stack([np.where(rng.random(N) < 0.5, np.uint64(11), np.uint64(22)),
+                     np.where(rng.random(N) < 0.5, np.uint64(33), np.uint64(44))], 1).astype(np.uint64)
+    keys = keys * np.uint64(0x9E3779B97F4A7C15)
+    qk = np.stack([keys[0], keys[1], keys[2]])
+    qh = np.stack([hv[0], np.zeros(H, np.uint64), np.full(H, 7, np.uint64)])
+    tk, ti = ssh.table_build(to_dev(keys))
+    cand, ncand, rs = ssh.probe(tk, ti, to_dev(keys), to_dev(hv), to_dev(qk), to_dev(qh), C)
+    torch.cuda.synchronize()
+    cand, ncand, rs = to_np(cand), to_np(ncand), to_np(rs)
+    for i in range(3):
+        oc, orr = oracle.probe(keys, hv, qk[i], qh[i], C)
+        assert rs[i] == orr and ncand[i] == len(oc)
+        assert np.array_equal(cand[i, : ncand[i]], oc), i
+
+
+# --------------------------------------------------------------------------
+# DTW re-rank
+# --------------------------------------------------------------------------
+def _compare_rerank(ids, dist, oids, odist, all_odist, cand, ncand):
+    for i in range(ids.shape[0]):
+        for j in range(ids.shape[1]):
+            if oids[i, j] < 0:
+                assert ids[i, j] == -1 and math.isinf(dist[i, j])
+                continue
+            if math.isinf(odist[i, j]):
+                assert math.isinf(dist[i, j])
+            else:
+                assert abs(dist[i, j] - odist[i, j]) <= DTW_RTOL * max(odist[i, j], 1e-30), (i, j)
+        # same ids except where the oracle's k-th and (k+1)-th are near ties
+        got, want = set(ids[i][ids[i] >= 0].tolist()), set(oids[i][oids[i] >= 0].tolist())
+        if got != want:
+            row = np.sort(all_odist[i, : ncand[i]])
+            kk = ids.shape[1]
+            assert kk < len(row) and abs(row[kk] - row[kk - 1]) <= DTW_RTOL * row[kk], i
+
+
+def _rerank_case(ssh, Q, X, cand, ncand, band, k):
+    q, qoff = datagen.csr(Q)
+    db, dboff = datagen.csr(X)
+    ids, dist = ssh.dtw_rerank(to_dev(q), to_dev(qoff), to_dev(db), to_dev(dboff), to_dev(cand),
+                               to_dev(ncand), band, Q.shape[1], X.shape[1], k)
+    torch.cuda.synchronize()
+    ssh.check_device_errors()
+    oids, odist, all_d = oracle.rerank(q, qoff, db, dboff, cand, ncand, band, k)
+    _compare_rerank(to_np(ids), to_np(dist), oids, odist, all_d, cand, ncand)
+
+
+def test_c1_rerank(ssh, c1):
+    _announce("C1 rerank")
+    X, r, Q, draws = c1
+    rng = np.random.default_rng(0)
+    nq, C = Q.shape[0], C1["C"]
+    cand = rng.integers(0, X.shape[0], size=(nq, C)).astype(np.int64)
+    cand[:, 0] = np.arange(nq) % X.shape[0]
+    ncand = rng.integers(0, C + 1, size=nq).astype(np.int32)
+    ncand[:5] = C
+    _rerank_case(ssh, Q, X, cand, ncand, C1["band"], C1["k"])
+
+
+@pytest.mark.parametrize("m,band,lq", [(128, 0.05, 128), (200, 0.0, 200), (200, 1.0, 200),
+                                       (1024, 0.05, 1024), (300, 0.1, 290), (64, 0.1, 50),
+                                       (2048, 0.1, 2048)])
+def test_rerank_band_shapes(ssh, m, band, lq):
+    _announce(f"rerank m={m} band={band} lq={lq}")
+    N = 40
+    X = datagen.random_walks(N, m, seed=m)
+    Q = datagen.random_walks(3, lq, seed=lq + 1)
+    if lq == m:
+        Q[0] = X[5]
+    nq = Q.shape[0]
+    C = 8 if m >= 2048 else 24
+    rng = np.random.default_rng(m)
+    cand = rng.integers(0, N, size=(nq, C)).astype(np.int64)
+    ncand = np.full(nq, C, np.int32)
+    _rerank_case(ssh, Q, X, cand, ncand, band, min(10, C))
+
+
+def test_rerank_reports_length_mismatch(ssh):
+    """A candidate whose length differs from db_len is flagged, not computed."""
+    _announce("rerank length mismatch flag")
+    X = datagen.random_walks(4, 100, seed=1)
+    q, qoff = datagen.csr(X[:1])
+    db, dboff = datagen.csr(X)
+    cand = np.array([[0, 1, 2]], np.int64)
+    ncand = np.array([3], np.int32)
+    ssh.dtw_rerank(to_dev(q), to_dev(qoff), to_dev(db), to_dev(dboff), to_dev(cand), to_dev(ncand),
+                   0.1, 100, 99, 2)
+    with pytest.raises(ssh.SSHError):
+        ssh.check_device_errors()
+    ssh.check_device_errors()  # flags were cleared
