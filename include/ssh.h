@@ -125,10 +125,9 @@ ssh_status ssh_shingle(const uint64_t* bits, const int64_t* bit_word_off, const 
 
 /* Random numbers of consistent weighted sampling, one triple per (token k,
  * hash j), code-major: element [k * H + j] of each array.  They are inputs,
- * drawn by the caller: r ~ Gamma(2,1) (> 0), lnc = ln c with c ~ Gamma(2,1),
- * beta ~ U[0,1).  a1 and lnS are scratch tables the caller allocates
- * (a1: 2^n * H doubles, lnS: SSH_LNS_ENTRIES doubles) and fills once with
- * ssh_cws_prepare. */
+ * drawn by the caller: r ~ Gamma(2,1) (0 < r < 1e5), lnc = ln c with
+ * c ~ Gamma(2,1), beta ~ U[0,1).  a1, lnS, k16 and p2 are scratch tables the
+ * caller allocates and fills once with ssh_cws_prepare. */
 typedef struct {
   int32_t n;          /* token length; tables have 2^n rows */
   int32_t H;          /* hashes per series, >= 1 */
@@ -137,6 +136,10 @@ typedef struct {
   const double* beta; /* [2^n * H] */
   double* a1;         /* [2^n * H] prepared: ln a of a token of weight 1 */
   double* lnS;        /* [SSH_LNS_ENTRIES] prepared: correctly rounded ln s */
+  uint16_t* k16;      /* [(3 * 2^n + 1) * H2], H2 = H rounded up to even:
+                         prepared 16-bit monotone keys of ln a for weights
+                         1, 2, 3, then one padding row */
+  float* p2;          /* [2^n * H] prepared: a float32 lower bound of ln c - r */
 } ssh_cws_tables;
 
 /* Fill tab->a1 and tab->lnS from the draws (device work on `stream`).

@@ -157,7 +157,7 @@ static ssh_status check_tables(const ssh_cws_tables* tab, const char* who) {
   if (!tab) return fail(SSH_EINVAL, std::string(who) + ": null tables");
   if (tab->n < 1 || tab->n > SSH_MAX_N) return fail(SSH_EINVAL, std::string(who) + ": n out of [1, SSH_MAX_N]");
   if (tab->H < 1) return fail(SSH_EINVAL, std::string(who) + ": H < 1");
-  if (!tab->r || !tab->lnc || !tab->beta || !tab->a1 || !tab->lnS)
+  if (!tab->r || !tab->lnc || !tab->beta || !tab->a1 || !tab->lnS || !tab->k16 || !tab->p2)
     return fail(SSH_EINVAL, std::string(who) + ": null table pointer");
   return SSH_OK;
 }
@@ -245,7 +245,8 @@ ssh_status ssh_check_device_errors(void) {
   std::string msg;
   if (a) msg += "ssh_sketch: bit_word_off capacity below ceil(N_B/64); ";
   if (b) msg += "ssh_shingle: hist_off or bit_word_off capacity too small; ";
-  if (c) msg += "ssh_cws_prepare: a draw is outside its range (r > 0, beta in [0,1), finite ln c); ";
+  if (c & 2) msg += "ssh_cws_prepare: a draw is outside its range (0 < r < 1e5, beta in [0,1), finite ln c); ";
+  if (c & 4) msg += "ssh_cws: internal error, a minimum pointed past the token list; ";
   if (d) msg += "dtw_rerank: candidate id outside [0, N) or a length differs from q_len/db_len; ";
   if (!msg.empty()) return fail(SSH_EINVAL, msg);
   return SSH_OK;

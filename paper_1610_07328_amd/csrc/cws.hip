@@ -11,9 +11,21 @@
 // library is compiled without floating-point contraction so no step fuses.
 // ln S comes from a table of correctly rounded logarithms prepared once on
 // the device by a double-double evaluation (and is evaluated the same way on
-// the fly for the rare count beyond the table).  A token of weight 1 has
-// ln S = 0, t = 0 and ln a = (ln c - r * (0 - beta)) - r, which the prepare
-// kernel stores per (k, j) so the common case is one 8-byte load.
+// the fly for the rare count beyond the table).
+//
+// One wavefront hashes one series, each lane two hashes.  The exact argmin is
+// found in two passes whose combination equals the first minimum of the
+// ascending float64 scan, i.e. the lexicographic minimum of (ln a, k):
+//  A. tokens of weight 1, 2 or 3 (almost all of them): the prepare kernel
+//     stores, per (weight, token, hash), a 16-bit key that is a monotone
+//     (non-decreasing) quantisation of the exact ln a.  A strictly smaller key
+//     therefore means a strictly smaller ln a.  Each lane keeps the smallest
+//     and second-smallest (key << 16 | position); position order is token
+//     order, so equal keys resolve to the earlier token.  If the smallest key
+//     is shared by two tokens the lane re-scans its hash exactly (rare).
+//  B. tokens of weight >= 4, in batches: ln a >= (ln c - r) - ln S, so a
+//     float32 lower bound of ln c - r rules most of them out; the rest are
+//     evaluated exactly and compared by (ln a, k) with the pass-A winner.
 #include <cmath>
 
 #include "common.hpp"
@@ -105,72 +117,306 @@ __device__ double ln_integer(double s) {
   return res.hi + res.lo;
 }
 
+// the sampler's exact steps for a token of weight with log ls
+__device__ __forceinline__ double icws_ln_a(double rr, double bb, double lc, double ls, double& tt) {
+  tt = __builtin_floor(ls / rr + bb);
+  const double ln_y = rr * (tt - bb);
+  return (lc - ln_y) - rr;
+}
+
+__device__ __forceinline__ double lnS_of(const double* lnS, uint32_t c) {
+  return c < (uint32_t)SSH_LNS_ENTRIES ? lnS[c] : ln_integer((double)c);
+}
+
 // ---------------------------------------------------------------------------
-// prepare: lnS table and the weight-1 ln a of every (k, j)
+// prepare: lnS table, the weight-1 ln a of every (k, j), 16-bit keys of ln a
+// for weights 1..3, and a float32 lower bound of ln c - r
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void cws_prepare_kernel(const double* __restrict__ r,
-                                                          const double* __restrict__ lnc,
-                                                          const double* __restrict__ beta,
-                                                          int64_t cells, double* __restrict__ a1,
-                                                          double* __restrict__ lnS, int* err) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cells; i += stride) {
-    const double rr = r[i], bb = beta[i], lc = lnc[i];
-    if (!(rr > 0.0) || !(rr < INFINITY) || !(bb >= 0.0) || !(bb < 1.0) || !(__builtin_fabs(lc) < INFINITY))
-      atomicOr(err, 2);
-    const double t = 0.0;  // floor(0 / r + beta) for beta in [0, 1)
-    const double ln_y = rr * (t - bb);
-    a1[i] = (lc - ln_y) - rr;
+__device__ __forceinline__ float f32_round_down(double v) {
+  float f = (float)v;
+  if ((double)f > v) {  // step to the next float32 below f
+    uint32_t b = __builtin_bit_cast(uint32_t, f);
+    if (f > 0.0f) b -= 1u;
+    else if (f < 0.0f) b += 1u;
+    else b = 0x80000001u;  // -smallest subnormal
+    f = __builtin_bit_cast(float, b);
   }
+  return f;
+}
+
+// Monotone non-decreasing 16-bit key of ln a.  For a token of weight S,
+// a ~ Exp(S), so for S <= 3 the range [-16, 4) holds ln a with probability
+// 1 - 1e-6; values outside saturate (they only cost exact tie checks).  Keys
+// stop at 0xFFFE so that no key equals the empty-minimum sentinel.
+constexpr double kKeyLo = -16.0;
+constexpr double kKeyScale = 65534.0 / 20.0;
+
+__device__ __forceinline__ uint32_t key16(double la) {
+  const double q = __builtin_floor((la - kKeyLo) * kKeyScale);  // monotone steps
+  const double c = q < 0.0 ? 0.0 : (q > 65534.0 ? 65534.0 : q);
+  return (uint32_t)c;
+}
+
+__global__ __launch_bounds__(256) void cws_prepare_kernel(
+    const double* __restrict__ r, const double* __restrict__ lnc, const double* __restrict__ beta,
+    int64_t rows, int H, int H2, double* __restrict__ a1, uint16_t* __restrict__ k16,
+    float* __restrict__ p2, double* __restrict__ lnS, int* err) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t cells = rows * H2;
+  // the same correctly rounded values as the lnS table entries 2 and 3
+  const double ln2 = ln_integer(2.0);
+  const double ln3 = ln_integer(3.0);
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < cells; c += stride) {
+    const int64_t k = c / H2;
+    const int j = (int)(c - k * H2);
+    if (j >= H) {  // padding column, never compared
+      k16[c] = 0xFFFF;
+      k16[cells + c] = 0xFFFF;
+      k16[2 * cells + c] = 0xFFFF;
+      continue;
+    }
+    const int64_t i = k * H + j;
+    const double rr = r[i], bb = beta[i], lc = lnc[i];
+    // r is bounded so that the float64 rounding of ln a stays far below the
+    // pass-B slack (a Gamma(2,1) draw above 1e5 has probability ~e^-1e5)
+    if (!(rr > 0.0) || !(rr < 1.0e5) || !(bb >= 0.0) || !(bb < 1.0) || !(__builtin_fabs(lc) < 1.0e300))
+      atomicOr(err, 2);
+    double tt;
+    const double a = icws_ln_a(rr, bb, lc, 0.0, tt);
+    a1[i] = a;
+    k16[c] = (uint16_t)key16(a);
+    k16[cells + c] = (uint16_t)key16(icws_ln_a(rr, bb, lc, ln2, tt));
+    k16[2 * cells + c] = (uint16_t)key16(icws_ln_a(rr, bb, lc, ln3, tt));
+    p2[i] = f32_round_down(lc - rr);
+  }
+  // one extra row of 0xFFFF keys after the three weight tables: padding
+  // entries of a key list point at it and never change a running minimum
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < H2; c += stride)
+    k16[3 * cells + c] = 0xFFFF;
   for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < SSH_LNS_ENTRIES; s += stride)
     lnS[s] = s == 0 ? -INFINITY : ln_integer((double)s);
 }
 
 // ---------------------------------------------------------------------------
-// main: one thread per (series, hash)
+// main
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void cws_kernel(
-    const uint32_t* __restrict__ codes, const uint32_t* __restrict__ counts,
-    const int64_t* __restrict__ hist_off, const int32_t* __restrict__ n_distinct, int64_t N, int H,
-    const double* __restrict__ r, const double* __restrict__ lnc, const double* __restrict__ beta,
-    const double* __restrict__ a1, const double* __restrict__ lnS, uint64_t* __restrict__ hv) {
-  const int64_t total = N * (int64_t)H;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += stride) {
-    const int64_t s = g / H;
-    const int j = (int)(g - s * H);
+struct CwsDev {
+  const double* r;
+  const double* lnc;
+  const double* beta;
+  const double* a1;
+  const double* lnS;
+  const uint16_t* k16;  // [3 * 2^n + 1][H2] keys; the last row is padding
+  const float* p2;
+  int H, H2, n;
+};
+
+constexpr int kCwsWaves = 4;  // wavefronts per workgroup
+constexpr int kPassA = 8;     // keyed tokens whose keys are loaded together
+constexpr uint32_t kNone = 0xFFFFFFFFu;
+
+// median of three; with a <= b it is the second smallest of {a, b, c}
+__device__ __forceinline__ uint32_t med3(uint32_t a, uint32_t b, uint32_t c) {
+  uint32_t m;
+  asm("v_med3_u32 %0, %1, %2, %3" : "=v"(m) : "v"(a), "v"(b), "v"(c));
+  return m;
+}
+
+// A token of weight S >= 4 has ln a = ln c - r (t - beta + 1) with
+// t <= ln S / r + beta, so ln a >= (ln c - r) - ln S.  The float32 table p2
+// holds a value <= ln c - r; the slack covers the float64 rounding of the
+// bound and of ln a itself (r < 1e5).
+__device__ __forceinline__ double heavy_bound(float p2v, double ls) {
+  const double b = (double)p2v - ls;
+  return b - 1.0e-9 * (1.0 + __builtin_fabs(b) + ls);
+}
+
+__device__ __forceinline__ double exact_ln_a(const CwsDev& t, uint32_t k, uint32_t c, int j,
+                                             double& tt) {
+  const int64_t i = (int64_t)k * t.H + j;
+  if (c == 1u) {
+    tt = 0.0;
+    return t.a1[i];
+  }
+  return icws_ln_a(t.r[i], t.beta[i], t.lnc[i], lnS_of(t.lnS, c), tt);
+}
+
+struct Best {
+  double la;  // exact ln a of the minimum (+inf if none)
+  uint32_t k;
+  double t;
+};
+
+__global__ __launch_bounds__(256) void cws_kernel(const uint32_t* __restrict__ codes,
+                                                  const uint32_t* __restrict__ counts,
+                                                  const int64_t* __restrict__ hist_off,
+                                                  const int32_t* __restrict__ n_distinct, int64_t N,
+                                                  CwsDev t, uint64_t* __restrict__ hv, int* err) {
+  // per wave: keyed-token list (row byte offset, position), padded to whole
+  // groups with the padding row, and the heavy-token list (position)
+  __shared__ uint4 klist[kCwsWaves][kWave / 2];
+  __shared__ uint32_t hlist[kCwsWaves][kWave];
+  const int w = threadIdx.x / kWave;
+  const int lane = lane_id();
+  const int H = t.H;
+  const uint32_t row_bytes = (uint32_t)t.H2 * 2u;
+  const uint32_t pad_row = (3u << t.n) * row_bytes;
+  // bounds-checked view of the key table: a lane past H reads inside it
+  const __amdgpu_buffer_rsrc_t ktab = __builtin_amdgcn_make_buffer_rsrc(
+      (void*)t.k16, 0, (int)(pad_row + row_bytes), 0x00020000);
+  uint2* klist2 = reinterpret_cast<uint2*>(klist[w]);
+  const uint64_t lt_mask = (1ull << lane) - 1ull;
+  for (int64_t s = (int64_t)blockIdx.x * kCwsWaves + w; s < N;
+       s += (int64_t)gridDim.x * kCwsWaves) {
     const int D = n_distinct[s];
+    uint64_t* out = hv + s * H;
     if (D <= 0) {
-      hv[g] = SSH_HV_EMPTY;
+      for (int j = lane; j < H; j += kWave) out[j] = SSH_HV_EMPTY;
       continue;
     }
     const int64_t ho = hist_off[s];
-    double best = INFINITY, bt = 0.0;
-    uint32_t bk = 0;
-    for (int d = 0; d < D; ++d) {
-      const uint32_t k = codes[ho + d];
-      const uint32_t c = counts[ho + d];
-      const int64_t idx = (int64_t)k * H + j;
-      double la, t;
-      if (c == 1) {
-        la = a1[idx];
-        t = 0.0;
+    const uint32_t* codes_s = codes + ho;
+    const uint32_t* counts_s = counts + ho;
+    for (int hb0 = 0; hb0 < H; hb0 += 2 * kWave) {
+      const int j0 = hb0 + 2 * lane, j1 = j0 + 1;
+      const bool v0 = j0 < H, v1 = j1 < H;
+      const uint32_t colb = (uint32_t)(v0 ? j0 : 0) * 2u;  // byte offset of the key pair
+      Best b[2] = {Best{INFINITY, 0u, 0.0}, Best{INFINITY, 0u, 0.0}};
+      bool done[2] = {!v0, !v1};
+      bool any_heavy = false;
+      if (D <= 0xFFFF) {
+        // ---- pass A over tokens of weight 1..3 ----
+        uint32_t m1[2] = {kNone, kNone}, m2[2] = {kNone, kNone};
+        for (int d0 = 0; d0 < D; d0 += kWave) {
+          const int nc = D - d0 < kWave ? D - d0 : kWave;
+          const bool have = lane < nc;
+          const uint32_t mcode = have ? codes_s[d0 + lane] : 0u;
+          const uint32_t mcnt = have ? counts_s[d0 + lane] : 0u;
+          const bool keyed = have && mcnt <= 3u;
+          const uint64_t km = ballot64(keyed);
+          any_heavy |= ballot64(have && mcnt > 3u) != 0;
+          const int nk = __builtin_popcountll(km);
+          const int nkp = (nk + kPassA - 1) & ~(kPassA - 1);
+          if (keyed) {
+            const uint32_t row = ((mcnt - 1u) << t.n) + mcode;  // row of the key table
+            klist2[__builtin_popcountll(km & lt_mask)] = make_uint2(row * row_bytes, (uint32_t)(d0 + lane));
+          }
+          // slots nk..nkp-1 are padding (keys 0xFFFF, position 0xFFFF: kNone);
+          // lane i writes slot i whether or not it holds a keyed token itself
+          if (lane >= nk && lane < nkp) klist2[lane] = make_uint2(pad_row, 0xFFFFu);
+          wave_sync_lds();
+          for (int i0 = 0; i0 < nk; i0 += kPassA) {
+            uint32_t wv[kPassA], pv[kPassA];
+#pragma unroll
+            for (int u = 0; u < kPassA; u += 2) {
+              const uint4 e = klist[w][(i0 + u) >> 1];
+              pv[u] = e.y;
+              pv[u + 1] = e.w;
+              wv[u] = __builtin_amdgcn_raw_buffer_load_b32(ktab, (int)(e.x + colb), 0, 0);
+              wv[u + 1] = __builtin_amdgcn_raw_buffer_load_b32(ktab, (int)(e.z + colb), 0, 0);
+            }
+#pragma unroll
+            for (int u = 0; u < kPassA; ++u) {
+              const uint32_t c0 = (wv[u] << 16) | pv[u];
+              const uint32_t c1 = (wv[u] & 0xFFFF0000u) | pv[u];
+              m2[0] = med3(m1[0], m2[0], c0);  // second smallest (m1 <= m2)
+              m1[0] = c0 < m1[0] ? c0 : m1[0];
+              m2[1] = med3(m1[1], m2[1], c1);
+              m1[1] = c1 < m1[1] ? c1 : m1[1];
+            }
+          }
+          wave_sync_lds();
+        }
+        // winner of pass A, unless its key is shared (then: exact re-scan)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          if (done[h] || m1[h] == kNone) continue;
+          if (((m1[h] ^ m2[h]) >> 16) == 0) continue;  // tie: resolved below
+          const uint32_t p = m1[h] & 0xFFFFu;
+          if (p >= (uint32_t)D) {  // cannot happen: every list entry read is a token or padding
+            atomicOr(err, 4);
+            done[h] = true;
+            continue;
+          }
+          b[h].k = codes_s[p];
+          if (any_heavy) b[h].la = exact_ln_a(t, b[h].k, counts_s[p], h ? j1 : j0, b[h].t);
+          else {
+            const uint32_t c = counts_s[p];
+            b[h].la = 0.0;  // not needed: no pass B
+            b[h].t = 0.0;
+            if (c > 1u) {
+              const int64_t i = (int64_t)b[h].k * H + (h ? j1 : j0);
+              b[h].t = __builtin_floor(lnS_of(t.lnS, c) / t.r[i] + t.beta[i]);
+            }
+          }
+          if (!any_heavy) done[h] = true;
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const bool tie = !done[h] && m1[h] != kNone && ((m1[h] ^ m2[h]) >> 16) == 0;
+          if (tie) {
+            // exact scan of every token for this hash, ascending, strict <
+            Best e{INFINITY, 0u, 0.0};
+            for (int d = 0; d < D; ++d) {
+              double tt;
+              const double la = exact_ln_a(t, codes_s[d], counts_s[d], h ? j1 : j0, tt);
+              if (la < e.la) e = Best{la, codes_s[d], tt};
+            }
+            b[h] = e;
+            done[h] = true;
+          }
+        }
+        // ---- pass B over tokens of weight >= 4 ----
+        if (any_heavy) {
+          for (int d0 = 0; d0 < D; d0 += kWave) {
+            const int nc = D - d0 < kWave ? D - d0 : kWave;
+            const bool have = lane < nc;
+            const uint32_t mcnt = have ? counts_s[d0 + lane] : 0u;
+            const bool heavy = have && mcnt > 3u;
+            const uint64_t hm = ballot64(heavy);
+            if (heavy) hlist[w][__builtin_popcountll(hm & lt_mask)] = (uint32_t)(d0 + lane);
+            wave_sync_lds();
+            const int nh = __builtin_popcountll(hm);
+            for (int i = 0; i < nh; ++i) {
+              const uint32_t p = hlist[w][i];
+              const uint32_t k = codes_s[p], c = counts_s[p];
+              const double ls = lnS_of(t.lnS, c);
+              const int64_t row = (int64_t)k * H;
+#pragma unroll
+              for (int h = 0; h < 2; ++h) {
+                if (done[h]) continue;
+                const int j = h ? j1 : j0;
+                if (heavy_bound(t.p2[row + j], ls) < b[h].la) {
+                  double tt;
+                  const double la = icws_ln_a(t.r[row + j], t.beta[row + j], t.lnc[row + j], ls, tt);
+                  if (la < b[h].la || (la == b[h].la && k < b[h].k)) b[h] = Best{la, k, tt};
+                }
+              }
+            }
+            wave_sync_lds();
+          }
+        }
       } else {
-        const double ls = c < (uint32_t)SSH_LNS_ENTRIES ? lnS[c] : ln_integer((double)c);
-        const double rr = r[idx], bb = beta[idx];
-        t = __builtin_floor(ls / rr + bb);
-        const double ln_y = rr * (t - bb);
-        la = (lnc[idx] - ln_y) - rr;
+        // more distinct tokens than 16-bit positions: plain exact scan
+        for (int d = 0; d < D; ++d) {
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            if (done[h]) continue;
+            double tt;
+            const double la = exact_ln_a(t, codes_s[d], counts_s[d], h ? j1 : j0, tt);
+            if (la < b[h].la) b[h] = Best{la, codes_s[d], tt};
+          }
+        }
       }
-      if (la < best) {
-        best = la;
-        bk = k;
-        bt = t;
+      const double tmax = 281474976710655.0;  // 2^48 - 1
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        if (h ? v1 : v0) {
+          const uint64_t tq = (uint64_t)(b[h].t < tmax ? b[h].t : tmax);
+          out[h ? j1 : j0] = (tq << 16) | (uint64_t)b[h].k;
+        }
       }
     }
-    const double tmax = 281474976710655.0;  // 2^48 - 1
-    const uint64_t tt = (uint64_t)(bt < tmax ? bt : tmax);
-    hv[g] = (tt << 16) | (uint64_t)bk;
   }
 }
 
@@ -187,9 +433,10 @@ ssh_status cws_prepare_launch(const ssh_cws_tables* tab, hipStream_t stream) {
   int* err = nullptr;
   if (hipGetSymbolAddress((void**)&err, HIP_SYMBOL(g_cws_err)) != hipSuccess)
     return fail(SSH_EDEVICE, "ssh_cws_prepare: cannot resolve error flag");
-  const int64_t cells = ((int64_t)1 << tab->n) * tab->H;
-  cws_prepare_kernel<<<grid_for(cells, 256, 4096), 256, 0, stream>>>(tab->r, tab->lnc, tab->beta,
-                                                                      cells, tab->a1, tab->lnS, err);
+  const int64_t rows = (int64_t)1 << tab->n;
+  const int H2 = tab->H + (tab->H & 1);
+  cws_prepare_kernel<<<grid_for(rows * H2, 256, 4096), 256, 0, stream>>>(
+      tab->r, tab->lnc, tab->beta, rows, tab->H, H2, tab->a1, tab->k16, tab->p2, tab->lnS, err);
   return check_launch("ssh_cws_prepare");
 }
 
@@ -197,10 +444,17 @@ ssh_status cws_launch(const uint32_t* codes, const uint32_t* counts, const int64
                       const int32_t* n_distinct, int64_t N, const ssh_cws_tables* tab, uint64_t* hv,
                       hipStream_t stream) {
   if (N == 0) return SSH_OK;
-  const int64_t total = N * (int64_t)tab->H;
-  cws_kernel<<<grid_for(total, 256, 1 << 20), 256, 0, stream>>>(
-      codes, counts, hist_off, n_distinct, N, tab->H, tab->r, tab->lnc, tab->beta, tab->a1,
-      tab->lnS, hv);
+  int* err = nullptr;
+  if (hipGetSymbolAddress((void**)&err, HIP_SYMBOL(g_cws_err)) != hipSuccess)
+    return fail(SSH_EDEVICE, "ssh_cws: cannot resolve error flag");
+  const int H2 = tab->H + (tab->H & 1);
+  // the key table is addressed by 32-bit byte offsets through a buffer resource
+  if (((3ll << tab->n) + 1) * H2 * 2 >= (1ll << 31))
+    return fail(SSH_EUNSUPPORTED, "ssh_cws: key table of 2 GiB or more");
+  CwsDev t{tab->r, tab->lnc, tab->beta, tab->a1, tab->lnS,
+           tab->k16, tab->p2, tab->H, H2, tab->n};
+  cws_kernel<<<grid_for(N, kCwsWaves, 1 << 16), 256, 0, stream>>>(codes, counts, hist_off,
+                                                                   n_distinct, N, t, hv, err);
   return check_launch("ssh_cws");
 }
 

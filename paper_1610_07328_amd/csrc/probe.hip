@@ -215,6 +215,7 @@ __global__ __launch_bounds__(kPrThreads) void probe_kernel(ProbeCtx c, const uin
         sel[base + i] = ((uint64_t)(c.H - thr) << 32) | ties[i];
       __syncthreads();
       if (tid == 0) nsel = base + need;
+      __syncthreads();
     } else {
       // radix select of the need-th smallest id of level thr, one byte per pass
       if (tid == 0) prefix = 0;

@@ -96,8 +96,11 @@ __device__ __forceinline__ void repair_round(const FilterArgs& fa, const float* 
   int n = *q.count;
   int cnt = n < kWave ? n : kWave;
   int start = n - cnt;
-  // earlier stores of stream words must reach L2 before the ORs below
-  __threadfence();
+  // This wave's earlier stores of stream words must be complete (in L2)
+  // before the atomic ORs below reach the same words; the stores and the
+  // atomics come from one wave, so a workgroup-scope fence (a wait on the
+  // outstanding stores, no cache maintenance) orders them.
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
   if (lane < cnt) {
     uint32_t s = q.series[start + lane];
     uint32_t wi = q.window[start + lane];

@@ -234,6 +234,32 @@ def test_cws_random_sets_exact(ssh):
         _cws_case(ssh, n, H, sets, seed=n)
 
 
+def test_cws_equal_keys_resolved_exactly(ssh):
+    """Draws whose weight-1 ln a values all fall into one 16-bit key bucket."""
+    _announce("cws equal keys")
+    n, H = 7, 24
+    rng = np.random.default_rng(12)
+    r = 1.0 + rng.random((1 << n, H)) * 1e-6
+    lnc = np.zeros((1 << n, H))
+    beta = np.zeros((1 << n, H))
+    tabs = ssh.CwsTables(r, lnc, beta, n)
+    sets = []
+    for i in range(200):
+        D = int(rng.integers(1, 100))
+        c = np.sort(rng.choice(1 << n, size=D, replace=False)).astype(np.uint32)
+        k = np.where(rng.random(D) < 0.8, 1, rng.integers(2, 6, size=D)).astype(np.uint32)
+        sets.append((c, k))
+    codes = np.concatenate([c for c, _ in sets]).astype(np.uint32)
+    counts = np.concatenate([k for _, k in sets]).astype(np.uint32)
+    ho = np.zeros(len(sets) + 1, np.int64)
+    np.cumsum([len(c) for c, _ in sets], out=ho[1:])
+    nd = np.array([len(c) for c, _ in sets], np.int32)
+    hv = to_np(ssh.cws(to_dev(codes), to_dev(counts), to_dev(ho), to_dev(nd), tabs))
+    lnS = oracle.ln_table(8)
+    for s, (c, k) in enumerate(sets):
+        assert np.array_equal(hv[s], oracle.cws(c, k, r, lnc, beta, lnS)[2]), s
+
+
 def test_cws_counts_beyond_table(ssh):
     _announce("cws counts beyond the ln table")
     rng = np.random.default_rng(4)
