@@ -32,6 +32,16 @@ HBM_PEAK_GBS = 8000.0
 FP64_VALU_TFLOPS = 78.6
 FP32_VALU_TFLOPS = 157.3
 
+# HBM traffic of one launch of a kernel on this workload, from two rocprofv3
+# counter runs of this script (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch),
+# each scaled by the ratio of known bytes to the same counter's reading for a
+# plain device copy (--copy-calibration).  A figure is reported only while the
+# kernel's source file still has the digest it was measured with.
+MEASURED_TRAFFIC = {
+    # kernel: (source file, sha256 of it, FETCH_SIZE KiB, WRITE_SIZE KiB,
+    #          fetch scale, write scale)
+}
+
 
 def band_cells(lq: int, lx: int, r: int) -> int:
     """Cells of an lq x lx DTW matrix inside the band |i - j| <= r."""
@@ -43,6 +53,34 @@ def band_cells(lq: int, lx: int, r: int) -> int:
     return total
 
 
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the recorded counters, or None."""
+    import hashlib
+    rec = MEASURED_TRAFFIC.get(kernel)
+    if rec is None:
+        return None
+    src, digest, fetch_kib, write_kib, fs, ws = rec
+    path = os.path.join(ROOT, src)
+    if not os.path.exists(path):
+        return None
+    with open(path, "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != digest:
+            return None
+    return fetch_kib * 1024.0 * fs + write_kib * 1024.0 * ws
+
+
+def copy_calibration(nbytes: int):
+    """One plain device-to-device copy of nbytes (the counter calibration run)."""
+    import torch
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda:0")
+    b = torch.empty_like(a)
+    a.fill_(1)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes": nbytes}), flush=True)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -52,7 +90,9 @@ def parse():
     ap.add_argument("--length", type=int, default=1024)
     ap.add_argument("--nq", type=int, default=1000)
     ap.add_argument("--latency-samples", type=int, default=200)
-    ap.add_argument("--cpu-sample", type=int, default=8000)
+    ap.add_argument("--cpu-sample", type=int, default=80000)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run one device copy of BYTES bytes (counter calibration)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=0)
     return ap.parse_args()
@@ -61,6 +101,7 @@ def parse():
 def cpu_baseline(X, r, draws, p, Q, sample: int):
     """The CPU oracle on the first `sample` series (and 16 queries) of the workload."""
     import oracle
+    from oracle import _dtw_c
 
     Xs = X[:sample]
     t0 = time.perf_counter()
@@ -93,7 +134,7 @@ def cpu_baseline(X, r, draws, p, Q, sample: int):
                   f"band keys (numpy float64, one thread); DTW re-rank of {nqs} queries x "
                   f"{p.C} candidates in C with OpenMP",
         "dtw_cells_per_s": cells / t_dtw,
-        "dtw_cores": os.cpu_count(),
+        "dtw_cores": _dtw_c.num_threads(),
         "seconds": t_hash + t_dtw,
     }
 
@@ -101,9 +142,12 @@ def cpu_baseline(X, r, draws, p, Q, sample: int):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported by this build "
-              f"(the index shards by series across GPUs, see DESIGN.md).", file=sys.stderr)
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
+              f"(the index would shard by series across GPUs; only one GPU is measured).", file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration > 0:
+        copy_calibration(args.copy_calibration)
+        return
 
     import torch
 
@@ -213,15 +257,16 @@ def main():
         peak = FP32_VALU_TFLOPS / 2  # lane-ops/s = FLOP/s of FMA / 2
         roof = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tops/s",
                 "frac": achieved / peak, "traffic": None, "kernel": "dtw_kernel"}
-    elif dominant == "cws":
-        achieved = bytes_stage["cws"] / (per_stage["cws"] / 1e3) / 1e9
-        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "cws_kernel",
-                "fp64_evals_per_s": cws_evals / (per_stage["cws"] / 1e3)}
     else:
+        kname = {"sketch": "sketch_fast_kernel", "shingle": "shingle_kernel", "cws": "cws_kernel",
+                 "band_keys": "band_keys_kernel", "table_build": "rs_scatter_kernel"}[dominant]
         achieved = bytes_stage[dominant] / (per_stage[dominant] / 1e3) / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": dominant}
+                "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(kname),
+                "kernel": kname, "kernel_ms": per_stage[dominant],
+                "algorithmic_bytes": bytes_stage[dominant]}
+        if dominant == "cws":
+            roof["token_hash_evals_per_s"] = cws_evals / (per_stage["cws"] / 1e3)
 
     # single-query latency with the index resident
     lat = []

@@ -20,6 +20,8 @@ def _load():
         lib.oracle_dtw.restype = ctypes.c_double
         lib.oracle_dtw.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
                                    ctypes.c_int64, ctypes.c_int64]
+        lib.oracle_num_threads.restype = ctypes.c_int32
+        lib.oracle_num_threads.argtypes = []
         lib.oracle_dtw_pairs.restype = None
         lib.oracle_dtw_pairs.argtypes = [ctypes.c_void_p] * 2 + [ctypes.c_int64] + \
             [ctypes.c_void_p] * 4 + [ctypes.c_int64, ctypes.c_float, ctypes.c_void_p]
@@ -51,3 +53,8 @@ def dtw_pairs(q, q_off, db, db_off, cand, ncand, band_frac: float) -> np.ndarray
                              db_off.ctypes.data, cand.ctypes.data, ncand.ctypes.data, C,
                              float(band_frac), out.ctypes.data)
     return out
+
+
+def num_threads() -> int:
+    """Threads the OpenMP pair loop runs on."""
+    return int(_load().oracle_num_threads())

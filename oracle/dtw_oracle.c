@@ -13,6 +13,9 @@
  * -ffp-contract=off, so cost(i,j) = d*d and the sum are separately rounded.
  */
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdint.h>
 #include <stdlib.h>
 
@@ -73,4 +76,13 @@ void oracle_dtw_pairs(const float* q, const int64_t* q_off, int64_t nq, const fl
     int64_t r = (int64_t)floor((double)band_frac * (double)mx);
     dist[p] = oracle_dtw(q + q_off[i], lq, db + db_off[id], lx, r);
   }
+}
+
+/* Number of threads the parallel loop above runs on. */
+int32_t oracle_num_threads(void) {
+#ifdef _OPENMP
+  return (int32_t)omp_get_max_threads();
+#else
+  return 1;
+#endif
 }

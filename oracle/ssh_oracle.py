@@ -12,8 +12,8 @@ Each function follows one passage of the paper (Luo & Shrivastava, "SSH
 * probe    -- Algorithm 2 (Query Process), the retrieved set R;
 * dtw, rerank -- Section 2.1 (DTW) and the last step of Algorithm 2.
 
-Points where the paper is silent or garbled follow the readings listed in
-the design doc; each is restated where it is used.
+Where the paper is silent or garbled, the reading taken is stated in the
+docstring of the function that depends on it.
 """
 from __future__ import annotations
 
