@@ -256,7 +256,7 @@ __global__ __launch_bounds__(256) void cws_kernel(const uint32_t* __restrict__ c
   // groups with the padding row, and the heavy-token list (position)
   __shared__ uint4 klist[kCwsWaves][kWave / 2];
   __shared__ uint32_t hlist[kCwsWaves][kWave];
-  const int w = threadIdx.x / kWave;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave-uniform
   const int lane = lane_id();
   const int H = t.H;
   const uint32_t row_bytes = (uint32_t)t.H2 * 2u;

@@ -1,75 +1,67 @@
 // Weighted set of length-n bit shingles (Section 4.2, eq. "set").
 //
-// One wavefront per series.  The 2^n-token universe is a bitmap in LDS with a
-// one-bit-per-word summary above it:
-//   1. the series' stream words are staged in LDS; every shingle position
-//      sets the bit of its token and the summary bit of that bitmap word
-//      (LDS atomic ORs);
-//   2. a wave prefix sum over the summary lists the occupied bitmap words in
-//      order, and a prefix sum of their popcounts gives each word the rank of
-//      its first token, so the distinct tokens come out in ascending order
-//      without scanning the empty part of the universe;
-//   3. every position adds one to the count of its token's rank (LDS
-//      atomics; global atomics when a series has more distinct tokens than
-//      the LDS count buffer holds);
-//   4. only the words that were set are cleared for the next series.
+// One wavefront per series; lane L takes P consecutive shingle positions
+// (P = ceil(S / 64), at most 33 - n, in rounds when the series is longer).
+// The P + n - 1 stream bits a lane needs sit in one 32-bit window; after a
+// bit reversal, the token at position b0 + k is the n-bit field at offset
+// 32 - n - k, so every token costs one bit-field extract.
+//   1. every lane sets its tokens' bits in a 2^n-bit LDS bitmap (LDS atomic
+//      OR, skipped when a token repeats the lane's previous one);
+//   2. each lane owns 2^n / 2048 consecutive bitmap words: their popcounts,
+//      a wave prefix sum and a running sum give every word the rank of its
+//      first token (16-bit), and the total is the number D of distinct tokens;
+//   3. each token's rank is its word's base plus the popcount of the lower
+//      bits of its word; runs of equal tokens inside a lane are counted once
+//      with their length (LDS atomic add, or a global one when D exceeds the
+//      LDS count buffer), and the token is written at its rank of `codes`,
+//      so tokens come out ascending without sorting;
+//   4. counts are copied out and the bitmap and counts are cleared.
 // A token is the n bits in stream order read most significant first.
 #include "common.hpp"
 
 namespace ssh {
 
-constexpr int kCountCap = 1024;
-constexpr int kWordCap = 64;  // stream words staged in LDS per series
+constexpr int kCountCap = 512;  // distinct tokens whose counts stay in LDS
+constexpr int kShWaves = 4;     // wavefronts per workgroup
 
-struct ShLds {
-  uint32_t* bm;    // bitmap, BW words
-  uint32_t* sm;    // summary, SW words
-  uint32_t* pre;   // rank of the first token of each occupied word
-  uint32_t* cnt;   // counts by rank
-  uint16_t* list;  // occupied bitmap words, ascending
-  uint64_t* wb;    // staged stream words
-};
+__host__ __device__ inline int shingle_bitmap_words(int n) { return n > 5 ? 1 << (n - 5) : 1; }
 
-__device__ __forceinline__ uint32_t token_from(const uint64_t* wb, int p, int n) {
-  const int wi = p >> 6, sh = p & 63;
-  uint64_t v = wb[wi] >> sh;
-  if (sh + n > 64) v |= wb[wi + 1] << (64 - sh);
-  const uint32_t low = (uint32_t)v & (uint32_t)((1ull << n) - 1);
-  return __builtin_bitreverse32(low) >> (32 - n);
+// LDS bytes of one wave: bitmap (u32), rank bases (u16, padded to 16 bytes), counts (u32)
+__host__ __device__ inline size_t shingle_lds_bytes(int n) {
+  const size_t bw = (size_t)shingle_bitmap_words(n);
+  return bw * 4 + ((bw * 2 + 15) & ~(size_t)15) + (size_t)kCountCap * 4;
 }
 
-__host__ __device__ inline size_t shingle_lds_words(int BW, int SW) {
-  // staged words (u64), bitmap, summary, ranks, counts, list (u16), rounded to 8 bytes
-  size_t w = (size_t)2 * kWordCap + BW + SW + BW + kCountCap + (BW + 1) / 2;
-  return (w + 1) & ~(size_t)1;
+// 32 stream bits starting at bit b0 (bit j of the result is stream bit b0 + j;
+// words at or past nw32 read as zero)
+__device__ __forceinline__ uint32_t stream_window(const uint32_t* __restrict__ w32, int nw32,
+                                                  int b0) {
+  const int i = b0 >> 5;
+  const uint32_t lo = i < nw32 ? w32[i] : 0u;
+  const uint32_t hi = i + 1 < nw32 ? w32[i + 1] : 0u;
+  return __builtin_amdgcn_alignbit(hi, lo, (uint32_t)(b0 & 31));
 }
 
-__global__ __launch_bounds__(256) void shingle_kernel(const uint64_t* __restrict__ bits,
-                                                      const int64_t* __restrict__ bit_word_off,
-                                                      const int32_t* __restrict__ nbits, int64_t N,
-                                                      int n, uint32_t* __restrict__ codes,
-                                                      uint32_t* __restrict__ counts,
-                                                      const int64_t* __restrict__ hist_off,
-                                                      int32_t* __restrict__ n_distinct, int* err) {
-  extern __shared__ uint64_t smem64[];
-  const int BW = (1 << n) > 32 ? (1 << n) / 32 : 1;  // bitmap words
-  const int SW = BW > 32 ? BW / 32 : 1;              // summary words
-  const int w = threadIdx.x / kWave;
+template <int WPL>
+__global__ __launch_bounds__(kShWaves * kWave) void shingle_kernel(
+    const uint64_t* __restrict__ bits, const int64_t* __restrict__ bit_word_off,
+    const int32_t* __restrict__ nbits, int64_t N, int n, uint32_t* __restrict__ codes,
+    uint32_t* __restrict__ counts, const int64_t* __restrict__ hist_off,
+    int32_t* __restrict__ n_distinct, int* err) {
+  extern __shared__ uint32_t smem32[];
+  const int BW = shingle_bitmap_words(n);
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave-uniform
   const int lane = lane_id();
-  uint32_t* base = reinterpret_cast<uint32_t*>(smem64) + shingle_lds_words(BW, SW) * w;
-  ShLds L;
-  L.wb = reinterpret_cast<uint64_t*>(base);
-  L.bm = base + 2 * kWordCap;
-  L.sm = L.bm + BW;
-  L.pre = L.sm + SW;
-  L.cnt = L.pre + BW;
-  L.list = reinterpret_cast<uint16_t*>(L.cnt + kCountCap);
-  for (int i = lane; i < BW; i += kWave) L.bm[i] = 0;
-  for (int i = lane; i < SW; i += kWave) L.sm[i] = 0;
+  uint32_t* bm = smem32 + (shingle_lds_bytes(n) / 4) * w;
+  uint16_t* pre = reinterpret_cast<uint16_t*>(bm + BW);
+  uint32_t* cnt = bm + BW + ((BW * 2 + 15) & ~15) / 4;
+  for (int i = lane; i < BW; i += kWave) bm[i] = 0;
+  for (int i = lane; i < kCountCap; i += kWave) cnt[i] = 0;
   wave_sync_lds();
+  const uint32_t mask = (1u << n) - 1u;  // n <= 16
+  const int w0 = lane * WPL;             // first bitmap word of this lane
 
-  const int wpb = blockDim.x / kWave;
-  for (int64_t s = (int64_t)blockIdx.x * wpb + w; s < N; s += (int64_t)gridDim.x * wpb) {
+  for (int64_t s = (int64_t)blockIdx.x * kShWaves + w; s < N; s += (int64_t)gridDim.x * kShWaves) {
     const int nb = nbits[s];
     const int S = nb >= n ? nb - n + 1 : 0;
     const int64_t ho = hist_off[s];
@@ -86,78 +78,92 @@ __global__ __launch_bounds__(256) void shingle_kernel(const uint64_t* __restrict
       }
       continue;
     }
-    const uint64_t* wb = bits + wo;
-    if (nw <= kWordCap) {
-      if (lane < nw) L.wb[lane] = wb[lane];
-      wave_sync_lds();
-      wb = L.wb;
-    }
-    // 1. mark tokens and their bitmap words
-    for (int p = lane; p < S; p += kWave) {
-      const uint32_t t = token_from(wb, p, n);
-      const uint32_t word = t >> 5;
-      atomicOr(L.bm + word, 1u << (t & 31));
-      atomicOr(L.sm + (word >> 5), 1u << (word & 31));
+    const uint32_t* w32 = reinterpret_cast<const uint32_t*>(bits + wo);
+    const int nw32 = 2 * nw;
+    int P = (S + kWave - 1) / kWave;
+    if (P > 33 - n) P = 33 - n;
+    const int per_round = kWave * P;
+
+    // 1. mark the tokens
+    for (int base = 0; base < S; base += per_round) {
+      const int b0 = base + lane * P;
+      if (b0 < S) {
+        const uint32_t rev = __builtin_bitreverse32(stream_window(w32, nw32, b0));
+        const int kend = S - b0 < P ? S - b0 : P;
+        uint32_t prev = 0xFFFFFFFFu;
+        for (int k = 0; k < kend; ++k) {
+          const uint32_t t = (rev >> (32 - n - k)) & mask;
+          if (t != prev) atomicOr(bm + (t >> 5), 1u << (t & 31));
+          prev = t;
+        }
+      }
     }
     wave_sync_lds();
-    // 2. occupied words in ascending order, then token ranks
-    uint32_t nz = 0;
-    for (int bi = 0; bi < SW; bi += kWave) {
-      const int i = bi + lane;
-      const uint32_t smw = i < SW ? L.sm[i] : 0u;
-      const uint32_t c = __builtin_popcount(smw);
-      const uint32_t incl = wave_incl_scan(c);
-      uint32_t pos = nz + incl - c;
-      uint32_t b = smw;
-      while (b) {
-        const int tb = __builtin_ctz(b);
-        L.list[pos++] = (uint16_t)(i * 32 + tb);
-        b &= b - 1;
-      }
-      nz += wave_bcast(incl, kWave - 1);
+
+    // 2. rank of the first token of every bitmap word, and D
+    uint32_t wv[WPL];
+    uint32_t c = 0;
+#pragma unroll
+    for (int j = 0; j < WPL; ++j) {
+      wv[j] = w0 + j < BW ? bm[w0 + j] : 0u;
+      c += __builtin_popcount(wv[j]);
     }
-    wave_sync_lds();
-    uint32_t D = 0;
-    for (uint32_t bi = 0; bi < nz; bi += kWave) {
-      const uint32_t i = bi + lane;
-      const uint32_t word = i < nz ? L.list[i] : 0u;
-      const uint32_t b0 = i < nz ? L.bm[word] : 0u;
-      const uint32_t c = __builtin_popcount(b0);
-      const uint32_t incl = wave_incl_scan(c);
-      uint32_t rk = D + incl - c;
-      if (i < nz) L.pre[word] = rk;
-      uint32_t b = b0;
-      while (b) {
-        const int tb = __builtin_ctz(b);
-        codes[ho + rk] = word * 32u + (uint32_t)tb;
-        ++rk;
-        b &= b - 1;
-      }
-      D += wave_bcast(incl, kWave - 1);
+    const uint32_t incl = wave_incl_scan(c);
+    uint32_t rk = incl - c;
+#pragma unroll
+    for (int j = 0; j < WPL; ++j) {
+      if (w0 + j < BW) pre[w0 + j] = (uint16_t)rk;
+      rk += __builtin_popcount(wv[j]);
     }
-    // 3. counts by rank
+    const uint32_t D = wave_bcast(incl, kWave - 1);
     const bool in_lds = D <= (uint32_t)kCountCap;
-    if (in_lds) {
-      for (uint32_t i = lane; i < D; i += kWave) L.cnt[i] = 0;
-    } else {
+    if (!in_lds) {
       for (uint32_t i = lane; i < D; i += kWave) counts[ho + i] = 0;
       // this wave's zero stores complete before its atomics below
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     }
     wave_sync_lds();
-    for (int p = lane; p < S; p += kWave) {
-      const uint32_t t = token_from(wb, p, n);
-      const uint32_t word = t >> 5, b = t & 31;
-      const uint32_t rank = L.pre[word] + __builtin_popcount(L.bm[word] & ((1u << b) - 1u));
-      if (in_lds) atomicAdd(L.cnt + rank, 1u);
-      else atomicAdd(counts + ho + rank, 1u);
+
+    // 3. counts by rank (runs of equal tokens in a lane counted at once), codes at their ranks
+    auto flush = [&](uint32_t t, uint32_t run) {
+      const uint32_t word = t >> 5;
+      const uint32_t rank = (uint32_t)pre[word] + __builtin_popcount(bm[word] & ((1u << (t & 31)) - 1u));
+      if (in_lds) atomicAdd(cnt + rank, run);
+      else atomicAdd(counts + ho + rank, run);
+      codes[ho + rank] = t;
+    };
+    for (int base = 0; base < S; base += per_round) {
+      const int b0 = base + lane * P;
+      if (b0 < S) {
+        const uint32_t rev = __builtin_bitreverse32(stream_window(w32, nw32, b0));
+        const int kend = S - b0 < P ? S - b0 : P;
+        uint32_t prev = (rev >> (32 - n)) & mask;
+        uint32_t run = 1;
+        for (int k = 1; k < kend; ++k) {
+          const uint32_t t = (rev >> (32 - n - k)) & mask;
+          if (t == prev) {
+            ++run;
+            continue;
+          }
+          flush(prev, run);
+          prev = t;
+          run = 1;
+        }
+        flush(prev, run);
+      }
     }
     wave_sync_lds();
-    if (in_lds)
-      for (uint32_t i = lane; i < D; i += kWave) counts[ho + i] = L.cnt[i];
-    // 4. clear what was set
-    for (uint32_t i = lane; i < nz; i += kWave) L.bm[L.list[i]] = 0;
-    for (int i = lane; i < SW; i += kWave) L.sm[i] = 0;
+
+    // 4. counts out; clear the bitmap words and counts that were used
+    if (in_lds) {
+      for (uint32_t i = lane; i < D; i += kWave) {
+        counts[ho + i] = cnt[i];
+        cnt[i] = 0;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < WPL; ++j)
+      if (w0 + j < BW && wv[j]) bm[w0 + j] = 0;
     wave_sync_lds();
     if (lane == 0) n_distinct[s] = (int32_t)D;
   }
@@ -179,12 +185,27 @@ ssh_status shingle_launch(const uint64_t* bits, const int64_t* bit_word_off, con
   int* err = nullptr;
   if (hipGetSymbolAddress((void**)&err, HIP_SYMBOL(g_shingle_err)) != hipSuccess)
     return fail(SSH_EDEVICE, "ssh_shingle: cannot resolve error flag");
-  const int BW = (1 << n) > 32 ? (1 << n) / 32 : 1;
-  const int SW = BW > 32 ? BW / 32 : 1;
-  const int wpb = n >= 16 ? 2 : 4;  // keep a block's LDS within 64 KiB
-  const size_t shm = (size_t)wpb * shingle_lds_words(BW, SW) * sizeof(uint32_t);
-  shingle_kernel<<<grid_for(N, wpb, 1 << 16), wpb * kWave, shm, stream>>>(
-      bits, bit_word_off, nbits, N, n, codes, counts, hist_off, n_distinct, err);
+  const int BW = shingle_bitmap_words(n);
+  const int wpl = BW >= kWave ? BW / kWave : 1;
+  const size_t shm = (size_t)kShWaves * shingle_lds_bytes(n);
+  const unsigned grid = grid_for(N, kShWaves, 1 << 16);
+  const dim3 block(kShWaves * kWave);
+#define SSH_SHINGLE_CASE(V)                                                                     \
+  case V:                                                                                       \
+    shingle_kernel<V><<<grid, block, shm, stream>>>(bits, bit_word_off, nbits, N, n, codes,      \
+                                                    counts, hist_off, n_distinct, err);          \
+    break;
+  switch (wpl) {
+    SSH_SHINGLE_CASE(1)
+    SSH_SHINGLE_CASE(2)
+    SSH_SHINGLE_CASE(4)
+    SSH_SHINGLE_CASE(8)
+    SSH_SHINGLE_CASE(16)
+    SSH_SHINGLE_CASE(32)
+    default:
+      return fail(SSH_EUNSUPPORTED, "ssh_shingle: n outside [1, 16]");
+  }
+#undef SSH_SHINGLE_CASE
   return check_launch("ssh_shingle");
 }
 

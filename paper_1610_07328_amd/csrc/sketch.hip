@@ -146,91 +146,212 @@ constexpr int kWavesPerBlock = 4;
 // ---------------------------------------------------------------------------
 // fast path: compile-time W, delta and R windows per lane
 // ---------------------------------------------------------------------------
+// A work item is one chunk of SUB = 64 R windows of one series.  The chunk's
+// samples are staged in LDS as fp16 pairs, converted once: ev[p] holds
+// (x[2p], x[2p+1]) and od[p] holds (x[2p-1], x[2p]) (chunk-relative indices),
+// so a lane whose span starts at an even sample reads ev and one starting at
+// an odd sample reads od.  While a chunk is computed, the samples of the
+// wave's next chunk are already being loaded into registers.
+struct ChunkItem {
+  int64_t s;     // series (>= N: no item)
+  int c;         // chunk of the series
+  int nb;        // bits of the series
+  int64_t base;  // first sample
+  int64_t m;     // samples of the series
+  int64_t wo;    // first stream word
+};
+
+__device__ __forceinline__ int64_t uniform64(int64_t v) {
+  const uint64_t u = (uint64_t)v;
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)u);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(u >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// Header of series s (nb = 0 when the stream capacity is too small), and the
+// series' bit count recorded.  Everything here is wave-uniform: every lane
+// stores the same value (no lane-dependent branch, so the header stays in
+// scalar registers).
+template <int W, int D>
+__device__ __forceinline__ ChunkItem series_item(int64_t s, const int64_t* __restrict__ x_off,
+                                                 const int64_t* __restrict__ bit_word_off,
+                                                 int32_t* __restrict__ nbits_out, int* err) {
+  ChunkItem it;
+  it.s = uniform64(s);
+  it.c = 0;
+  it.base = uniform64(x_off[it.s]);
+  it.m = uniform64(x_off[it.s + 1]) - it.base;
+  int nb = it.m >= W ? (int)((it.m - W) / D + 1) : 0;
+  it.wo = uniform64(bit_word_off[it.s]);
+  if (uniform64(bit_word_off[it.s + 1]) - it.wo < (nb + 63) / 64) {
+    atomicOr(err, 1);
+    nb = 0;
+  }
+  nbits_out[it.s] = nb;
+  it.nb = nb;
+  return it;
+}
+
+// The item after `it` for a wave striding over series by `stride`: the next
+// chunk of the same series, else the first chunk of the next series that has
+// at least one bit.
+template <int W, int D, int SUB>
+__device__ __forceinline__ ChunkItem next_item(ChunkItem it, int64_t N, int64_t stride,
+                                               const int64_t* __restrict__ x_off,
+                                               const int64_t* __restrict__ bit_word_off,
+                                               int32_t* __restrict__ nbits_out, int* err) {
+  if ((it.c + 1) * SUB < it.nb) {
+    ++it.c;
+    return it;
+  }
+  for (int64_t s = it.s + stride; s < N; s += stride) {
+    ChunkItem n = series_item<W, D>(s, x_off, bit_word_off, nbits_out, err);
+    if (n.nb > 0) return n;
+  }
+  it.s = N;
+  return it;
+}
+
+// Samples 2p and 2p+1 (p = lane + 64 i) of a chunk starting at sample sb;
+// samples past the series read as zero.  Every load is issued (its index
+// clamped to the series' last sample, m >= W >= 1 for an item) so that the
+// loads stay in flight without branches; the zeroing happens on use.
+template <int PF>
+__device__ __forceinline__ void load_chunk(const float* __restrict__ x, const ChunkItem& it,
+                                           int64_t sb, float (&pa)[PF], float (&pb)[PF]) {
+  const int lane = lane_id();
+  const float* xs = x + it.base;
+  const int64_t last = it.m - 1;
+#pragma unroll
+  for (int i = 0; i < PF; ++i) {
+    const int64_t j = sb + 2 * (lane + kWave * i);
+    pa[i] = xs[j < last ? j : last];
+    pb[i] = xs[j + 1 < last ? j + 1 : last];
+  }
+}
+
+// Zero the prefetched samples that lie past the series (see load_chunk).
+template <int PF>
+__device__ __forceinline__ void mask_chunk(const ChunkItem& it, int64_t sb, float (&pa)[PF],
+                                           float (&pb)[PF]) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int i = 0; i < PF; ++i) {
+    const int64_t j = sb + 2 * (lane + kWave * i);
+    if (!(j < it.m)) pa[i] = 0.0f;
+    if (!(j + 1 < it.m)) pb[i] = 0.0f;
+  }
+}
+
 template <int W, int D, int R>
 __global__ __launch_bounds__(256) void sketch_fast_kernel(
     const float* __restrict__ x, const int64_t* __restrict__ x_off, int64_t N, FilterArgs fa,
     uint64_t* __restrict__ bits, const int64_t* __restrict__ bit_word_off,
     int32_t* __restrict__ nbits_out, unsigned long long* repair_count, int* err) {
   constexpr int SUB = kWave * R;          // windows per chunk
-  constexpr int XCAP = (SUB - 1) * D + W; // samples a chunk touches
+  constexpr int XCAP = (SUB - 1) * D + W; // samples a chunk's windows touch
   constexpr int SPAN = D * (R - 1) + W;   // samples of one lane's R windows
   constexpr int NP = (SPAN + 1) / 2;      // fp16 pairs a lane holds
   constexpr int PE = (W + 1) / 2;         // pairs of an even-aligned window
   constexpr int PO = W / 2 + 1;           // pairs of an odd-aligned window
+  constexpr int NPAIR = XCAP / 2 + 2;     // pairs per copy (sample XCAP included)
+  constexpr int PF = (NPAIR + kWave - 1) / kWave;
   constexpr int QCAP = SUB + kWave;
   static_assert(R <= 32, "R bits per lane must fit a word");
 
-  __shared__ float xs[kWavesPerBlock][XCAP + 4];
+  __shared__ uint32_t ev[kWavesPerBlock][PF * kWave];
+  __shared__ uint32_t od[kWavesPerBlock][PF * kWave];
   __shared__ uint32_t qser[kWavesPerBlock][QCAP];
   __shared__ uint32_t qwin[kWavesPerBlock][QCAP];
   __shared__ uint32_t bw[kWavesPerBlock][2 * R];
   __shared__ int qn[kWavesPerBlock];
 
-  const int w = threadIdx.x / kWave;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave-uniform
   const int lane = lane_id();
-  float* X = xs[w];
   RepairQueue q{qser[w], qwin[w], &qn[w]};
   uint32_t* bits32 = reinterpret_cast<uint32_t*>(bits);
   if (lane == 0) qn[w] = 0;
   wave_sync_lds();
 
-  for (int64_t s = (int64_t)blockIdx.x * kWavesPerBlock + w; s < N;
-       s += (int64_t)gridDim.x * kWavesPerBlock) {
-    const int64_t base = x_off[s];
-    const int64_t m = x_off[s + 1] - base;
-    int nb = m >= W ? (int)((m - W) / D + 1) : 0;
-    const int64_t wo = bit_word_off[s];
-    if (bit_word_off[s + 1] - wo < (nb + 63) / 64) {
-      if (lane == 0) atomicOr(err, 1);
-      nb = 0;
+  const int64_t stride = (int64_t)gridDim.x * kWavesPerBlock;
+  const int64_t s0 = (int64_t)blockIdx.x * kWavesPerBlock + w;
+  ChunkItem cur;
+  cur.s = N;
+  if (s0 < N) {
+    cur = series_item<W, D>(s0, x_off, bit_word_off, nbits_out, err);
+    if (cur.nb == 0) cur = next_item<W, D, SUB>(cur, N, stride, x_off, bit_word_off, nbits_out, err);
+  }
+  float pa[PF], pb[PF];
+  if (cur.s < N) load_chunk<PF>(x, cur, (int64_t)cur.c * SUB * D, pa, pb);
+
+  while (cur.s < N) {
+    // stage the chunk as fp16 pairs; flag it when a sample it uses could
+    // overflow the fp16 products or is not finite
+    mask_chunk<PF>(cur, (int64_t)cur.c * SUB * D, pa, pb);
+    bool bad = false;
+#pragma unroll
+    for (int i = 0; i < PF; ++i) {
+      const int p = lane + kWave * i;
+      // x[2p-1]: the lane before's x[2p+1]; for lane 0, lane 63's of the previous pair
+      // row (both shuffles run on the whole wave before the select)
+      const float up = __shfl_up(pb[i], 1, kWave);
+      const float last = i == 0 ? 0.0f : __shfl(pb[i == 0 ? 0 : i - 1], kWave - 1, kWave);
+      const float prev = lane == 0 ? last : up;
+      ev[w][p] = __builtin_bit_cast(uint32_t, pack_h2(pa[i], pb[i]));
+      od[w][p] = __builtin_bit_cast(uint32_t, pack_h2(prev, pa[i]));
+      bad |= (2 * p <= XCAP && !(__builtin_fabsf(pa[i]) < 16384.0f)) ||
+             (2 * p + 1 <= XCAP && !(__builtin_fabsf(pb[i]) < 16384.0f));
     }
-    if (lane == 0) nbits_out[s] = nb;
-    const int nwords = (nb + 63) / 64;
+    const bool unsafe = ballot64(bad) != 0;
+    if (lane < 2 * R) bw[w][lane] = 0;
+    wave_sync_lds();
 
-    for (int c = 0; c * SUB < nb; ++c) {
-      const bool unsafe = stage_chunk(X, XCAP + 1, x, base, m, (int64_t)c * SUB * D);
-      if (lane < 2 * R) bw[w][lane] = 0;
-      wave_sync_lds();
+    // start loading the next chunk; it is consumed at the top of the next iteration
+    const ChunkItem nxt = next_item<W, D, SUB>(cur, N, stride, x_off, bit_word_off, nbits_out, err);
+    if (nxt.s < N) load_chunk<PF>(x, nxt, (int64_t)nxt.c * SUB * D, pa, pb);
 
-      const int wl = lane * R;
-      const int nvalid = nb - c * SUB - wl;
-      if (nvalid > 0) {
-        const float* P = X + wl * D;
-        h2 pr[NP];
+    const int nb = cur.nb;
+    const int c = cur.c;
+    const int wl = lane * R;
+    const int nvalid = nb - c * SUB - wl;
+    if (nvalid > 0) {
+      const int a = wl * D;  // first sample of the lane's span
+      const uint32_t* src = (a & 1) ? od[w] + (a + 1) / 2 : ev[w] + a / 2;
+      h2 pr[NP];
 #pragma unroll
-        for (int p = 0; p < NP; ++p) pr[p] = pack_h2(P[2 * p], P[2 * p + 1]);
-        float E = 0.0f;
+      for (int p = 0; p < NP; ++p) pr[p] = as_h2(src[p]);
+      float E = 0.0f;
 #pragma unroll
-        for (int p = 0; p < NP; ++p) E = fdot2(pr[p], pr[p], E);
-        const float M = window_margin(fa, E, 2 * NP);
-        uint32_t mybits = 0, myflags = 0;
+      for (int p = 0; p < NP; ++p) E = fdot2(pr[p], pr[p], E);
+      const float M = window_margin(fa, E, 2 * NP);
+      uint32_t mybits = 0, myflags = 0;
 #pragma unroll
-        for (int rho = 0; rho < R; ++rho) {
-          float acc = 0.0f;
-          if (((D * rho) & 1) == 0) {
+      for (int rho = 0; rho < R; ++rho) {
+        float acc = 0.0f;
+        if (((D * rho) & 1) == 0) {
 #pragma unroll
-            for (int p = 0; p < PE; ++p) acc = fdot2(pr[(D * rho) / 2 + p], as_h2(fa.even[p]), acc);
-          } else {
+          for (int p = 0; p < PE; ++p) acc = fdot2(pr[(D * rho) / 2 + p], as_h2(fa.even[p]), acc);
+        } else {
 #pragma unroll
-            for (int p = 0; p < PO; ++p)
-              acc = fdot2(pr[(D * rho - 1) / 2 + p], as_h2(fa.odd[p]), acc);
-          }
-          if (rho < nvalid) {
-            const bool flag = unsafe || !(__builtin_fabsf(acc) >= M);
-            if (flag) myflags |= 1u << rho;
-            else if (acc >= 0.0f) mybits |= 1u << rho;
-          }
+          for (int p = 0; p < PO; ++p) acc = fdot2(pr[(D * rho - 1) / 2 + p], as_h2(fa.odd[p]), acc);
         }
-        or_bits<R>(bw[w], wl, mybits);
-        push_flags<R>(q, myflags, (uint32_t)s, (uint32_t)(c * SUB + wl));
+        if (rho < nvalid) {
+          const bool flag = unsafe || !(__builtin_fabsf(acc) >= M);
+          if (flag) myflags |= 1u << rho;
+          else if (acc >= 0.0f) mybits |= 1u << rho;
+        }
       }
-      wave_sync_lds();
-      if (lane < 2 * R) {
-        const int64_t wd = (int64_t)c * R + (lane >> 1);
-        if (wd < nwords) bits32[2 * (wo + wd) + (lane & 1)] = bw[w][lane];
-      }
-      while (qn[w] >= kWave) repair_round(fa, x, x_off, bits32, bit_word_off, q, repair_count);
+      or_bits<R>(bw[w], wl, mybits);
+      push_flags<R>(q, myflags, (uint32_t)cur.s, (uint32_t)(c * SUB + wl));
     }
+    wave_sync_lds();
+    const int nwords = (nb + 63) / 64;
+    if (lane < 2 * R) {
+      const int64_t wd = (int64_t)c * R + (lane >> 1);
+      if (wd < nwords) bits32[2 * (cur.wo + wd) + (lane & 1)] = bw[w][lane];
+    }
+    while (qn[w] >= kWave) repair_round(fa, x, x_off, bits32, bit_word_off, q, repair_count);
+    cur = nxt;
   }
   while (qn[w] > 0) repair_round(fa, x, x_off, bits32, bit_word_off, q, repair_count);
 }
@@ -246,7 +367,7 @@ __global__ __launch_bounds__(256) void sketch_generic_kernel(
   const int W = fa.W, D = fa.delta;
   const int XCAP = (kWave - 1) * D + W + 2;
   constexpr int QCAP = 2 * kWave;
-  const int w = threadIdx.x / kWave;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave-uniform
   const int lane = lane_id();
   // per wave: XCAP floats, 2*QCAP queue words, 2 stream words, 1 counter
   const size_t per_wave = (size_t)XCAP * 4 + 2 * QCAP * 4 + 2 * 4 + 4;
