@@ -5,7 +5,9 @@
 // Fast path: one wavefront per series chunk; each lane owns R consecutive
 // windows and keeps the union of their samples in registers as packed fp16
 // pairs, so every loaded sample feeds several windows.  Products are fp16 x
-// fp16 (exact in fp32) accumulated in fp32 by v_dot2_f32_f16.
+// fp16 (exact in fp32) accumulated in fp32 by v_dot2_f32_f16.  The fp16
+// filter pairs sit in LDS and are read at their point of use.  The grid is capped at 2048 workgroups, so each wavefront walks
+// many series and its repair queue drains in full rounds.
 //
 // Exactness: the reference bit is the sign of the float64 sum of the exact
 // float32 products in ascending filter index.  The fast-path sum s16 differs
@@ -20,8 +22,9 @@
 // of a chunk holding a sample with |x| >= 2^14 or a non-finite one) is queued
 // and recomputed exactly like the reference, one window per lane, in float64.
 // Queued windows are drained in rounds of 64 so a round keeps the whole wave
-// busy; a repaired 1 is OR-ed into the stored stream (the fast path stores 0
-// for every queued window).
+// busy (each lane loads its window's samples 16 at a time); a repaired 1 is
+// OR-ed into the stored stream (the fast path stores 0 for every queued
+// window).
 #include <cmath>
 #include <cstring>
 
@@ -106,7 +109,17 @@ __device__ __forceinline__ void repair_round(const FilterArgs& fa, const float* 
     uint32_t wi = q.window[start + lane];
     const float* xw = x + x_off[s] + (int64_t)wi * fa.delta;
     double acc = 0.0;
-    for (int k = 0; k < fa.W; ++k) acc = __builtin_fma((double)fa.r[k], (double)xw[k], acc);
+    // loads in groups of 16 (one wait per group), products in ascending order
+    int k = 0;
+#pragma clang loop unroll(disable)
+    for (; k + 16 <= fa.W; k += 16) {
+      float xv[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) xv[u] = xw[k + u];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) acc = __builtin_fma((double)fa.r[k + u], (double)xv[u], acc);
+    }
+    for (; k < fa.W; ++k) acc = __builtin_fma((double)fa.r[k], (double)xw[k], acc);
     if (acc >= 0.0) {
       int64_t word = bit_word_off[s] + (wi >> 6);
       atomicOr(bits32 + 2 * word + ((wi >> 5) & 1), 1u << (wi & 31));
@@ -212,34 +225,26 @@ __device__ __forceinline__ ChunkItem next_item(ChunkItem it, int64_t N, int64_t 
   return it;
 }
 
-// Samples 2p and 2p+1 (p = lane + 64 i) of a chunk starting at sample sb;
-// samples past the series read as zero.  Every load is issued (its index
-// clamped to the series' last sample, m >= W >= 1 for an item) so that the
-// loads stay in flight without branches; the zeroing happens on use.
+// Samples 2p and 2p+1 (p = lane + 64 i) of a chunk starting at sample sb,
+// read through a buffer resource whose range ends at the series' last sample
+// (or past what the chunk needs), so samples past the series read as zero
+// without any per-load bounds arithmetic.
 template <int PF>
 __device__ __forceinline__ void load_chunk(const float* __restrict__ x, const ChunkItem& it,
                                            int64_t sb, float (&pa)[PF], float (&pb)[PF]) {
   const int lane = lane_id();
-  const float* xs = x + it.base;
-  const int64_t last = it.m - 1;
+  const int64_t rem = it.m - sb;  // > 0 for an item's chunk
+  const int64_t need = 2 * kWave * PF;
+  const int nrec = (int)((rem < need ? rem : need) * 4);
+  const __amdgpu_buffer_rsrc_t rs =
+      __builtin_amdgcn_make_buffer_rsrc((void*)(x + it.base + sb), 0, nrec, 0x00020000);
+  const int voff = 8 * lane;
 #pragma unroll
   for (int i = 0; i < PF; ++i) {
-    const int64_t j = sb + 2 * (lane + kWave * i);
-    pa[i] = xs[j < last ? j : last];
-    pb[i] = xs[j + 1 < last ? j + 1 : last];
-  }
-}
-
-// Zero the prefetched samples that lie past the series (see load_chunk).
-template <int PF>
-__device__ __forceinline__ void mask_chunk(const ChunkItem& it, int64_t sb, float (&pa)[PF],
-                                           float (&pb)[PF]) {
-  const int lane = lane_id();
-#pragma unroll
-  for (int i = 0; i < PF; ++i) {
-    const int64_t j = sb + 2 * (lane + kWave * i);
-    if (!(j < it.m)) pa[i] = 0.0f;
-    if (!(j + 1 < it.m)) pb[i] = 0.0f;
+    // per-lane offset in a register, the row offset as a scalar offset
+    const int soff = 2 * kWave * i * 4;
+    pa[i] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, voff, soff, 0));
+    pb[i] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, voff + 4, soff, 0));
   }
 }
 
@@ -265,13 +270,19 @@ __global__ __launch_bounds__(256) void sketch_fast_kernel(
   __shared__ uint32_t qwin[kWavesPerBlock][QCAP];
   __shared__ uint32_t bw[kWavesPerBlock][2 * R];
   __shared__ int qn[kWavesPerBlock];
+  // fp16 filter pairs (even[p], odd[p]) side by side: read with a uniform
+  // address at the point of use rather than held in scalar registers across
+  // the whole loop
+  __shared__ uint2 filt[(PE > PO ? PE : PO)];
 
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave-uniform
   const int lane = lane_id();
   RepairQueue q{qser[w], qwin[w], &qn[w]};
   uint32_t* bits32 = reinterpret_cast<uint32_t*>(bits);
+  for (int p = threadIdx.x; p < (PE > PO ? PE : PO); p += blockDim.x)
+    filt[p] = make_uint2(fa.even[p], fa.odd[p]);
   if (lane == 0) qn[w] = 0;
-  wave_sync_lds();
+  __syncthreads();
 
   const int64_t stride = (int64_t)gridDim.x * kWavesPerBlock;
   const int64_t s0 = (int64_t)blockIdx.x * kWavesPerBlock + w;
@@ -287,7 +298,6 @@ __global__ __launch_bounds__(256) void sketch_fast_kernel(
   while (cur.s < N) {
     // stage the chunk as fp16 pairs; flag it when a sample it uses could
     // overflow the fp16 products or is not finite
-    mask_chunk<PF>(cur, (int64_t)cur.c * SUB * D, pa, pb);
     bool bad = false;
 #pragma unroll
     for (int i = 0; i < PF; ++i) {
@@ -324,21 +334,29 @@ __global__ __launch_bounds__(256) void sketch_fast_kernel(
 #pragma unroll
       for (int p = 0; p < NP; ++p) E = fdot2(pr[p], pr[p], E);
       const float M = window_margin(fa, E, 2 * NP);
+      float acc[R];
+#pragma unroll
+      for (int rho = 0; rho < R; ++rho) acc[rho] = 0.0f;
+#pragma unroll
+      for (int p = 0; p < (PE > PO ? PE : PO); ++p) {
+        const uint2 f = filt[p];
+#pragma unroll
+        for (int rho = 0; rho < R; ++rho) {
+          if (((D * rho) & 1) == 0) {
+            if (p < PE) acc[rho] = fdot2(pr[(D * rho) / 2 + p], as_h2(f.x), acc[rho]);
+          } else {
+            if (p < PO) acc[rho] = fdot2(pr[(D * rho - 1) / 2 + p], as_h2(f.y), acc[rho]);
+          }
+        }
+        if ((p & 7) == 7) asm volatile("" ::: "memory");
+      }
       uint32_t mybits = 0, myflags = 0;
 #pragma unroll
       for (int rho = 0; rho < R; ++rho) {
-        float acc = 0.0f;
-        if (((D * rho) & 1) == 0) {
-#pragma unroll
-          for (int p = 0; p < PE; ++p) acc = fdot2(pr[(D * rho) / 2 + p], as_h2(fa.even[p]), acc);
-        } else {
-#pragma unroll
-          for (int p = 0; p < PO; ++p) acc = fdot2(pr[(D * rho - 1) / 2 + p], as_h2(fa.odd[p]), acc);
-        }
         if (rho < nvalid) {
-          const bool flag = unsafe || !(__builtin_fabsf(acc) >= M);
+          const bool flag = unsafe || !(__builtin_fabsf(acc[rho]) >= M);
           if (flag) myflags |= 1u << rho;
-          else if (acc >= 0.0f) mybits |= 1u << rho;
+          else if (acc[rho] >= 0.0f) mybits |= 1u << rho;
         }
       }
       or_bits<R>(bw[w], wl, mybits);
@@ -487,10 +505,11 @@ ssh_status sketch_launch(const float* x, const int64_t* x_off, int64_t N, const 
     return fail(SSH_EDEVICE, "ssh_sketch: cannot resolve error flag");
   unsigned long long* rc = reinterpret_cast<unsigned long long*>(repair_count);
   const unsigned grid = grid_for(N, kWavesPerBlock, 1 << 16);
+  const unsigned fgrid = grid_for(N, kWavesPerBlock, 2048);
   const dim3 blk(256);
 #define SSH_FAST(WW, DD, RR)                                                                   \
   if (!force_generic && W == WW && delta == DD) {                                              \
-    sketch_fast_kernel<WW, DD, RR><<<grid, blk, 0, stream>>>(x, x_off, N, fa, bits,           \
+    sketch_fast_kernel<WW, DD, RR><<<fgrid, blk, 0, stream>>>(x, x_off, N, fa, bits,          \
                                                               bit_word_off, nbits, rc, err);  \
     return check_launch("ssh_sketch");                                                         \
   }
