@@ -16,6 +16,8 @@
 //      LDS count buffer), and the token is written at its rank of `codes`,
 //      so tokens come out ascending without sorting;
 //   4. counts are copied out and the bitmap and counts are cleared.
+// Bitmap word w (and its rank base) sits at slot w + w/16, so the per-lane
+// scans of step 2 hit distinct LDS banks.
 // A token is the n bits in stream order read most significant first.
 #include "common.hpp"
 
@@ -26,10 +28,16 @@ constexpr int kShWaves = 4;     // wavefronts per workgroup
 
 __host__ __device__ inline int shingle_bitmap_words(int n) { return n > 5 ? 1 << (n - 5) : 1; }
 
+// Bitmap word w and its rank base are stored at slot w + w / 16: a lane that
+// scans 16 or more consecutive words then starts on a different LDS bank
+// than its neighbours.
+__host__ __device__ inline int pad_slot(int w) { return w + (w >> 4); }
+__host__ __device__ inline int shingle_slots(int n) { return pad_slot(shingle_bitmap_words(n) - 1) + 1; }
+
 // LDS bytes of one wave: bitmap (u32), rank bases (u16, padded to 16 bytes), counts (u32)
 __host__ __device__ inline size_t shingle_lds_bytes(int n) {
-  const size_t bw = (size_t)shingle_bitmap_words(n);
-  return bw * 4 + ((bw * 2 + 15) & ~(size_t)15) + (size_t)kCountCap * 4;
+  const size_t bs = (size_t)shingle_slots(n);
+  return bs * 4 + ((bs * 2 + 15) & ~(size_t)15) + (size_t)kCountCap * 4;
 }
 
 // 32 stream bits starting at bit b0 (bit j of the result is stream bit b0 + j;
@@ -50,12 +58,13 @@ __global__ __launch_bounds__(kShWaves * kWave) void shingle_kernel(
     int32_t* __restrict__ n_distinct, int* err) {
   extern __shared__ uint32_t smem32[];
   const int BW = shingle_bitmap_words(n);
+  const int BS = shingle_slots(n);
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave-uniform
   const int lane = lane_id();
   uint32_t* bm = smem32 + (shingle_lds_bytes(n) / 4) * w;
-  uint16_t* pre = reinterpret_cast<uint16_t*>(bm + BW);
-  uint32_t* cnt = bm + BW + ((BW * 2 + 15) & ~15) / 4;
-  for (int i = lane; i < BW; i += kWave) bm[i] = 0;
+  uint16_t* pre = reinterpret_cast<uint16_t*>(bm + BS);
+  uint32_t* cnt = bm + BS + ((BS * 2 + 15) & ~15) / 4;
+  for (int i = lane; i < BS; i += kWave) bm[i] = 0;
   for (int i = lane; i < kCountCap; i += kWave) cnt[i] = 0;
   wave_sync_lds();
   const uint32_t mask = (1u << n) - 1u;  // n <= 16
@@ -93,7 +102,7 @@ __global__ __launch_bounds__(kShWaves * kWave) void shingle_kernel(
         uint32_t prev = 0xFFFFFFFFu;
         for (int k = 0; k < kend; ++k) {
           const uint32_t t = (rev >> (32 - n - k)) & mask;
-          if (t != prev) atomicOr(bm + (t >> 5), 1u << (t & 31));
+          if (t != prev) atomicOr(bm + pad_slot(t >> 5), 1u << (t & 31));
           prev = t;
         }
       }
@@ -105,14 +114,14 @@ __global__ __launch_bounds__(kShWaves * kWave) void shingle_kernel(
     uint32_t c = 0;
 #pragma unroll
     for (int j = 0; j < WPL; ++j) {
-      wv[j] = w0 + j < BW ? bm[w0 + j] : 0u;
+      wv[j] = w0 + j < BW ? bm[pad_slot(w0 + j)] : 0u;
       c += __builtin_popcount(wv[j]);
     }
     const uint32_t incl = wave_incl_scan(c);
     uint32_t rk = incl - c;
 #pragma unroll
     for (int j = 0; j < WPL; ++j) {
-      if (w0 + j < BW) pre[w0 + j] = (uint16_t)rk;
+      if (w0 + j < BW) pre[pad_slot(w0 + j)] = (uint16_t)rk;
       rk += __builtin_popcount(wv[j]);
     }
     const uint32_t D = wave_bcast(incl, kWave - 1);
@@ -126,8 +135,8 @@ __global__ __launch_bounds__(kShWaves * kWave) void shingle_kernel(
 
     // 3. counts by rank (runs of equal tokens in a lane counted at once), codes at their ranks
     auto flush = [&](uint32_t t, uint32_t run) {
-      const uint32_t word = t >> 5;
-      const uint32_t rank = (uint32_t)pre[word] + __builtin_popcount(bm[word] & ((1u << (t & 31)) - 1u));
+      const int slot = pad_slot((int)(t >> 5));
+      const uint32_t rank = (uint32_t)pre[slot] + __builtin_popcount(bm[slot] & ((1u << (t & 31)) - 1u));
       if (in_lds) atomicAdd(cnt + rank, run);
       else atomicAdd(counts + ho + rank, run);
       codes[ho + rank] = t;
@@ -163,7 +172,7 @@ __global__ __launch_bounds__(kShWaves * kWave) void shingle_kernel(
     }
 #pragma unroll
     for (int j = 0; j < WPL; ++j)
-      if (w0 + j < BW && wv[j]) bm[w0 + j] = 0;
+      if (w0 + j < BW && wv[j]) bm[pad_slot(w0 + j)] = 0;
     wave_sync_lds();
     if (lane == 0) n_distinct[s] = (int32_t)D;
   }
