@@ -247,7 +247,7 @@ struct Best {
   double t;
 };
 
-__global__ __launch_bounds__(256) void cws_kernel(const uint32_t* __restrict__ codes,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) void cws_kernel(const uint32_t* __restrict__ codes,
                                                   const uint32_t* __restrict__ counts,
                                                   const int64_t* __restrict__ hist_off,
                                                   const int32_t* __restrict__ n_distinct, int64_t N,
@@ -317,8 +317,9 @@ __global__ __launch_bounds__(256) void cws_kernel(const uint32_t* __restrict__ c
             }
 #pragma unroll
             for (int u = 0; u < kPassA; ++u) {
-              const uint32_t c0 = (wv[u] << 16) | pv[u];
-              const uint32_t c1 = (wv[u] & 0xFFFF0000u) | pv[u];
+              // (key << 16 | position) as byte selects of (key pair, position)
+              const uint32_t c0 = __builtin_amdgcn_perm(wv[u], pv[u], 0x05040100u);
+              const uint32_t c1 = __builtin_amdgcn_perm(wv[u], pv[u], 0x07060100u);
               m2[0] = med3(m1[0], m2[0], c0);  // second smallest (m1 <= m2)
               m1[0] = c0 < m1[0] ? c0 : m1[0];
               m2[1] = med3(m1[1], m2[1], c1);
