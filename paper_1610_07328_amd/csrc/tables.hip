@@ -93,30 +93,76 @@ __global__ __launch_bounds__(kRsThreads) void rs_hist_kernel(RsIn in, int64_t N,
   hist[((int64_t)l * 256 + threadIdx.x) * nblk + b] = h[threadIdx.x];
 }
 
-// exclusive scan, per table, of the nblk*256 counts in (digit, tile) order
-__global__ __launch_bounds__(1024) void rs_scan_kernel(uint32_t* __restrict__ hist, int nblk) {
-  __shared__ uint32_t part[1024];
-  const int l = blockIdx.x;
-  uint32_t* h = hist + (int64_t)l * 256 * nblk;
-  const int64_t n = (int64_t)256 * nblk;
-  const int64_t chunk = (n + 1023) / 1024;
-  const int64_t lo = threadIdx.x * chunk;
-  const int64_t hi = lo + chunk < n ? lo + chunk : n;
+// Exclusive scan, per table, of the n = 256 * nblk counts in (digit, tile)
+// order, in S segments of `seg` counts (seg a multiple of 4): rs_reduce sums
+// each segment; rs_scan adds the sums of the segments before its own and
+// scans its segment in tiles of 1024 counts (four per thread).
+__global__ __launch_bounds__(kRsThreads) void rs_reduce_kernel(const uint32_t* __restrict__ hist,
+                                                               int64_t n, int64_t seg,
+                                                               uint32_t* __restrict__ seg_sum) {
+  __shared__ uint32_t ws[kRsWaves];
+  const int l = blockIdx.y, sg = blockIdx.x;
+  const uint32_t* h = hist + (int64_t)l * n;
+  const int64_t lo = (int64_t)sg * seg;
+  const int64_t hi = lo + seg < n ? lo + seg : n;
   uint32_t sum = 0;
-  for (int64_t i = lo; i < hi; ++i) sum += h[i];
-  part[threadIdx.x] = sum;
+  for (int64_t i = lo + threadIdx.x; i < hi; i += kRsThreads) sum += h[i];
+  sum = wave_sum(sum);
+  if (lane_id() == 0) ws[threadIdx.x / kWave] = sum;
   __syncthreads();
-  for (int d = 1; d < 1024; d <<= 1) {
-    uint32_t v = threadIdx.x >= (unsigned)d ? part[threadIdx.x - d] : 0u;
-    __syncthreads();
-    part[threadIdx.x] += v;
-    __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t t = 0;
+    for (int i = 0; i < kRsWaves; ++i) t += ws[i];
+    seg_sum[(int64_t)l * gridDim.x + sg] = t;
   }
-  uint32_t run = part[threadIdx.x] - sum;
-  for (int64_t i = lo; i < hi; ++i) {
-    uint32_t c = h[i];
-    h[i] = run;
-    run += c;
+}
+
+__global__ __launch_bounds__(kRsThreads) void rs_scan_kernel(uint32_t* __restrict__ hist, int64_t n,
+                                                             int64_t seg,
+                                                             const uint32_t* __restrict__ seg_sum) {
+  __shared__ uint32_t wtot[kRsWaves];
+  __shared__ uint32_t carry_s;
+  const int l = blockIdx.y, sg = blockIdx.x;
+  const int w = threadIdx.x / kWave;
+  uint32_t* h = hist + (int64_t)l * n;
+  if (threadIdx.x == 0) {
+    uint32_t c = 0;
+    for (int i = 0; i < sg; ++i) c += seg_sum[(int64_t)l * gridDim.x + i];
+    carry_s = c;
+  }
+  __syncthreads();
+  uint32_t carry = carry_s;
+  const int64_t lo = (int64_t)sg * seg;
+  const int64_t hi = lo + seg < n ? lo + seg : n;
+  for (int64_t t0 = lo; t0 < hi; t0 += 4 * kRsThreads) {
+    const int64_t i = t0 + 4 * threadIdx.x;
+    uint4 v = make_uint4(0u, 0u, 0u, 0u);
+    if (i + 3 < hi) {
+      v = *reinterpret_cast<const uint4*>(h + i);
+    } else {
+      if (i < hi) v.x = h[i];
+      if (i + 1 < hi) v.y = h[i + 1];
+      if (i + 2 < hi) v.z = h[i + 2];
+    }
+    const uint32_t tsum = v.x + v.y + v.z + v.w;
+    const uint32_t incl = wave_incl_scan(tsum);
+    if (lane_id() == kWave - 1) wtot[w] = incl;
+    __syncthreads();
+    uint32_t before = carry;
+    for (int ww = 0; ww < w; ++ww) before += wtot[ww];
+    uint32_t tile = 0;
+    for (int ww = 0; ww < kRsWaves; ++ww) tile += wtot[ww];
+    uint32_t run = before + incl - tsum;
+    const uint4 o = make_uint4(run, run + v.x, run + v.x + v.y, run + v.x + v.y + v.z);
+    if (i + 3 < hi) {
+      *reinterpret_cast<uint4*>(h + i) = o;
+    } else {
+      if (i < hi) h[i] = o.x;
+      if (i + 1 < hi) h[i + 1] = o.y;
+      if (i + 2 < hi) h[i + 2] = o.z;
+    }
+    carry += tile;
+    __syncthreads();  // wtot is reused by the next tile
   }
 }
 
@@ -220,10 +266,12 @@ __global__ __launch_bounds__(kRsThreads) void rs_scatter_kernel(RsIn in, int64_t
 
 static inline size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
+constexpr int kRsMaxSeg = 64;  // scan segments per table
+
 size_t table_workspace_bytes(int64_t N, int L) {
   const int64_t nblk = ceil_div(N > 0 ? N : 1, kRsTile);
   return align256((size_t)N * L * 8) + align256((size_t)N * L * 4) +
-         align256((size_t)L * 256 * nblk * 4);
+         align256((size_t)L * 256 * nblk * 4) + align256((size_t)L * kRsMaxSeg * 4);
 }
 
 ssh_status table_build_launch(const uint64_t* keys, int64_t N, int L, uint64_t* tab_keys,
@@ -238,7 +286,16 @@ ssh_status table_build_launch(const uint64_t* keys, int64_t N, int L, uint64_t* 
   uint32_t* alt_ids = reinterpret_cast<uint32_t*>(p);
   p += align256((size_t)N * L * 4);
   uint32_t* hist = reinterpret_cast<uint32_t*>(p);
+  p += align256((size_t)L * 256 * nblk * 4);
+  uint32_t* seg_sum = reinterpret_cast<uint32_t*>(p);
   const dim3 grid(nblk, L);
+  // scan segments: about 4096 counts each, a multiple of 4, at most kRsMaxSeg
+  const int64_t n = (int64_t)256 * nblk;
+  int nseg = (int)ceil_div(n, 4096);
+  if (nseg > kRsMaxSeg) nseg = kRsMaxSeg;
+  const int64_t seg = (ceil_div(n, nseg) + 3) & ~(int64_t)3;
+  nseg = (int)ceil_div(n, seg);
+  const dim3 sgrid(nseg, L);
   // passes: keys -> alt -> tab -> alt -> tab
   for (int pass = 0; pass < 4; ++pass) {
     const int shift = 32 + 8 * pass;
@@ -259,7 +316,8 @@ ssh_status table_build_launch(const uint64_t* keys, int64_t N, int L, uint64_t* 
       oi = alt_ids;
     }
     rs_hist_kernel<<<grid, kRsThreads, 0, stream>>>(in, N, L, shift, nblk, hist);
-    rs_scan_kernel<<<L, 1024, 0, stream>>>(hist, nblk);
+    rs_reduce_kernel<<<sgrid, kRsThreads, 0, stream>>>(hist, n, seg, seg_sum);
+    rs_scan_kernel<<<sgrid, kRsThreads, 0, stream>>>(hist, n, seg, seg_sum);
     rs_scatter_kernel<<<grid, kRsThreads, 0, stream>>>(in, N, L, shift, nblk, hist, ok, oi);
   }
   return check_launch("ssh_table_build");
