@@ -225,6 +225,7 @@ def main():
 
     # workload facts for the algorithmic byte counts
     ncand = qry.ncand[:nq].cpu().numpy()
+    rsz = qry.rsize[:nq].cpu().numpy().astype(np.float64)
     nd = db.ndist[:N].cpu().numpy().astype(np.int64)
     repaired = int(db.repair.cpu().numpy()[0]) / (args.warmup + args.steps)
     nb = int(db.plan.max_nbits)
@@ -314,6 +315,9 @@ def main():
                              "samples": int(lat.size), "batch": 1},
         "stage_ms": per_stage,
         "stage_hbm": stage_roofline,
+        "retrieved_set": {"mean": float(rsz.mean()), "p50": float(np.percentile(rsz, 50)),
+                          "p99": float(np.percentile(rsz, 99)), "max": float(rsz.max()),
+                          "pruned_frac": float(1.0 - rsz.mean() / N)},
         "sketch_fp64_repaired_windows": repaired,
         "mean_distinct_shingles": sum_d / N,
         "roofline": roof,

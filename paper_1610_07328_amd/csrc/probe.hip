@@ -33,24 +33,70 @@ struct ProbeCtx {
   int H;
 };
 
-// Visit every member of R (once each) with its score.
+// Number of the H hash values of X equal to the query's (qh in LDS): the
+// row is read 16 bytes at a time, eight loads in flight.
+__device__ __forceinline__ int member_score(const ProbeCtx& c, uint32_t X, const uint64_t* qh) {
+  const uint64_t* xh = c.db_hv + (int64_t)X * c.H;
+  int score = 0;
+  int j = 0;
+  if ((c.H & 1) == 0 && ((uintptr_t)c.db_hv & 15) == 0) {  // rows are 16-byte aligned
+    const ulonglong2* x2 = reinterpret_cast<const ulonglong2*>(xh);
+    for (; j + 16 <= c.H; j += 16) {
+      ulonglong2 v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = x2[j / 2 + u];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) score += (v[u].x == qh[j + 2 * u]) + (v[u].y == qh[j + 2 * u + 1]);
+    }
+  }
+  for (; j < c.H; ++j) score += xh[j] == qh[j];
+  return score;
+}
+
+// Entry e of the concatenated key runs: the member it names, or -1 when its
+// full key differs from the query's or the member already matched an earlier
+// table (a member of R is counted at the first table whose key matches).
+__device__ __forceinline__ int64_t entry_member(const ProbeCtx& c, const uint64_t* qk,
+                                                const int64_t* glo, const int64_t* gpre,
+                                                int64_t e) {
+  int l = 0;
+  while (l + 1 < c.L && gpre[l + 1] <= e) ++l;
+  const int64_t idx = (int64_t)l * c.N + glo[l] + (e - gpre[l]);
+  if (c.tab_keys[idx] != qk[l]) return -1;
+  const uint32_t X = c.tab_ids[idx];
+  for (int l2 = 0; l2 < l; ++l2)
+    if (c.db_keys[(int64_t)X * c.L + l2] == qk[l2]) return -1;
+  return X;
+}
+
+constexpr int kScoreCap = 16384;          // entries whose scores are kept in LDS
+constexpr uint16_t kNotMember = 0xFFFFu;
+
+// Visit every member of R (once each) with its score.  With `sc` set, the
+// first visit records every entry's score (kNotMember for non-members) and
+// later visits read it instead of re-scoring.
 template <typename F>
 __device__ __forceinline__ void for_members(const ProbeCtx& c, const uint64_t* qk, const uint64_t* qh,
                                             const int64_t* glo, const int64_t* gpre, int64_t G,
-                                            F&& f) {
+                                            uint16_t* sc, bool first, F&& f) {
   for (int64_t e = threadIdx.x; e < G; e += kPrThreads) {
-    int l = 0;
-    while (l + 1 < c.L && gpre[l + 1] <= e) ++l;
-    const int64_t idx = (int64_t)l * c.N + glo[l] + (e - gpre[l]);
-    if (c.tab_keys[idx] != qk[l]) continue;
-    const uint32_t X = c.tab_ids[idx];
-    bool dup = false;
-    for (int l2 = 0; l2 < l && !dup; ++l2) dup = c.db_keys[(int64_t)X * c.L + l2] == qk[l2];
-    if (dup) continue;
-    const uint64_t* xh = c.db_hv + (int64_t)X * c.H;
-    int score = 0;
-    for (int j = 0; j < c.H; ++j) score += xh[j] == qh[j];
-    f(X, score);
+    if (sc && !first) {
+      const uint16_t v = sc[e];
+      if (v == kNotMember) continue;
+      int l = 0;
+      while (l + 1 < c.L && gpre[l + 1] <= e) ++l;
+      const uint32_t X = c.tab_ids[(int64_t)l * c.N + glo[l] + (e - gpre[l])];
+      f(X, (int)v);
+      continue;
+    }
+    const int64_t X = entry_member(c, qk, glo, gpre, e);
+    if (X < 0) {
+      if (sc) sc[e] = kNotMember;
+      continue;
+    }
+    const int score = member_score(c, (uint32_t)X, qh);
+    if (sc) sc[e] = (uint16_t)score;
+    f((uint32_t)X, score);
   }
 }
 
@@ -111,6 +157,7 @@ __global__ __launch_bounds__(kPrThreads) void probe_kernel(ProbeCtx c, const uin
   __shared__ uint32_t bhist[256];
   __shared__ uint64_t sel[SSH_MAX_C];
   __shared__ uint32_t ties[kTieCap];
+  __shared__ uint16_t sc_buf[kScoreCap];
   __shared__ uint32_t nR, nsel, ntie;
   __shared__ int s_thr;
   __shared__ uint32_t prefix, need;
@@ -163,8 +210,9 @@ __global__ __launch_bounds__(kPrThreads) void probe_kernel(ProbeCtx c, const uin
   }
   __syncthreads();
   const int64_t G = gpre[c.L];
+  uint16_t* sc = G <= kScoreCap ? sc_buf : nullptr;
   // 2. score histogram over R
-  for_members(c, qk, qh, glo, gpre, G, [&](uint32_t X, int score) {
+  for_members(c, qk, qh, glo, gpre, G, sc, true, [&](uint32_t X, int score) {
     (void)X;
     atomicAdd(&hist[score], 1u);
     atomicAdd(&nR, 1u);
@@ -195,7 +243,8 @@ __global__ __launch_bounds__(kPrThreads) void probe_kernel(ProbeCtx c, const uin
   const uint32_t tieN = thr >= 0 ? hist[thr] : 0;
   const bool ties_fit = tieN <= (uint32_t)kTieCap;
   // 3. keep members above the level, collect the level's ids if they fit
-  for_members(c, qk, qh, glo, gpre, G, [&](uint32_t X, int score) {
+  __syncthreads();  // recorded scores visible to every thread
+  for_members(c, qk, qh, glo, gpre, G, sc, false, [&](uint32_t X, int score) {
     if (score > thr) {
       const uint32_t slot = atomicAdd(&nsel, 1u);
       sel[slot] = ((uint64_t)(c.H - score) << 32) | X;
@@ -225,7 +274,7 @@ __global__ __launch_bounds__(kPrThreads) void probe_kernel(ProbeCtx c, const uin
         bhist[tid] = 0;
         __syncthreads();
         const uint32_t pfx = prefix;
-        for_members(c, qk, qh, glo, gpre, G, [&](uint32_t X, int score) {
+        for_members(c, qk, qh, glo, gpre, G, sc, false, [&](uint32_t X, int score) {
           if (score == thr && (pass == 0 || (X >> (sh + 8)) == (pfx >> (sh + 8))))
             atomicAdd(&bhist[(X >> sh) & 255], 1u);
         });
@@ -243,7 +292,7 @@ __global__ __launch_bounds__(kPrThreads) void probe_kernel(ProbeCtx c, const uin
         __syncthreads();
       }
       const uint32_t T = prefix;  // the need-th smallest id of the level
-      for_members(c, qk, qh, glo, gpre, G, [&](uint32_t X, int score) {
+      for_members(c, qk, qh, glo, gpre, G, sc, false, [&](uint32_t X, int score) {
         if (score == thr && X <= T) sel[atomicAdd(&nsel, 1u)] = ((uint64_t)(c.H - thr) << 32) | X;
       });
       __syncthreads();
