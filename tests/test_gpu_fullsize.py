@@ -1,0 +1,223 @@
+"""Parity at workload size, in the launch configuration the benchmark times.
+
+The oracle computes sampled outputs one by one: the bits, tokens, hash values
+and keys of sampled series and queries, and the DTW re-rank of sampled queries.
+What it cannot compute at this size is checked through properties that hold at
+any size:
+* every hash table is a stable order of (key, id) by the key's high half;
+* every query's candidates are exactly the first C members of its retrieved
+  set, ranked by (shared hash values desc, id asc), which torch recomputes from
+  the same keys and hash values.
+
+Workloads: the batched index build (1,000,000 random walks x 1024, W=80,
+delta=3, n=15, K=L=10, 1,000 queries, C=50, 5 % band), the uneven batch (series
+of 256..8192 samples, random walk and ECG-like mixed) and the large
+configuration's per-series shape (length 2048, W=128, delta=4, n=15, K=10,
+L=20, C=200, 10 % band) on 100,000 series.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1610_07328_amd import datagen
+from paper_1610_07328_amd.pipeline import HashBatch, Index, Params, QueryBatch
+from tests._gpu_helpers import compare_rerank, unpack_bits
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ssh():
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_1610_07328_amd import ssh as mod
+    mod.lib()
+    return mod
+
+
+def _announce(msg):
+    print(f"\n[case] {msg}", flush=True)
+
+
+def _rows(t: torch.Tensor, idx: np.ndarray) -> np.ndarray:
+    """Rows idx of a device tensor (uint64 rows gathered through an int64 view)."""
+    i = torch.as_tensor(np.asarray(idx, np.int64), device=t.device)
+    if t.dtype == torch.uint64:
+        return t.view(torch.int64)[i].cpu().numpy().view(np.uint64)
+    return t[i].cpu().numpy()
+
+
+def _check_sampled_hash(hb: HashBatch, x, off, r, draws, p: Params, sample):
+    """Bits, tokens, hash values and keys of the sampled series against the oracle."""
+    bwo, hoff = hb.plan.bit_word_off, hb.plan.hist_off
+    nb = _rows(hb.nbits, sample)
+    nd = _rows(hb.ndist, sample)
+    hv = _rows(hb.hv, sample)
+    keys = _rows(hb.keys, sample)
+    smax = max(1, int(hb.plan.max_nbits) - p.n + 1)
+    lnS = oracle.ln_table(smax)
+    for i, s in enumerate(sample):
+        xs = x[off[s]:off[s + 1]]
+        ob = oracle.sketch_series(xs, r, p.W, p.delta)
+        assert nb[i] == len(ob), s
+        w0, w1 = int(bwo[s]), int(bwo[s + 1])
+        words = hb.bits[w0:w1].cpu().numpy()
+        got = unpack_bits(words, np.array([0, w1 - w0]), np.array([nb[i]]), 0)
+        assert np.array_equal(got, ob), f"series {s}: bits differ"
+        oc, ok = oracle.shingle(ob, p.n)
+        assert nd[i] == len(oc), s
+        h0 = int(hoff[s])
+        assert np.array_equal(hb.codes[h0:h0 + len(oc)].cpu().numpy(), oc), s
+        assert np.array_equal(hb.counts[h0:h0 + len(oc)].cpu().numpy(), ok), s
+        _, _, ohv = oracle.cws(oc, ok, *draws, lnS)
+        assert np.array_equal(hv[i], ohv), f"series {s}: hash values differ"
+        okeys = oracle.band_keys(ohv[None, :], p.K, p.L, p.key_seed)[0]
+        assert np.array_equal(keys[i], okeys), f"series {s}: keys differ"
+
+
+def _check_tables(ix: Index, N: int, L: int):
+    """Each table: a permutation of the ids, keys in place, stable by the high half."""
+    keys = ix.db.keys[:N].view(torch.int64)
+    for l in range(L):
+        tk = ix.tab_keys[l, :N].view(torch.int64)
+        ti = ix.tab_ids[l, :N].view(torch.int32).to(torch.int64)  # ids < 2^31
+        hi = (tk >> 32) & 0xFFFFFFFF
+        assert bool((hi[1:] >= hi[:-1]).all()), l
+        eq = hi[1:] == hi[:-1]
+        assert bool((ti[1:][eq] > ti[:-1][eq]).all()), l
+        assert torch.equal(torch.sort(ti).values, torch.arange(N, device=ti.device)), l
+        assert torch.equal(keys[ti, l], tk), l
+
+
+def _check_probe(qb: QueryBatch, qsel, C: int, H: int):
+    """Candidates = the first C of R by (score desc, id asc); |R| reported."""
+    db = qb.index.db
+    N = db.N
+    dkeys = db.keys[:N].view(torch.int64)
+    dhv = db.hv[:N].view(torch.int64)
+    cand = qb.cand.cpu().numpy()
+    ncand = qb.ncand.cpu().numpy()
+    rsz = qb.rsize.cpu().numpy()
+    empty = np.int64(-1)  # the reserved empty key as a signed view
+    for q in qsel:
+        qk = qb.qh.keys[q].view(torch.int64)
+        qh = qb.qh.hv[q].view(torch.int64)
+        if int(qk[0]) == empty:
+            assert ncand[q] == 0 and rsz[q] == 0
+            continue
+        members = (dkeys == qk[None, :]).any(dim=1).nonzero().flatten()
+        assert rsz[q] == members.numel(), q
+        score = (dhv[members] == qh[None, :]).sum(dim=1)
+        order = torch.sort((H - score) * (1 << 32) + members).values
+        want = (order[:C] & 0xFFFFFFFF).cpu().numpy()
+        assert ncand[q] == len(want), q
+        assert np.array_equal(cand[q, :ncand[q]], want), q
+        assert np.all(cand[q, ncand[q]:] == -1), q
+
+
+def _check_rerank(qb: QueryBatch, Qx, Qoff, x, off, p: Params, qsel):
+    """DTW top-k of sampled queries against the oracle on the same candidates."""
+    cand = qb.cand.cpu().numpy()[qsel]
+    ncand = qb.ncand.cpu().numpy()[qsel]
+    ids = qb.ids.cpu().numpy()[qsel]
+    dist = qb.dist.cpu().numpy()[qsel]
+    qs = [Qx[Qoff[q]:Qoff[q + 1]] for q in qsel]
+    qoff = np.zeros(len(qsel) + 1, np.int64)
+    np.cumsum([len(v) for v in qs], out=qoff[1:])
+    qx = np.concatenate(qs).astype(np.float32)
+    oids, odist, all_d = oracle.rerank(qx, qoff, x, off, cand, ncand, p.band_frac, p.k)
+    compare_rerank(ids, dist, oids, odist, all_d, cand, ncand)
+
+
+def _run_index_and_queries(ssh, X, Q, p: Params, seed: int):
+    x, off = datagen.csr(X)
+    qx, qoff = datagen.csr(Q)
+    r = datagen.filter_r(p.W, seed=seed)
+    draws = datagen.cws_draws(p.n, p.H, seed=seed)
+    tables = ssh.CwsTables(*draws, p.n)
+    db = HashBatch(torch.as_tensor(x).cuda(), off, p)
+    qh = HashBatch(torch.as_tensor(qx).cuda(), qoff, p)
+    ix = Index(db)
+    qb = QueryBatch(qh, ix)
+    # the benchmark's step, launch for launch
+    db.sketch(r)
+    db.shingle()
+    db.cws(tables)
+    db.band_keys()
+    ix.build()
+    qh.run(r, tables)
+    qb.probe()
+    qb.rerank(Q.shape[1], X.shape[1])
+    torch.cuda.synchronize()
+    ssh.check_device_errors()
+    return x, off, qx, qoff, r, draws, db, qh, ix, qb
+
+
+def _query_sample(qb: QueryBatch, rng, want: int):
+    """Queries with candidates first (they exercise the re-rank), then some without."""
+    nc = qb.ncand.cpu().numpy()
+    with_c = np.nonzero(nc > 0)[0]
+    without = np.nonzero(nc == 0)[0]
+    a = rng.choice(with_c, size=min(want, len(with_c)), replace=False) if len(with_c) else []
+    b = rng.choice(without, size=min(4, len(without)), replace=False) if len(without) else []
+    return np.sort(np.concatenate([np.asarray(a, np.int64), np.asarray(b, np.int64)]))
+
+
+def test_index_build_workload_sampled(ssh):
+    """1,000,000 x 1024 random walks, the benchmark's workload and launches."""
+    _announce("index build 1M x 1024, sampled parity")
+    p = Params(W=80, delta=3, n=15, K=10, L=10, band_frac=0.05, C=50, k=10)
+    N, m, nq = 1_000_000, 1024, 1000
+    X = datagen.random_walks(N, m, seed=0)
+    Q, _ = datagen.perturbed_queries(X[:100_000], nq, 0.1, seed=0)
+    x, off, qx, qoff, r, draws, db, qh, ix, qb = _run_index_and_queries(ssh, X, Q, p, seed=0)
+    rng = np.random.default_rng(1)
+    sample = np.sort(np.concatenate([rng.choice(N, 44, replace=False), [0, 1, N - 2, N - 1]]))
+    _check_sampled_hash(db, x, off, r, draws, p, sample)
+    _check_tables(ix, N, p.L)
+    qsel = _query_sample(qb, rng, 16)
+    _check_sampled_hash(qh, qx, qoff, r, draws, p, qsel)
+    _check_probe(qb, range(nq), p.C, p.H)
+    _check_rerank(qb, qx, qoff, x, off, p, qsel)
+
+
+def test_uneven_batch_sampled(ssh):
+    """Series of 256..8192 samples, random walk and ECG-like, in one launch per stage."""
+    _announce("uneven batch 20k, sampled parity")
+    p = Params(W=80, delta=3, n=15, K=10, L=10)
+    x, off = datagen.ragged_series(20_000, 256, 8192, seed=3)
+    r = datagen.filter_r(p.W, seed=3)
+    draws = datagen.cws_draws(p.n, p.H, seed=3)
+    tables = ssh.CwsTables(*draws, p.n)
+    hb = HashBatch(torch.as_tensor(x).cuda(), off, p)
+    hb.run(r, tables)
+    ix = Index(hb)
+    ix.build()
+    torch.cuda.synchronize()
+    ssh.check_device_errors()
+    N = len(off) - 1
+    lens = np.diff(off)
+    rng = np.random.default_rng(4)
+    longest = np.argsort(lens)[-3:]
+    shortest = np.argsort(lens)[:3]
+    sample = np.unique(np.concatenate([rng.choice(N, 26, replace=False), longest, shortest]))
+    _check_sampled_hash(hb, x, off, r, draws, p, sample)
+    _check_tables(ix, N, p.L)
+
+
+def test_large_config_shape_sampled(ssh):
+    """Length 2048, W=128, delta=4, H=200 (K=10, L=20), C=200, 10 % band, 100,000 series."""
+    _announce("large-configuration shape 100k x 2048, sampled parity")
+    p = Params(W=128, delta=4, n=15, K=10, L=20, band_frac=0.10, C=200, k=10)
+    N, m, nq = 100_000, 2048, 64
+    X = datagen.random_walks(N, m, seed=5)
+    Q, _ = datagen.perturbed_queries(X, nq, 0.1, seed=5)
+    x, off, qx, qoff, r, draws, db, qh, ix, qb = _run_index_and_queries(ssh, X, Q, p, seed=5)
+    rng = np.random.default_rng(6)
+    sample = np.sort(rng.choice(N, 24, replace=False))
+    _check_sampled_hash(db, x, off, r, draws, p, sample)
+    _check_tables(ix, N, p.L)
+    qsel = _query_sample(qb, rng, 6)
+    _check_sampled_hash(qh, qx, qoff, r, draws, p, qsel)
+    _check_probe(qb, range(nq), p.C, p.H)
+    _check_rerank(qb, qx, qoff, x, off, p, qsel)

@@ -12,11 +12,10 @@ import torch
 
 import oracle
 from paper_1610_07328_amd import datagen
-from tests._gpu_helpers import ragged, to_dev, to_np, unpack_bits
+from tests._gpu_helpers import DTW_RTOL, compare_rerank, ragged, to_dev, to_np, unpack_bits
 
 pytestmark = pytest.mark.gpu
 
-DTW_RTOL = 1e-5
 
 
 @pytest.fixture(scope="module")
@@ -341,17 +340,17 @@ def test_table_build_exact(ssh, N, L, distinct):
 
 
 def test_c1_probe_exact(ssh, c1):
+    """Tables and probe on hash values and keys that the oracle computed."""
     _announce("C1 probe")
     X, r, Q, draws = c1
     P = C1
-    hv, keys = _gpu_hash(ssh, X, r, draws, P)
-    qhv, qkeys = _gpu_hash(ssh, Q, r, draws, P)
+    ohv, okeys = _oracle_hash(X, r, draws, P)
+    oq_hv, oq_keys = _oracle_hash(Q, r, draws, P)
+    hv, keys = to_dev(ohv), to_dev(okeys)
     tk, ti = ssh.table_build(keys)
-    cand, ncand, rs = ssh.probe(tk, ti, keys, hv, qkeys, qhv, P["C"])
+    cand, ncand, rs = ssh.probe(tk, ti, keys, hv, to_dev(oq_keys), to_dev(oq_hv), P["C"])
     torch.cuda.synchronize()
     cand, ncand, rs = to_np(cand), to_np(ncand), to_np(rs)
-    ohv, okeys = to_np(hv), to_np(keys)
-    oq_hv, oq_keys = to_np(qhv), to_np(qkeys)
     for i in range(Q.shape[0]):
         oc, orr = oracle.probe(okeys, ohv, oq_keys[i], oq_hv[i], P["C"])
         assert rs[i] == orr and ncand[i] == len(oc), i
@@ -386,24 +385,6 @@ def test_probe_large_retrieved_sets_with_ties(ssh):
 # --------------------------------------------------------------------------
 # DTW re-rank
 # --------------------------------------------------------------------------
-def _compare_rerank(ids, dist, oids, odist, all_odist, cand, ncand):
-    for i in range(ids.shape[0]):
-        for j in range(ids.shape[1]):
-            if oids[i, j] < 0:
-                assert ids[i, j] == -1 and math.isinf(dist[i, j])
-                continue
-            if math.isinf(odist[i, j]):
-                assert math.isinf(dist[i, j])
-            else:
-                assert abs(dist[i, j] - odist[i, j]) <= DTW_RTOL * max(odist[i, j], 1e-30), (i, j)
-        # same ids except where the oracle's k-th and (k+1)-th are near ties
-        got, want = set(ids[i][ids[i] >= 0].tolist()), set(oids[i][oids[i] >= 0].tolist())
-        if got != want:
-            row = np.sort(all_odist[i, : ncand[i]])
-            kk = ids.shape[1]
-            assert kk < len(row) and abs(row[kk] - row[kk - 1]) <= DTW_RTOL * row[kk], i
-
-
 def _rerank_case(ssh, Q, X, cand, ncand, band, k):
     q, qoff = datagen.csr(Q)
     db, dboff = datagen.csr(X)
@@ -412,7 +393,7 @@ def _rerank_case(ssh, Q, X, cand, ncand, band, k):
     torch.cuda.synchronize()
     ssh.check_device_errors()
     oids, odist, all_d = oracle.rerank(q, qoff, db, dboff, cand, ncand, band, k)
-    _compare_rerank(to_np(ids), to_np(dist), oids, odist, all_d, cand, ncand)
+    compare_rerank(to_np(ids), to_np(dist), oids, odist, all_d, cand, ncand)
 
 
 def test_c1_rerank(ssh, c1):
