@@ -22,7 +22,8 @@
 //     therefore means a strictly smaller ln a.  Each lane keeps the smallest
 //     and second-smallest (key << 16 | position); position order is token
 //     order, so equal keys resolve to the earlier token.  If the smallest key
-//     is shared by two tokens the lane re-scans its hash exactly (rare).
+//     is shared by two tokens (rare), the lane evaluates exactly the keyed
+//     tokens holding that key.
 //  B. tokens of weight >= 4, in batches: ln a >= (ln c - r) - ln S, so a
 //     float32 lower bound of ln c - r rules most of them out; the rest are
 //     evaluated exactly and compared by (ln a, k) with the pass-A winner.
@@ -356,15 +357,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) void c
         for (int h = 0; h < 2; ++h) {
           const bool tie = !done[h] && m1[h] != kNone && ((m1[h] ^ m2[h]) >> 16) == 0;
           if (tie) {
-            // exact scan of every token for this hash, ascending, strict <
+            // The keyed minimum is among the keyed tokens whose key equals the
+            // smallest key K (a smaller key means a smaller ln a): evaluate
+            // exactly those, ascending, strict <.  Heavy tokens follow below.
+            const int j = h ? j1 : j0;
+            const uint32_t K = m1[h] >> 16;
             Best e{INFINITY, 0u, 0.0};
             for (int d = 0; d < D; ++d) {
+              const uint32_t c = counts_s[d];
+              if (c > 3u) continue;
+              const uint32_t k = codes_s[d];
+              const int64_t krow = (int64_t)(((c - 1u) << t.n) + k);
+              if ((uint32_t)t.k16[krow * t.H2 + j] != K) continue;
               double tt;
-              const double la = exact_ln_a(t, codes_s[d], counts_s[d], h ? j1 : j0, tt);
-              if (la < e.la) e = Best{la, codes_s[d], tt};
+              const double la = exact_ln_a(t, k, c, j, tt);
+              if (la < e.la) e = Best{la, k, tt};
             }
             b[h] = e;
-            done[h] = true;
+            done[h] = !any_heavy;
           }
         }
         // ---- pass B over tokens of weight >= 4 ----
