@@ -39,7 +39,11 @@ FP32_VALU_TFLOPS = 157.3
 # kernel's source file still has the digest it was measured with.
 MEASURED_TRAFFIC = {
     # kernel: (source file, sha256 of it, FETCH_SIZE KiB, WRITE_SIZE KiB,
-    #          fetch scale, write scale)
+    #          fetch scale, write scale); the 1 GiB copy read 524306.9 KiB on
+    #          FETCH_SIZE and 1048576 KiB on WRITE_SIZE
+    "cws_kernel": ("paper_1610_07328_amd/csrc/cws.hip",
+                   "47a5c57de71ecccd235f3560662f4697812fbf1d2a02e97c9e4a2e5a23267e6f",
+                   6023714.875, 792109.6875, 1048576.0 / 524306.9375, 1.0),
 }
 
 
