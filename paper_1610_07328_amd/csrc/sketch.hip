@@ -493,6 +493,21 @@ int take_sketch_err() {
   return v;
 }
 
+// Workgroups for the fast path: as many as the device holds at once (every
+// wavefront then walks many series and its repair queue drains in full
+// rounds, with no second, partly filled round of workgroups), and no more
+// than the series need.
+static unsigned resident_grid(const void* kernel, int64_t N) {
+  int dev = 0, cus = 0, per_cu = 0;
+  unsigned cap = 2048;
+  if (hipGetDevice(&dev) == hipSuccess &&
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 256, 0) == hipSuccess &&
+      cus > 0 && per_cu > 0)
+    cap = (unsigned)(cus * per_cu);
+  return grid_for(N, kWavesPerBlock, cap);
+}
+
 ssh_status sketch_launch(const float* x, const int64_t* x_off, int64_t N, const float* r, int W,
                          int delta, uint64_t* bits, const int64_t* bit_word_off, int32_t* nbits,
                          uint64_t* repair_count, hipStream_t stream, bool force_generic) {
@@ -505,10 +520,11 @@ ssh_status sketch_launch(const float* x, const int64_t* x_off, int64_t N, const 
     return fail(SSH_EDEVICE, "ssh_sketch: cannot resolve error flag");
   unsigned long long* rc = reinterpret_cast<unsigned long long*>(repair_count);
   const unsigned grid = grid_for(N, kWavesPerBlock, 1 << 16);
-  const unsigned fgrid = grid_for(N, kWavesPerBlock, 2048);
   const dim3 blk(256);
 #define SSH_FAST(WW, DD, RR)                                                                   \
   if (!force_generic && W == WW && delta == DD) {                                              \
+    const unsigned fgrid = resident_grid(reinterpret_cast<const void*>(                        \
+        &sketch_fast_kernel<WW, DD, RR>), N);                                                  \
     sketch_fast_kernel<WW, DD, RR><<<fgrid, blk, 0, stream>>>(x, x_off, N, fa, bits,          \
                                                               bit_word_off, nbits, rc, err);  \
     return check_launch("ssh_sketch");                                                         \
