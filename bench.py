@@ -31,6 +31,9 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 FP64_VALU_TFLOPS = 78.6
 FP32_VALU_TFLOPS = 157.3
+# non-packed vector lane operations per second: 256 CUs x 4 SIMDs x 16 lanes x
+# 2.4 GHz (157.3 TFLOP/s counts an FMA as 2 and packed fp32 as 2 lanes)
+VALU_LANE_OPS = FP32_VALU_TFLOPS * 1e12 / 4
 
 # HBM traffic of one launch of a kernel on this workload, from two rocprofv3
 # counter runs of this script (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch),
@@ -257,9 +260,9 @@ def main():
     dominant = max(["sketch", "shingle", "cws", "band_keys", "table_build", "rerank"],
                    key=lambda k: per_stage[k])
     if dominant == "rerank":
-        # 3 VALU lane-ops per cell (subtract, 3-way min, FMA) against the fp32 VALU peak
+        # 3 VALU lane-ops per cell (subtract, 3-way min, FMA) against the lane-op peak
         achieved = cells * 3 / (per_stage["rerank"] / 1e3) / 1e12
-        peak = FP32_VALU_TFLOPS / 2  # lane-ops/s = FLOP/s of FMA / 2
+        peak = VALU_LANE_OPS / 1e12
         roof = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tops/s",
                 "frac": achieved / peak, "traffic": None, "kernel": "dtw_kernel"}
     else:
@@ -272,6 +275,34 @@ def main():
                 "algorithmic_bytes": bytes_stage[dominant]}
         if dominant == "cws":
             roof["token_hash_evals_per_s"] = cws_evals / (per_stage["cws"] / 1e3)
+
+    # DTW kernel throughput on a full batch: every query re-ranks C seeded
+    # random candidates in the same band (outside the timed step)
+    g = np.random.default_rng(args.seed + 1)
+    cand_full = torch.as_tensor(g.integers(0, N, size=(nq, p.C)), device=dev)
+    ncand_full = torch.full((nq,), p.C, dtype=torch.int32, device=dev)
+    ws_full = torch.empty(max(ssh.rerank_workspace_bytes(nq, p.C), 1), dtype=torch.uint8, device=dev)
+    out_full = (torch.empty((nq, p.k), dtype=torch.int64, device=dev),
+                torch.empty((nq, p.k), dtype=torch.float32, device=dev))
+
+    def full_rerank():
+        ssh.dtw_rerank(qb.x, qb.x_off, db.x, db.x_off, cand_full, ncand_full, p.band_frac, m, m,
+                       p.k, ws=ws_full, out=out_full)
+
+    full_rerank()
+    torch.cuda.synchronize()
+    reps = 5
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        full_rerank()
+    e1.record()
+    e1.synchronize()
+    t_full = e0.elapsed_time(e1) / reps / 1e3
+    full_cells = nq * p.C * cells_per_pair
+    dtw_full = {"cells_per_s": full_cells / t_full, "ms": t_full * 1e3,
+                "pairs": nq * p.C, "cells": full_cells,
+                "alu_frac": full_cells * 3 / t_full / VALU_LANE_OPS}
 
     # single-query latency with the index resident
     lat = []
@@ -314,6 +345,7 @@ def main():
                    "K": p.K, "L": p.L, "queries": nq, "C": p.C, "band_frac": p.band_frac,
                    "k": p.k},
         "dtw_cells_per_s": cells / (per_stage["rerank"] / 1e3),
+        "dtw_full_batch": dtw_full,
         "query_latency_ms": {"p50": float(np.percentile(lat, 50)),
                              "p99": float(np.percentile(lat, 99)),
                              "samples": int(lat.size), "batch": 1},

@@ -19,8 +19,12 @@
 // so a lane loads one new x per row; in the steady state the ring of x
 // registers is renamed by unrolling G rows instead of moved.
 //
-// Each cell costs one subtract, one three-way min and one fused multiply-add
-// in float32.
+// Each cell costs one subtract, one three-way min, one fused multiply-add and
+// one add of a per-slot constant in float32: the constant is +inf for the one
+// slot that holds the first offset past the band (offset r + 1) and 0 for every
+// other slot, which keeps that slot at +inf without a select (all cell values
+// are >= 0, so adding 0 is exact).  In the steady state, blocks of rows whose
+// x indices are provably inside the series on every lane load x unchecked.
 #include <cmath>
 
 #include "common.hpp"
@@ -61,7 +65,7 @@ __device__ __forceinline__ float x_at(const DtwLane& d, int j) {
 // leave the lane's state untouched.
 template <int G>
 __device__ __forceinline__ void step_masked(DtwLane& d, float (&V)[G], float (&xr)[G], int T,
-                                            int gv) {
+                                            const float (&cb)[G]) {
   const int i = T - d.L;
   const bool active = (unsigned)i < (unsigned)d.lq;
   const int ic = i < 0 ? 0 : (i >= d.lq ? d.lq - 1 : i);
@@ -69,18 +73,15 @@ __device__ __forceinline__ void step_masked(DtwLane& d, float (&V)[G], float (&x
   float nv[G];
   const float leftN = dpp_from_left(V[G - 1]);
   float t = qv - xr[0];
-  nv[0] = __builtin_fmaf(t, t, fminf(fminf(leftN, V[1]), V[0]));
-  if (gv == 0) nv[0] = d.clampLane ? kInf : nv[0];
+  nv[0] = __builtin_fmaf(t, t, fminf(fminf(leftN, V[1]), V[0])) + cb[0];
 #pragma unroll
   for (int g = 1; g < G - 1; ++g) {
     t = qv - xr[g];
-    nv[g] = __builtin_fmaf(t, t, fminf(fminf(nv[g - 1], V[g + 1]), V[g]));
-    if (gv == g) nv[g] = d.clampLane ? kInf : nv[g];
+    nv[g] = __builtin_fmaf(t, t, fminf(fminf(nv[g - 1], V[g + 1]), V[g])) + cb[g];
   }
   const float upN = dpp_from_right(active ? nv[0] : kInf);
   t = qv - xr[G - 1];
-  nv[G - 1] = __builtin_fmaf(t, t, fminf(fminf(nv[G - 2], upN), V[G - 1]));
-  if (gv == G - 1) nv[G - 1] = d.clampLane ? kInf : nv[G - 1];
+  nv[G - 1] = __builtin_fmaf(t, t, fminf(fminf(nv[G - 2], upN), V[G - 1])) + cb[G - 1];
 #pragma unroll
   for (int g = 0; g < G; ++g) V[g] = active ? nv[g] : V[g];
 #pragma unroll
@@ -90,37 +91,37 @@ __device__ __forceinline__ void step_masked(DtwLane& d, float (&V)[G], float (&x
 }
 
 // Steady-state step: every lane's row is inside [0, lq).  Logical slot g is
-// physical register (g + ROT) % G of the x ring.
-template <int G, int ROT>
-__device__ __forceinline__ void step_full(DtwLane& d, float (&V)[G], float (&xr)[G], int T, int gv) {
+// physical register (g + ROT) % G of the x ring.  With IN, the x index this
+// step loads is inside [0, lx) on every lane and is read unchecked.
+template <int G, int ROT, bool IN>
+__device__ __forceinline__ void step_full(DtwLane& d, float (&V)[G], float (&xr)[G], int T,
+                                          const float (&cb)[G]) {
   const int i = T - d.L;
   const float qv = d.qs[i];
   float nv[G];
   const float leftN = dpp_from_left(V[G - 1]);
   float t = qv - xr[(0 + ROT) % G];
-  nv[0] = __builtin_fmaf(t, t, fminf(fminf(leftN, V[1]), V[0]));
-  if (gv == 0) nv[0] = d.clampLane ? kInf : nv[0];
+  nv[0] = __builtin_fmaf(t, t, fminf(fminf(leftN, V[1]), V[0])) + cb[0];
 #pragma unroll
   for (int g = 1; g < G - 1; ++g) {
     t = qv - xr[(g + ROT) % G];
-    nv[g] = __builtin_fmaf(t, t, fminf(fminf(nv[g - 1], V[g + 1]), V[g]));
-    if (gv == g) nv[g] = d.clampLane ? kInf : nv[g];
+    nv[g] = __builtin_fmaf(t, t, fminf(fminf(nv[g - 1], V[g + 1]), V[g])) + cb[g];
   }
   const float upN = dpp_from_right(nv[0]);
   t = qv - xr[(G - 1 + ROT) % G];
-  nv[G - 1] = __builtin_fmaf(t, t, fminf(fminf(nv[G - 2], upN), V[G - 1]));
-  if (gv == G - 1) nv[G - 1] = d.clampLane ? kInf : nv[G - 1];
+  nv[G - 1] = __builtin_fmaf(t, t, fminf(fminf(nv[G - 2], upN), V[G - 1])) + cb[G - 1];
 #pragma unroll
   for (int g = 0; g < G; ++g) V[g] = nv[g];
-  xr[ROT % G] = x_at(d, d.jn);
+  xr[ROT % G] = IN ? d.xs[d.jn] : x_at(d, d.jn);
   d.jn += 1;
 }
 
-template <int G, int ROT>
-__device__ __forceinline__ void steps_full(DtwLane& d, float (&V)[G], float (&xr)[G], int T0, int gv) {
+template <int G, int ROT, bool IN>
+__device__ __forceinline__ void steps_full(DtwLane& d, float (&V)[G], float (&xr)[G], int T0,
+                                           const float (&cb)[G]) {
   if constexpr (ROT < G) {
-    step_full<G, ROT>(d, V, xr, T0 + ROT, gv);
-    steps_full<G, ROT + 1>(d, V, xr, T0, gv);
+    step_full<G, ROT, IN>(d, V, xr, T0 + ROT, cb);
+    steps_full<G, ROT + 1, IN>(d, V, xr, T0, cb);
   }
 }
 
@@ -167,6 +168,11 @@ __global__ __launch_bounds__(256) void dtw_kernel(const float* __restrict__ q,
   const int Lv = span / G, gv = span % G;
   d.clampLane = L == Lv;
   const int L0 = r / G, g0 = r % G;  // slot of offset 0 (holds D(-1,-1) = 0)
+  // the first offset past the band (slot gv of lane Lv) stays +inf: its cost
+  // gets +inf added; every other cell adds 0 (exact: all values are >= 0)
+  float cb[G];
+#pragma unroll
+  for (int g = 0; g < G; ++g) cb[g] = (d.clampLane && g == gv) ? kInf : 0.0f;
   // At step T lane L is on row i = T - L; its x ring holds x[i + o] for its G
   // offsets o, so at T = 0 (row -L) it starts at x[L(G-1) - r + g].
   float V[G], xr[G];
@@ -179,13 +185,25 @@ __global__ __launch_bounds__(256) void dtw_kernel(const float* __restrict__ q,
   const int Ttot = lq + kPrologue;
   int T = 0;
   const int p_end = kPrologue < lq ? kPrologue : lq;
-  for (; T < p_end; ++T) step_masked<G>(d, V, xr, T, gv);
+  for (; T < p_end; ++T) step_masked<G>(d, V, xr, T, cb);
   if (T == kPrologue) {
     const int full = (lq - kPrologue) / G * G;
-    for (int T0 = kPrologue; T0 < kPrologue + full; T0 += G) steps_full<G, 0>(d, V, xr, T0, gv);
-    T = kPrologue + full;
+    const int T_end = kPrologue + full;
+    // At step T lane L loads x[T + L(G-1) - r + G].  Over a block of G steps
+    // from T0 the indices span [T0 - r + G, T0 + 17G - 16 - r] (lanes 0 and
+    // 15), inside [0, min(lx, lq)) -- every lane's x, a borrowed query of
+    // length lq included, is that long -- when T0 >= r - G and
+    // T0 <= min(lx, lq) + 15 - 17G + r.
+    const int lmin = lx < lq ? lx : lq;
+    const int in_lo = r - G;
+    const int in_hi = lmin + (kSegLanes - 1) - (kSegLanes + 1) * G + r;  // last T0 allowed
+    int T0 = kPrologue;
+    for (; T0 < T_end && T0 < in_lo; T0 += G) steps_full<G, 0, false>(d, V, xr, T0, cb);
+    for (; T0 < T_end && T0 <= in_hi; T0 += G) steps_full<G, 0, true>(d, V, xr, T0, cb);
+    for (; T0 < T_end; T0 += G) steps_full<G, 0, false>(d, V, xr, T0, cb);
+    T = T_end;
   }
-  for (; T < Ttot; ++T) step_masked<G>(d, V, xr, T, gv);
+  for (; T < Ttot; ++T) step_masked<G>(d, V, xr, T, cb);
 
   // D(lq-1, lx-1) sits at offset lx - lq
   const int of = lx - lq;
