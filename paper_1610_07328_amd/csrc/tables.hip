@@ -34,7 +34,16 @@ __global__ __launch_bounds__(256) void band_keys_kernel(const uint64_t* __restri
       continue;
     }
     uint64_t k = mix64(seed + (uint64_t)(l + 1) * 0x9E3779B97F4A7C15ull);
-    for (int t = 0; t < K; ++t) k = mix64(k ^ h[t]);
+    int t = 0;
+    if ((((uintptr_t)h) & 15) == 0) {  // 16-byte aligned band: two values per load
+      const ulonglong2* h2 = reinterpret_cast<const ulonglong2*>(h);
+      for (; t + 2 <= K; t += 2) {
+        const ulonglong2 v = h2[t / 2];
+        k = mix64(k ^ v.x);
+        k = mix64(k ^ v.y);
+      }
+    }
+    for (; t < K; ++t) k = mix64(k ^ h[t]);
     keys[g] = k == SSH_KEY_EMPTY ? SSH_KEY_EMPTY - 1 : k;
   }
 }
