@@ -66,15 +66,16 @@ constexpr int kRsWaves = kRsThreads / kWave;
 constexpr int kRsPerWave = kWave * kRsItems;   // 1024 contiguous elements per wave
 
 struct RsIn {
-  const uint64_t* keys;  // pass 0: series-major [N * L]; later: table-major [L * N]
+  const uint64_t* keys;  // series-major [N * L] when sm, else table-major [L * N]
   const uint32_t* ids;   // null on pass 0 (ids are the series index)
   bool first;
+  bool sm;
 };
 
 __device__ __forceinline__ void rs_load(const RsIn in, int64_t e, int64_t N, int L, int l,
                                         uint64_t& key, uint32_t& id) {
   if (in.first) {
-    key = in.keys[e * L + l];
+    key = in.sm ? in.keys[e * L + l] : in.keys[(int64_t)l * N + e];
     id = (uint32_t)e;
   } else {
     key = in.keys[(int64_t)l * N + e];
@@ -273,6 +274,26 @@ __global__ __launch_bounds__(kRsThreads) void rs_scatter_kernel(RsIn in, int64_t
   }
 }
 
+// keys [N][L] -> out [L][N] through an LDS tile of kTrRows series, so both
+// the reads and the writes are contiguous (L <= kTrMaxL)
+constexpr int kTrRows = 64;
+constexpr int kTrMaxL = 64;
+
+__global__ __launch_bounds__(256) void keys_transpose_kernel(const uint64_t* __restrict__ keys,
+                                                             int64_t N, int L,
+                                                             uint64_t* __restrict__ out) {
+  __shared__ uint64_t tile[kTrRows * kTrMaxL];
+  const int64_t s0 = (int64_t)blockIdx.x * kTrRows;
+  const int rows = N - s0 < kTrRows ? (int)(N - s0) : kTrRows;
+  const int n = rows * L;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) tile[i] = keys[s0 * L + i];
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const int l = i / rows, r = i - l * rows;
+    out[(int64_t)l * N + s0 + r] = tile[r * L + l];
+  }
+}
+
 static inline size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 constexpr int kRsMaxSeg = 64;  // scan segments per table
@@ -305,22 +326,27 @@ ssh_status table_build_launch(const uint64_t* keys, int64_t N, int L, uint64_t* 
   const int64_t seg = (ceil_div(n, nseg) + 3) & ~(int64_t)3;
   nseg = (int)ceil_div(n, seg);
   const dim3 sgrid(nseg, L);
-  // passes: keys -> alt -> tab -> alt -> tab
+  // With L <= kTrMaxL the keys are first transposed into tab_keys, so every
+  // pass reads table-major: (keys ->) tab -> alt -> tab -> alt -> tab.
+  // Otherwise pass 0 reads the series-major keys: keys -> alt -> tab -> alt -> tab.
+  const bool transposed = L <= kTrMaxL;
+  if (transposed)
+    keys_transpose_kernel<<<(unsigned)ceil_div(N, kTrRows), 256, 0, stream>>>(keys, N, L, tab_keys);
   for (int pass = 0; pass < 4; ++pass) {
     const int shift = 32 + 8 * pass;
     RsIn in;
     uint64_t* ok;
     uint32_t* oi;
     if (pass == 0) {
-      in = RsIn{keys, nullptr, true};
+      in = transposed ? RsIn{tab_keys, nullptr, true, false} : RsIn{keys, nullptr, true, true};
       ok = alt_keys;
       oi = alt_ids;
     } else if (pass % 2 == 1) {
-      in = RsIn{alt_keys, alt_ids, false};
+      in = RsIn{alt_keys, alt_ids, false, false};
       ok = tab_keys;
       oi = tab_ids;
     } else {
-      in = RsIn{tab_keys, tab_ids, false};
+      in = RsIn{tab_keys, tab_ids, false, false};
       ok = alt_keys;
       oi = alt_ids;
     }
