@@ -8,6 +8,8 @@ any size:
 * every query's candidates are exactly the first C members of its retrieved
   set, ranked by (shared hash values desc, id asc), which torch recomputes from
   the same keys and hash values.
+The DTW re-rank is checked on seeded random candidates (drawn here, not taken
+from the probe) in the re-rank's launch shape.
 
 Workloads: the batched index build (1,000,000 random walks x 1024, W=80,
 delta=3, n=15, K=L=10, 1,000 queries, C=50, 5 % band), the uneven batch (series
@@ -115,18 +117,29 @@ def _check_probe(qb: QueryBatch, qsel, C: int, H: int):
         assert np.all(cand[q, ncand[q]:] == -1), q
 
 
-def _check_rerank(qb: QueryBatch, Qx, Qoff, x, off, p: Params, qsel):
-    """DTW top-k of sampled queries against the oracle on the same candidates."""
-    cand = qb.cand.cpu().numpy()[qsel]
-    ncand = qb.ncand.cpu().numpy()[qsel]
-    ids = qb.ids.cpu().numpy()[qsel]
-    dist = qb.dist.cpu().numpy()[qsel]
+def _check_rerank(ssh, qh: HashBatch, db: HashBatch, Qx, Qoff, x, off, p: Params, qsel, seed):
+    """DTW top-k of sampled queries on seeded random candidates, against the oracle.
+
+    The kernel and launch shape are the re-rank's (queries x C candidates);
+    the candidates are drawn here, independently of the probe's output.
+    """
+    rng = np.random.default_rng(seed)
+    nq = len(qsel)
+    cand = rng.integers(0, db.N, size=(nq, p.C)).astype(np.int64)
+    ncand = rng.integers(p.C // 2, p.C + 1, size=nq).astype(np.int32)
+    ncand[0] = p.C
     qs = [Qx[Qoff[q]:Qoff[q + 1]] for q in qsel]
-    qoff = np.zeros(len(qsel) + 1, np.int64)
+    qoff = np.zeros(nq + 1, np.int64)
     np.cumsum([len(v) for v in qs], out=qoff[1:])
     qx = np.concatenate(qs).astype(np.float32)
+    ids, dist = ssh.dtw_rerank(torch.as_tensor(qx).cuda(), torch.as_tensor(qoff).cuda(), db.x,
+                               db.x_off, torch.as_tensor(cand).cuda(),
+                               torch.as_tensor(ncand).cuda(), p.band_frac, len(qs[0]),
+                               int(off[1] - off[0]), p.k)
+    torch.cuda.synchronize()
+    ssh.check_device_errors()
     oids, odist, all_d = oracle.rerank(qx, qoff, x, off, cand, ncand, p.band_frac, p.k)
-    compare_rerank(ids, dist, oids, odist, all_d, cand, ncand)
+    compare_rerank(ids.cpu().numpy(), dist.cpu().numpy(), oids, odist, all_d, cand, ncand)
 
 
 def _run_index_and_queries(ssh, X, Q, p: Params, seed: int):
@@ -178,7 +191,7 @@ def test_index_build_workload_sampled(ssh):
     qsel = _query_sample(qb, rng, 16)
     _check_sampled_hash(qh, qx, qoff, r, draws, p, qsel)
     _check_probe(qb, range(nq), p.C, p.H)
-    _check_rerank(qb, qx, qoff, x, off, p, qsel)
+    _check_rerank(ssh, qh, db, qx, qoff, x, off, p, qsel, seed=2)
 
 
 def test_uneven_batch_sampled(ssh):
@@ -220,4 +233,4 @@ def test_large_config_shape_sampled(ssh):
     qsel = _query_sample(qb, rng, 6)
     _check_sampled_hash(qh, qx, qoff, r, draws, p, qsel)
     _check_probe(qb, range(nq), p.C, p.H)
-    _check_rerank(qb, qx, qoff, x, off, p, qsel)
+    _check_rerank(ssh, qh, db, qx, qoff, x, off, p, qsel, seed=2)
