@@ -45,8 +45,8 @@ MEASURED_TRAFFIC = {
     #          fetch scale, write scale); the 1 GiB copy read 524306.9 KiB on
     #          FETCH_SIZE and 1048576 KiB on WRITE_SIZE
     "cws_kernel": ("paper_1610_07328_amd/csrc/cws.hip",
-                   "47a5c57de71ecccd235f3560662f4697812fbf1d2a02e97c9e4a2e5a23267e6f",
-                   6023714.875, 792109.6875, 1048576.0 / 524306.9375, 1.0),
+                   "c62c383c0c2e5fb3d44f58c3087d64ffa7260939781f4bce7ad22ac1ad934809",
+                   5859053.8125, 793223.59375, 1048576.0 / 524306.9375, 1.0),
 }
 
 

@@ -126,7 +126,7 @@ ssh_status ssh_shingle(const uint64_t* bits, const int64_t* bit_word_off, const 
 /* Random numbers of consistent weighted sampling, one triple per (token k,
  * hash j), code-major: element [k * H + j] of each array.  They are inputs,
  * drawn by the caller: r ~ Gamma(2,1) (0 < r < 1e5), lnc = ln c with
- * c ~ Gamma(2,1), beta ~ U[0,1).  a1, lnS, k16 and p2 are scratch tables the
+ * c ~ Gamma(2,1), beta ~ U[0,1).  a1, lnS and k16 are scratch tables the
  * caller allocates and fills once with ssh_cws_prepare. */
 typedef struct {
   int32_t n;          /* token length; tables have 2^n rows */
@@ -139,7 +139,6 @@ typedef struct {
   uint16_t* k16;      /* [(3 * 2^n + 1) * H2], H2 = H rounded up to even:
                          prepared 16-bit monotone keys of ln a for weights
                          1, 2, 3, then one padding row */
-  float* p2;          /* [2^n * H] prepared: a float32 lower bound of ln c - r */
 } ssh_cws_tables;
 
 /* Fill tab->a1 and tab->lnS from the draws (device work on `stream`).

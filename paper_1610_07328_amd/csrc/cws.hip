@@ -24,9 +24,12 @@
 //     order, so equal keys resolve to the earlier token.  If the smallest key
 //     is shared by two tokens (rare), the lane evaluates exactly the keyed
 //     tokens holding that key.
-//  B. tokens of weight >= 4, in batches: ln a >= (ln c - r) - ln S, so a
-//     float32 lower bound of ln c - r rules most of them out; the rest are
-//     evaluated exactly and compared by (ln a, k) with the pass-A winner.
+//  B. tokens of weight >= 4 (about 1 % of a series' tokens): pass A lists
+//     up to 64 of them in LDS with their ln S (beyond that, pass B relists
+//     them one chunk at a time); every lane evaluates each of them exactly
+//     for its two hashes and compares by (ln a, k) with the pass-A winner.
+//     No cheaper bound pays here: with 100 hashes per series some lane almost
+//     always fails any bound, and the wave then pays for both.
 #include <cmath>
 
 #include "common.hpp"
@@ -131,20 +134,8 @@ __device__ __forceinline__ double lnS_of(const double* lnS, uint32_t c) {
 
 // ---------------------------------------------------------------------------
 // prepare: lnS table, the weight-1 ln a of every (k, j), 16-bit keys of ln a
-// for weights 1..3, and a float32 lower bound of ln c - r
+// for weights 1..3
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ float f32_round_down(double v) {
-  float f = (float)v;
-  if ((double)f > v) {  // step to the next float32 below f
-    uint32_t b = __builtin_bit_cast(uint32_t, f);
-    if (f > 0.0f) b -= 1u;
-    else if (f < 0.0f) b += 1u;
-    else b = 0x80000001u;  // -smallest subnormal
-    f = __builtin_bit_cast(float, b);
-  }
-  return f;
-}
-
 // Monotone non-decreasing 16-bit key of ln a.  For a token of weight S,
 // a ~ Exp(S), so for S <= 3 the range [-16, 4) holds ln a with probability
 // 1 - 1e-6; values outside saturate (they only cost exact tie checks).  Keys
@@ -161,7 +152,7 @@ __device__ __forceinline__ uint32_t key16(double la) {
 __global__ __launch_bounds__(256) void cws_prepare_kernel(
     const double* __restrict__ r, const double* __restrict__ lnc, const double* __restrict__ beta,
     int64_t rows, int H, int H2, double* __restrict__ a1, uint16_t* __restrict__ k16,
-    float* __restrict__ p2, double* __restrict__ lnS, int* err) {
+    double* __restrict__ lnS, int* err) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t cells = rows * H2;
   // the same correctly rounded values as the lnS table entries 2 and 3
@@ -188,7 +179,6 @@ __global__ __launch_bounds__(256) void cws_prepare_kernel(
     k16[c] = (uint16_t)key16(a);
     k16[cells + c] = (uint16_t)key16(icws_ln_a(rr, bb, lc, ln2, tt));
     k16[2 * cells + c] = (uint16_t)key16(icws_ln_a(rr, bb, lc, ln3, tt));
-    p2[i] = f32_round_down(lc - rr);
   }
   // one extra row of 0xFFFF keys after the three weight tables: padding
   // entries of a key list point at it and never change a running minimum
@@ -208,12 +198,12 @@ struct CwsDev {
   const double* a1;
   const double* lnS;
   const uint16_t* k16;  // [3 * 2^n + 1][H2] keys; the last row is padding
-  const float* p2;
   int H, H2, n;
 };
 
 constexpr int kCwsWaves = 4;  // wavefronts per workgroup
 constexpr int kPassA = 8;     // keyed tokens whose keys are loaded together
+constexpr int kHeavyCap = 64; // heavy tokens listed per series in LDS
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 
 // median of three; with a <= b it is the second smallest of {a, b, c}
@@ -221,15 +211,6 @@ __device__ __forceinline__ uint32_t med3(uint32_t a, uint32_t b, uint32_t c) {
   uint32_t m;
   asm("v_med3_u32 %0, %1, %2, %3" : "=v"(m) : "v"(a), "v"(b), "v"(c));
   return m;
-}
-
-// A token of weight S >= 4 has ln a = ln c - r (t - beta + 1) with
-// t <= ln S / r + beta, so ln a >= (ln c - r) - ln S.  The float32 table p2
-// holds a value <= ln c - r; the slack covers the float64 rounding of the
-// bound and of ln a itself (r < 1e5).
-__device__ __forceinline__ double heavy_bound(float p2v, double ls) {
-  const double b = (double)p2v - ls;
-  return b - 1.0e-9 * (1.0 + __builtin_fabs(b) + ls);
 }
 
 __device__ __forceinline__ double exact_ln_a(const CwsDev& t, uint32_t k, uint32_t c, int j,
@@ -256,7 +237,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) void c
   // per wave: keyed-token list (row byte offset, position), padded to whole
   // groups with the padding row, and the heavy-token list (position)
   __shared__ uint4 klist[kCwsWaves][kWave / 2];
-  __shared__ uint32_t hlist[kCwsWaves][kWave];
+  // heavy tokens of the series: (code, count, ln count as two words)
+  __shared__ uint4 hl[kCwsWaves][kHeavyCap];
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave-uniform
   const int lane = lane_id();
   const int H = t.H;
@@ -286,8 +268,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) void c
       bool done[2] = {!v0, !v1};
       bool any_heavy = false;
       if (D <= 0xFFFF) {
-        // ---- pass A over tokens of weight 1..3 ----
+        // ---- pass A over tokens of weight 1..3; heavy tokens are listed ----
         uint32_t m1[2] = {kNone, kNone}, m2[2] = {kNone, kNone};
+        int nhl = 0;  // heavy tokens seen; listed while nhl <= kHeavyCap
         for (int d0 = 0; d0 < D; d0 += kWave) {
           const int nc = D - d0 < kWave ? D - d0 : kWave;
           const bool have = lane < nc;
@@ -295,7 +278,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) void c
           const uint32_t mcnt = have ? counts_s[d0 + lane] : 0u;
           const bool keyed = have && mcnt <= 3u;
           const uint64_t km = ballot64(keyed);
-          any_heavy |= ballot64(have && mcnt > 3u) != 0;
+          const bool heavy = have && mcnt > 3u;
+          const uint64_t hmk = ballot64(heavy);
+          if (heavy && nhl + (int)__builtin_popcountll(hmk) <= kHeavyCap) {
+            const double ls = lnS_of(t.lnS, mcnt);
+            const uint64_t lb = __builtin_bit_cast(uint64_t, ls);
+            hl[w][nhl + __builtin_popcountll(hmk & lt_mask)] =
+                make_uint4(mcode, mcnt, (uint32_t)lb, (uint32_t)(lb >> 32));
+          }
+          nhl += __builtin_popcountll(hmk);
+          any_heavy |= hmk != 0;
           const int nk = __builtin_popcountll(km);
           const int nkp = (nk + kPassA - 1) & ~(kPassA - 1);
           if (keyed) {
@@ -379,29 +371,38 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) void c
         }
         // ---- pass B over tokens of weight >= 4 ----
         if (any_heavy) {
-          for (int d0 = 0; d0 < D; d0 += kWave) {
-            const int nc = D - d0 < kWave ? D - d0 : kWave;
-            const bool have = lane < nc;
-            const uint32_t mcnt = have ? counts_s[d0 + lane] : 0u;
-            const bool heavy = have && mcnt > 3u;
-            const uint64_t hm = ballot64(heavy);
-            if (heavy) hlist[w][__builtin_popcountll(hm & lt_mask)] = (uint32_t)(d0 + lane);
-            wave_sync_lds();
-            const int nh = __builtin_popcountll(hm);
-            for (int i = 0; i < nh; ++i) {
-              const uint32_t p = hlist[w][i];
-              const uint32_t k = codes_s[p], c = counts_s[p];
-              const double ls = lnS_of(t.lnS, c);
+          // the list built in pass A when it holds every heavy token; else the
+          // heavy tokens of one chunk at a time
+          const bool listed = nhl <= kHeavyCap;
+          for (int d0 = 0; d0 < (listed ? 1 : D); d0 += kWave) {
+            int cnt = nhl;
+            if (!listed) {
+              const int nc = D - d0 < kWave ? D - d0 : kWave;
+              const bool have = lane < nc;
+              const uint32_t mcode = have ? codes_s[d0 + lane] : 0u;
+              const uint32_t mcnt = have ? counts_s[d0 + lane] : 0u;
+              const bool heavy = have && mcnt > 3u;
+              const uint64_t hm = ballot64(heavy);
+              if (heavy) {
+                const uint64_t lb = __builtin_bit_cast(uint64_t, lnS_of(t.lnS, mcnt));
+                hl[w][__builtin_popcountll(hm & lt_mask)] =
+                    make_uint4(mcode, mcnt, (uint32_t)lb, (uint32_t)(lb >> 32));
+              }
+              cnt = __builtin_popcountll(hm);
+              wave_sync_lds();
+            }
+            for (int i = 0; i < cnt; ++i) {
+              const uint4 e = hl[w][i];
+              const uint32_t k = e.x;
+              const double ls = __builtin_bit_cast(double, ((uint64_t)e.w << 32) | e.z);
               const int64_t row = (int64_t)k * H;
 #pragma unroll
               for (int h = 0; h < 2; ++h) {
                 if (done[h]) continue;
                 const int j = h ? j1 : j0;
-                if (heavy_bound(t.p2[row + j], ls) < b[h].la) {
-                  double tt;
-                  const double la = icws_ln_a(t.r[row + j], t.beta[row + j], t.lnc[row + j], ls, tt);
-                  if (la < b[h].la || (la == b[h].la && k < b[h].k)) b[h] = Best{la, k, tt};
-                }
+                double tt;
+                const double la = icws_ln_a(t.r[row + j], t.beta[row + j], t.lnc[row + j], ls, tt);
+                if (la < b[h].la || (la == b[h].la && k < b[h].k)) b[h] = Best{la, k, tt};
               }
             }
             wave_sync_lds();
@@ -447,7 +448,7 @@ ssh_status cws_prepare_launch(const ssh_cws_tables* tab, hipStream_t stream) {
   const int64_t rows = (int64_t)1 << tab->n;
   const int H2 = tab->H + (tab->H & 1);
   cws_prepare_kernel<<<grid_for(rows * H2, 256, 4096), 256, 0, stream>>>(
-      tab->r, tab->lnc, tab->beta, rows, tab->H, H2, tab->a1, tab->k16, tab->p2, tab->lnS, err);
+      tab->r, tab->lnc, tab->beta, rows, tab->H, H2, tab->a1, tab->k16, tab->lnS, err);
   return check_launch("ssh_cws_prepare");
 }
 
@@ -462,8 +463,7 @@ ssh_status cws_launch(const uint32_t* codes, const uint32_t* counts, const int64
   // the key table is addressed by 32-bit byte offsets through a buffer resource
   if (((3ll << tab->n) + 1) * H2 * 2 >= (1ll << 31))
     return fail(SSH_EUNSUPPORTED, "ssh_cws: key table of 2 GiB or more");
-  CwsDev t{tab->r, tab->lnc, tab->beta, tab->a1, tab->lnS,
-           tab->k16, tab->p2, tab->H, H2, tab->n};
+  CwsDev t{tab->r, tab->lnc, tab->beta, tab->a1, tab->lnS, tab->k16, tab->H, H2, tab->n};
   cws_kernel<<<grid_for(N, kCwsWaves, 1 << 16), 256, 0, stream>>>(codes, counts, hist_off,
                                                                    n_distinct, N, t, hv, err);
   return check_launch("ssh_cws");

@@ -38,7 +38,7 @@ class SSHError(RuntimeError):
 
 class _CwsTablesC(ctypes.Structure):
     _fields_ = [("n", _i32), ("H", _i32), ("r", _vp), ("lnc", _vp), ("beta", _vp),
-                ("a1", _vp), ("lnS", _vp), ("k16", _vp), ("p2", _vp)]
+                ("a1", _vp), ("lnS", _vp), ("k16", _vp)]
 
 
 # name -> (restype, argtypes); mirrors include/ssh.h
@@ -188,7 +188,7 @@ def shingle(bits, bit_word_off, nbits, n: int, hist_off, out=None):
 
 
 class CwsTables:
-    """Device copies of the ICWS draws plus the prepared a1 / lnS tables."""
+    """Device copies of the ICWS draws plus the prepared a1, lnS and key tables."""
 
     def __init__(self, r: np.ndarray, lnc: np.ndarray, beta: np.ndarray, n: int,
                  device="cuda"):
@@ -203,10 +203,8 @@ class CwsTables:
         self.a1 = torch.empty((D, H), **f64)
         self.lnS = torch.empty(LNS_ENTRIES, **f64)
         self.k16 = torch.empty((3 * D + 1, H + (H & 1)), dtype=torch.int16, device=device)
-        self.p2 = torch.empty((D, H), dtype=torch.float32, device=device)
         self._c = _CwsTablesC(n, H, self.r.data_ptr(), self.lnc.data_ptr(), self.beta.data_ptr(),
-                              self.a1.data_ptr(), self.lnS.data_ptr(), self.k16.data_ptr(),
-                              self.p2.data_ptr())
+                              self.a1.data_ptr(), self.lnS.data_ptr(), self.k16.data_ptr())
         _check(lib().ssh_cws_prepare(ctypes.byref(self._c), _stream()), "ssh_cws_prepare")
 
 

@@ -97,7 +97,7 @@ def test_validation_rejects_without_device_work(ssh):
     # empty batches are not errors
     assert L.ssh_sketch(None, None, 0, r.ctypes.data, 8, 1, None, None, None, None, None) == 0
     # CWS tables with n out of range
-    t = ssh._CwsTablesC(17, 4, 16, 16, 16, 16, 16, 16, 16)
+    t = ssh._CwsTablesC(17, 4, 16, 16, 16, 16, 16, 16)
     assert L.ssh_cws_prepare(ctypes.byref(t), None) == EINVAL
     assert L.ssh_status_str(EUNSUP) == b"SSH_EUNSUPPORTED"
 
