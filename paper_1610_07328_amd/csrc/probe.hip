@@ -1,5 +1,5 @@
-// Query probe (Algorithm 2: "add all the time series in the probed bucket to
-// R", for every hash table), then ranking of R.
+// Query probe (Algorithm 2: the retrieved set R is the union, over the hash
+// tables, of the query's bucket in each), then ranking of R.
 //
 // One workgroup per query.
 //  1. Per table, two binary searches find the run of entries whose high key

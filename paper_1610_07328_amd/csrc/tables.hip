@@ -1,10 +1,11 @@
-// Band keys and hash tables (Algorithm 1, "hash each time series into d
-// different hash tables").
+// Band keys and hash tables (Algorithm 1: every series goes into each of the
+// L hash tables under one key per table).
 //
 // Keys: table l folds its K hash values with the SplitMix64 output function.
-// Tables: per table, a stable LSD radix sort of (key, id) on the high 32 bits
-// of the key, four 8-bit digit passes.  Each pass is three launches over all
-// tables at once: per-tile digit histograms, an exclusive scan of the
+// Tables: the keys [N][L] are first transposed to table-major [L][N]; then,
+// per table, a stable LSD radix sort of (key, id) on the high 32 bits of the
+// key, four 8-bit digit passes.  Each pass is four launches over all tables at
+// once: per-tile digit histograms, a segmented reduce and then scan of the
 // (digit, tile) counts, and a stable scatter.  The scatter ranks elements
 // inside a wavefront with a ballot-based match of equal digits, keeps one
 // running count per (wave, digit) in LDS, reorders the tile in LDS and writes
