@@ -56,6 +56,8 @@ typedef int32_t ssh_status;
 #define SSH_MAX_W 256            /* longest supported filter                */
 #define SSH_MAX_N 16             /* longest supported shingle               */
 #define SSH_LNS_ENTRIES 65536    /* entries of the prepared ln-count table  */
+#define SSH_CWS_KEY_WEIGHTS 7    /* weights keyed for every token code      */
+#define SSH_CWS_RUN_CAP 4096     /* counts keyed for the codes 0 and 2^n-1  */
 #define SSH_MAX_C 4096           /* largest candidate cap of ssh_probe      */
 #define SSH_MAX_K 1024           /* largest k of dtw_rerank                 */
 #define SSH_MAX_BAND 255         /* largest Sakoe-Chiba radius of dtw_rerank */
@@ -136,13 +138,18 @@ typedef struct {
   const double* beta; /* [2^n * H] */
   double* a1;         /* [2^n * H] prepared: ln a of a token of weight 1 */
   double* lnS;        /* [SSH_LNS_ENTRIES] prepared: correctly rounded ln s */
-  uint16_t* k16;      /* [(3 * 2^n + 1) * H2], H2 = H rounded up to even:
-                         prepared 16-bit monotone keys of ln a for weights
-                         1, 2, 3, then one padding row */
+  uint16_t* k16;      /* [R * H2], H2 = H rounded up to even and
+                         R = SSH_CWS_KEY_WEIGHTS * 2^n + 2 * SSH_CWS_RUN_CAP + 1:
+                         prepared 16-bit monotone keys of ln a, one row per
+                         (code, weight 1..SSH_CWS_KEY_WEIGHTS), then rows for
+                         the codes 0 and 2^n - 1 at weights 1..SSH_CWS_RUN_CAP,
+                         then one padding row; R * H2 * 2 must stay below 2^31 */
 } ssh_cws_tables;
 
-/* Fill tab->a1 and tab->lnS from the draws (device work on `stream`).
- * tab is a [host] struct of device pointers. */
+/* Fill tab->a1, tab->lnS and tab->k16 from the draws (device work on
+ * `stream`).  tab is a [host] struct of device pointers.  A draw outside the
+ * ranges above raises a device flag that ssh_check_device_errors reports.
+ * Returns SSH_EINVAL for n outside 1..SSH_MAX_N, H < 1 or a null pointer. */
 ssh_status ssh_cws_prepare(const ssh_cws_tables* tab, void* stream);
 
 /* Weighted MinHash of every weighted set (Section 4.3), by Ioffe's improved

@@ -16,20 +16,20 @@
 // One wavefront hashes one series, each lane two hashes.  The exact argmin is
 // found in two passes whose combination equals the first minimum of the
 // ascending float64 scan, i.e. the lexicographic minimum of (ln a, k):
-//  A. tokens of weight 1, 2 or 3 (almost all of them): the prepare kernel
-//     stores, per (weight, token, hash), a 16-bit key that is a monotone
-//     (non-decreasing) quantisation of the exact ln a.  A strictly smaller key
-//     therefore means a strictly smaller ln a.  Each lane keeps the smallest
-//     and second-smallest (key << 16 | position); position order is token
-//     order, so equal keys resolve to the earlier token.  If the smallest key
-//     is shared by two tokens (rare), the lane evaluates exactly the keyed
-//     tokens holding that key.
-//  B. tokens of weight >= 4 (about 1 % of a series' tokens): pass A lists
-//     up to 64 of them in LDS with their ln S (beyond that, pass B relists
-//     them one chunk at a time); every lane evaluates each of them exactly
-//     for its two hashes and compares by (ln a, k) with the pass-A winner.
-//     No cheaper bound pays here: with 100 hashes per series some lane almost
-//     always fails any bound, and the wave then pays for both.
+//  A. keyed tokens (all of them in practice): tokens of weight 1..7, and
+//     the two run codes 0 and 2^n - 1 (which collect the constant stretches of
+//     the bit stream and alone reach large weights) up to weight 4096.  The
+//     prepare kernel stores, per (key row, hash), a 16-bit key that is a
+//     monotone (non-decreasing) quantisation of the exact ln a.  A strictly
+//     smaller key therefore means a strictly smaller ln a.  Each lane keeps
+//     the smallest and second-smallest (key << 16 | position); position order
+//     is token order, so equal keys resolve to the earlier token.  If the
+//     smallest key is shared by two tokens (rare), the lane evaluates exactly
+//     the keyed tokens holding that key.
+//  B. any other token (heavy): pass A lists up to 64 of them in LDS with
+//     their ln S (beyond that, pass B relists them one chunk at a time); every
+//     lane evaluates each of them exactly for its two hashes and compares by
+//     (ln a, k) with the pass-A winner, whose ln a is then evaluated exactly.
 #include <cmath>
 
 #include "common.hpp"
@@ -133,15 +133,35 @@ __device__ __forceinline__ double lnS_of(const double* lnS, uint32_t c) {
 }
 
 // ---------------------------------------------------------------------------
-// prepare: lnS table, the weight-1 ln a of every (k, j), 16-bit keys of ln a
-// for weights 1..3
+// prepare: lnS table, the weight-1 ln a of every (k, j), and the 16-bit keys
 // ---------------------------------------------------------------------------
 // Monotone non-decreasing 16-bit key of ln a.  For a token of weight S,
-// a ~ Exp(S), so for S <= 3 the range [-16, 4) holds ln a with probability
-// 1 - 1e-6; values outside saturate (they only cost exact tie checks).  Keys
-// stop at 0xFFFE so that no key equals the empty-minimum sentinel.
+// a ~ Exp(S), so ln a < -16 has probability about S * 1.1e-7; such values
+// saturate at key 0 and values above 4 at the top key (saturation only costs
+// exact tie checks).  Keys stop at 0xFFFE so that no key equals the
+// empty-minimum sentinel.
 constexpr double kKeyLo = -16.0;
 constexpr double kKeyScale = 65534.0 / 20.0;
+
+constexpr uint32_t kKeyW = SSH_CWS_KEY_WEIGHTS;  // weights keyed for every code
+constexpr uint32_t kRunCap = SSH_CWS_RUN_CAP;    // counts keyed for the two run codes
+constexpr uint32_t kNoRow = 0xFFFFFFFFu;
+
+// Rows of the key table: weight w (1..kKeyW) of code k at (w - 1) 2^n + k;
+// count c (1..kRunCap) of code 0 at kKeyW 2^n + c - 1 and of code 2^n - 1
+// (the tokens of constant runs in the bit stream, the only ones that reach
+// large weights) at kKeyW 2^n + kRunCap + c - 1; then one padding row.
+__host__ __device__ inline int64_t key_rows(int n) {
+  return ((int64_t)kKeyW << n) + 2 * (int64_t)kRunCap + 1;
+}
+
+// row of token (code, count c) or kNoRow when it is not keyed (c == 0 included)
+__device__ __forceinline__ uint32_t key_row(uint32_t code, uint32_t c, int n) {
+  if (c - 1u < kKeyW) return ((c - 1u) << n) + code;
+  if (c <= kRunCap && (code == 0u || code == (1u << n) - 1u))
+    return (kKeyW << n) + (code ? kRunCap : 0u) + c - 1u;
+  return kNoRow;
+}
 
 __device__ __forceinline__ uint32_t key16(double la) {
   const double q = __builtin_floor((la - kKeyLo) * kKeyScale);  // monotone steps
@@ -151,39 +171,44 @@ __device__ __forceinline__ uint32_t key16(double la) {
 
 __global__ __launch_bounds__(256) void cws_prepare_kernel(
     const double* __restrict__ r, const double* __restrict__ lnc, const double* __restrict__ beta,
-    int64_t rows, int H, int H2, double* __restrict__ a1, uint16_t* __restrict__ k16,
+    int n, int H, int H2, double* __restrict__ a1, uint16_t* __restrict__ k16,
     double* __restrict__ lnS, int* err) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t rows = key_rows(n);
   const int64_t cells = rows * H2;
-  // the same correctly rounded values as the lnS table entries 2 and 3
-  const double ln2 = ln_integer(2.0);
-  const double ln3 = ln_integer(3.0);
+  const uint32_t wrows = kKeyW << n;  // rows of the per-weight part
   for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < cells; c += stride) {
-    const int64_t k = c / H2;
-    const int j = (int)(c - k * H2);
-    if (j >= H) {  // padding column, never compared
+    const int64_t row = c / H2;
+    const int j = (int)(c - row * H2);
+    if (j >= H || row == rows - 1) {  // padding column or row, never wins a minimum
       k16[c] = 0xFFFF;
-      k16[cells + c] = 0xFFFF;
-      k16[2 * cells + c] = 0xFFFF;
       continue;
     }
-    const int64_t i = k * H + j;
+    uint32_t code, w;
+    if (row < wrows) {
+      code = (uint32_t)row & ((1u << n) - 1u);
+      w = (uint32_t)(row >> n) + 1u;
+    } else {
+      const uint32_t q = (uint32_t)(row - wrows);
+      code = q < kRunCap ? 0u : (1u << n) - 1u;
+      w = q % kRunCap + 1u;
+    }
+    const int64_t i = (int64_t)code * H + j;
     const double rr = r[i], bb = beta[i], lc = lnc[i];
-    // r is bounded so that the float64 rounding of ln a stays far below the
-    // pass-B slack (a Gamma(2,1) draw above 1e5 has probability ~e^-1e5)
-    if (!(rr > 0.0) || !(rr < 1.0e5) || !(bb >= 0.0) || !(bb < 1.0) || !(__builtin_fabs(lc) < 1.0e300))
-      atomicOr(err, 2);
+    // the same correctly rounded logarithm as the lnS table entry w
+    const double ls = w == 1u ? 0.0 : ln_integer((double)w);
     double tt;
-    const double a = icws_ln_a(rr, bb, lc, 0.0, tt);
-    a1[i] = a;
+    const double a = icws_ln_a(rr, bb, lc, ls, tt);
     k16[c] = (uint16_t)key16(a);
-    k16[cells + c] = (uint16_t)key16(icws_ln_a(rr, bb, lc, ln2, tt));
-    k16[2 * cells + c] = (uint16_t)key16(icws_ln_a(rr, bb, lc, ln3, tt));
+    if (row < (1 << n)) {  // weight 1: the ln a table and the range checks of the draws
+      a1[i] = a;
+      // r is bounded so that the float64 rounding of ln a stays far below the
+      // pass-B slack (a Gamma(2,1) draw above 1e5 has probability ~e^-1e5)
+      if (!(rr > 0.0) || !(rr < 1.0e5) || !(bb >= 0.0) || !(bb < 1.0) ||
+          !(__builtin_fabs(lc) < 1.0e300))
+        atomicOr(err, 2);
+    }
   }
-  // one extra row of 0xFFFF keys after the three weight tables: padding
-  // entries of a key list point at it and never change a running minimum
-  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < H2; c += stride)
-    k16[3 * cells + c] = 0xFFFF;
   for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < SSH_LNS_ENTRIES; s += stride)
     lnS[s] = s == 0 ? -INFINITY : ln_integer((double)s);
 }
@@ -197,7 +222,7 @@ struct CwsDev {
   const double* beta;
   const double* a1;
   const double* lnS;
-  const uint16_t* k16;  // [3 * 2^n + 1][H2] keys; the last row is padding
+  const uint16_t* k16;  // [key_rows(n)][H2] keys; the last row is padding
   int H, H2, n;
 };
 
@@ -243,7 +268,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) void c
   const int lane = lane_id();
   const int H = t.H;
   const uint32_t row_bytes = (uint32_t)t.H2 * 2u;
-  const uint32_t pad_row = (3u << t.n) * row_bytes;
+  const uint32_t pad_row = (uint32_t)(key_rows(t.n) - 1) * row_bytes;
   // bounds-checked view of the key table: a lane past H reads inside it
   const __amdgpu_buffer_rsrc_t ktab = __builtin_amdgcn_make_buffer_rsrc(
       (void*)t.k16, 0, (int)(pad_row + row_bytes), 0x00020000);
@@ -268,7 +293,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) void c
       bool done[2] = {!v0, !v1};
       bool any_heavy = false;
       if (D <= 0xFFFF) {
-        // ---- pass A over tokens of weight 1..3; heavy tokens are listed ----
+        // ---- pass A over keyed tokens; the others (heavy) are listed ----
         uint32_t m1[2] = {kNone, kNone}, m2[2] = {kNone, kNone};
         int nhl = 0;  // heavy tokens seen; listed while nhl <= kHeavyCap
         for (int d0 = 0; d0 < D; d0 += kWave) {
@@ -276,9 +301,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) void c
           const bool have = lane < nc;
           const uint32_t mcode = have ? codes_s[d0 + lane] : 0u;
           const uint32_t mcnt = have ? counts_s[d0 + lane] : 0u;
-          const bool keyed = have && mcnt <= 3u;
+          const uint32_t row = have ? key_row(mcode, mcnt, t.n) : kNoRow;
+          const bool keyed = row != kNoRow;
           const uint64_t km = ballot64(keyed);
-          const bool heavy = have && mcnt > 3u;
+          const bool heavy = have && !keyed;
           const uint64_t hmk = ballot64(heavy);
           if (heavy && nhl + (int)__builtin_popcountll(hmk) <= kHeavyCap) {
             const double ls = lnS_of(t.lnS, mcnt);
@@ -291,7 +317,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) void c
           const int nk = __builtin_popcountll(km);
           const int nkp = (nk + kPassA - 1) & ~(kPassA - 1);
           if (keyed) {
-            const uint32_t row = ((mcnt - 1u) << t.n) + mcode;  // row of the key table
             klist2[__builtin_popcountll(km & lt_mask)] = make_uint2(row * row_bytes, (uint32_t)(d0 + lane));
           }
           // slots nk..nkp-1 are padding (keys 0xFFFF, position 0xFFFF: kNone);
@@ -357,10 +382,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) void c
             Best e{INFINITY, 0u, 0.0};
             for (int d = 0; d < D; ++d) {
               const uint32_t c = counts_s[d];
-              if (c > 3u) continue;
               const uint32_t k = codes_s[d];
-              const int64_t krow = (int64_t)(((c - 1u) << t.n) + k);
-              if ((uint32_t)t.k16[krow * t.H2 + j] != K) continue;
+              const uint32_t krow = key_row(k, c, t.n);
+              if (krow == kNoRow || (uint32_t)t.k16[(int64_t)krow * t.H2 + j] != K) continue;
               double tt;
               const double la = exact_ln_a(t, k, c, j, tt);
               if (la < e.la) e = Best{la, k, tt};
@@ -381,7 +405,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) void c
               const bool have = lane < nc;
               const uint32_t mcode = have ? codes_s[d0 + lane] : 0u;
               const uint32_t mcnt = have ? counts_s[d0 + lane] : 0u;
-              const bool heavy = have && mcnt > 3u;
+              const bool heavy = have && key_row(mcode, mcnt, t.n) == kNoRow;
               const uint64_t hm = ballot64(heavy);
               if (heavy) {
                 const uint64_t lb = __builtin_bit_cast(uint64_t, lnS_of(t.lnS, mcnt));
@@ -445,10 +469,9 @@ ssh_status cws_prepare_launch(const ssh_cws_tables* tab, hipStream_t stream) {
   int* err = nullptr;
   if (hipGetSymbolAddress((void**)&err, HIP_SYMBOL(g_cws_err)) != hipSuccess)
     return fail(SSH_EDEVICE, "ssh_cws_prepare: cannot resolve error flag");
-  const int64_t rows = (int64_t)1 << tab->n;
   const int H2 = tab->H + (tab->H & 1);
-  cws_prepare_kernel<<<grid_for(rows * H2, 256, 4096), 256, 0, stream>>>(
-      tab->r, tab->lnc, tab->beta, rows, tab->H, H2, tab->a1, tab->k16, tab->lnS, err);
+  cws_prepare_kernel<<<grid_for(key_rows(tab->n) * H2, 256, 4096), 256, 0, stream>>>(
+      tab->r, tab->lnc, tab->beta, tab->n, tab->H, H2, tab->a1, tab->k16, tab->lnS, err);
   return check_launch("ssh_cws_prepare");
 }
 
@@ -461,7 +484,7 @@ ssh_status cws_launch(const uint32_t* codes, const uint32_t* counts, const int64
     return fail(SSH_EDEVICE, "ssh_cws: cannot resolve error flag");
   const int H2 = tab->H + (tab->H & 1);
   // the key table is addressed by 32-bit byte offsets through a buffer resource
-  if (((3ll << tab->n) + 1) * H2 * 2 >= (1ll << 31))
+  if (key_rows(tab->n) * H2 * 2 >= (1ll << 31))
     return fail(SSH_EUNSUPPORTED, "ssh_cws: key table of 2 GiB or more");
   CwsDev t{tab->r, tab->lnc, tab->beta, tab->a1, tab->lnS, tab->k16, tab->H, H2, tab->n};
   cws_kernel<<<grid_for(N, kCwsWaves, 1 << 16), 256, 0, stream>>>(codes, counts, hist_off,

@@ -22,6 +22,8 @@ LIB_PATH = os.path.join(_HERE, "libssh_hip.so")
 HV_EMPTY = (1 << 64) - 1
 KEY_EMPTY = (1 << 64) - 1
 LNS_ENTRIES = 65536
+CWS_KEY_WEIGHTS = 7
+CWS_RUN_CAP = 4096
 MAX_C = 4096
 
 _vp = ctypes.c_void_p
@@ -202,7 +204,8 @@ class CwsTables:
         self.beta = torch.as_tensor(np.ascontiguousarray(beta), **f64)
         self.a1 = torch.empty((D, H), **f64)
         self.lnS = torch.empty(LNS_ENTRIES, **f64)
-        self.k16 = torch.empty((3 * D + 1, H + (H & 1)), dtype=torch.int16, device=device)
+        rows = CWS_KEY_WEIGHTS * D + 2 * CWS_RUN_CAP + 1
+        self.k16 = torch.empty((rows, H + (H & 1)), dtype=torch.int16, device=device)
         self._c = _CwsTablesC(n, H, self.r.data_ptr(), self.lnc.data_ptr(), self.beta.data_ptr(),
                               self.a1.data_ptr(), self.lnS.data_ptr(), self.k16.data_ptr())
         _check(lib().ssh_cws_prepare(ctypes.byref(self._c), _stream()), "ssh_cws_prepare")

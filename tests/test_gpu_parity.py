@@ -271,6 +271,33 @@ def test_cws_counts_beyond_table(ssh):
     _cws_case(ssh, 6, 33, sets, seed=9)
 
 
+def test_cws_key_rows_at_their_limits(ssh):
+    """Weights around the keyed limits: every code up to SSH_CWS_KEY_WEIGHTS, the
+    run codes 0 and 2^n - 1 up to SSH_CWS_RUN_CAP, and tokens just past each
+    (exact path), alone and mixed, in sets of 1 to 200 tokens."""
+    _announce("cws key rows at their limits")
+    KW, RC = ssh.CWS_KEY_WEIGHTS, ssh.CWS_RUN_CAP
+    edge = np.array([1, 2, 3, KW - 1, KW, KW + 1, KW + 2, 100, RC - 1, RC, RC + 1, 65535, 65536,
+                     70000], np.uint32)
+    rng = np.random.default_rng(21)
+    for n, H in [(10, 30), (15, 100)]:
+        mask = (1 << n) - 1
+        sets = []
+        for i in range(240):
+            D = int(rng.integers(1, 201))
+            c = np.sort(rng.choice(np.arange(1, mask), size=D, replace=False)).astype(np.uint32)
+            k = rng.integers(1, KW + 3, size=D).astype(np.uint32)  # other codes up to KW + 2
+            if i % 3 != 2:  # run codes present, with edge weights
+                c = np.concatenate([[0], c[: max(D - 2, 0)], [mask]]).astype(np.uint32)
+                k = np.concatenate([[edge[rng.integers(len(edge))]], k[: max(D - 2, 0)],
+                                    [edge[rng.integers(len(edge))]]]).astype(np.uint32)
+            if i % 5 == 0:  # only keyed tokens
+                other = (c != 0) & (c != mask)
+                k = np.where(other, np.minimum(k, KW), np.minimum(k, RC)).astype(np.uint32)
+            sets.append((c, k))
+        _cws_case(ssh, n, H, sets, seed=30 + n)
+
+
 # --------------------------------------------------------------------------
 # full pipeline pieces on C1-shaped data
 # --------------------------------------------------------------------------
