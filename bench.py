@@ -45,8 +45,8 @@ MEASURED_TRAFFIC = {
     #          fetch scale, write scale); the 1 GiB copy read 524306.9 KiB on
     #          FETCH_SIZE and 1048576 KiB on WRITE_SIZE
     "cws_kernel": ("paper_1610_07328_amd/csrc/cws.hip",
-                   "c62c383c0c2e5fb3d44f58c3087d64ffa7260939781f4bce7ad22ac1ad934809",
-                   5859053.8125, 793223.59375, 1048576.0 / 524306.9375, 1.0),
+                   "9cb8e80520448ba43b46edd5b6d20372741b66a5634cf2ef13b34543c45cba5d",
+                   3784249.375, 926747.125, 1048576.0 / 524306.9375, 1.0),
 }
 
 

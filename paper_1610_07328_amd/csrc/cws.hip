@@ -323,7 +323,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) void c
           // lane i writes slot i whether or not it holds a keyed token itself
           if (lane >= nk && lane < nkp) klist2[lane] = make_uint2(pad_row, 0xFFFFu);
           wave_sync_lds();
-          for (int i0 = 0; i0 < nk; i0 += kPassA) {
+          if (v0) for (int i0 = 0; i0 < nk; i0 += kPassA) {
             uint32_t wv[kPassA], pv[kPassA];
 #pragma unroll
             for (int u = 0; u < kPassA; u += 2) {
