@@ -205,7 +205,7 @@ class CwsTables:
         self.a1 = torch.empty((D, H), **f64)
         self.lnS = torch.empty(LNS_ENTRIES, **f64)
         rows = CWS_KEY_WEIGHTS * D + 2 * CWS_RUN_CAP + 1
-        self.k16 = torch.empty((rows, (H + 3) & ~3), dtype=torch.int16, device=device)
+        self.k16 = torch.empty((rows, H + (H & 1)), dtype=torch.int16, device=device)
         self._c = _CwsTablesC(n, H, self.r.data_ptr(), self.lnc.data_ptr(), self.beta.data_ptr(),
                               self.a1.data_ptr(), self.lnS.data_ptr(), self.k16.data_ptr())
         _check(lib().ssh_cws_prepare(ctypes.byref(self._c), _stream()), "ssh_cws_prepare")
