@@ -266,7 +266,7 @@ def main():
         roof = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tops/s",
                 "frac": achieved / peak, "traffic": None, "kernel": "dtw_kernel"}
     else:
-        kname = {"sketch": "sketch_fast_kernel", "shingle": "shingle_kernel", "cws": "cws_kernel",
+        kname = {"sketch": "sketch_mfma_kernel", "shingle": "shingle_kernel", "cws": "cws_kernel",
                  "band_keys": "band_keys_kernel", "table_build": "rs_scatter_kernel"}[dominant]
         achieved = bytes_stage[dominant] / (per_stage[dominant] / 1e3) / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -2,24 +2,28 @@
 //
 // bit i of a series = [ r . x[i*delta .. i*delta + W) >= 0 ].
 //
-// Fast path: one wavefront per series chunk; each lane owns R consecutive
-// windows and keeps the union of their samples in registers as packed fp16
-// pairs, so every loaded sample feeds several windows.  Products are fp16 x
-// fp16 (exact in fp32) accumulated in fp32 by v_dot2_f32_f16.  The fp16
-// filter pairs sit in LDS and are read at their point of use.  The grid is capped at 2048 workgroups, so each wavefront walks
-// many series and its repair queue drains in full rounds.
+// Fast path (W, delta) in {(80, 3), (64, 4), (128, 4), (30, 5)}: the windows
+// of a work item (256 windows of one series) are one matrix product on the
+// matrix cores: with windows laid out as 16 rows of 16, window 16 a + b is
+// sum_k F[b][k] X[k][a], F[b][k] = r[k - delta b] (the filter on a band),
+// X[k][a] = x[16 delta a + k], computed by 16x16x16 fp16 MFMAs (fp16 x fp16
+// products exact in fp32, fp32 accumulation).  The same product of the 0/1
+// band with bf16(x^2) gives each window's sum of squares.  The item's samples
+// are staged once in LDS and loaded for the next item while one is computed.
+// Any other (W, delta) takes the generic path: one window per lane with
+// v_dot2_f32_f16 over fp16 sample pairs.
 //
 // Exactness: the reference bit is the sign of the float64 sum of the exact
-// float32 products in ascending filter index.  The fast-path sum s16 differs
+// float32 products in ascending filter index.  The fast sum s16 differs
 // from that float64 sum by at most
 //     c1 ||r|| ||w|| + c2 sqrt(W) (||r|| + ||w||)
 // (fp16 rounding of both operands, fp32 accumulation with up to W + 2
-// roundings counted at 2^-23 each, fp16 underflow/flush at 2^-14 absolute,
-// and the float64 sum's own rounding).  ||w|| is bounded from above by the
-// norm of the lane's whole sample span, computed from the same fp16 values
-// with the conversion and accumulation slack added.  A window with
+// roundings counted at 2^-23 each in any order, fp16 underflow/flush at 2^-14
+// absolute, and the float64 sum's own rounding).  ||w|| is bounded from above
+// with slack for the bf16 and fp32 roundings of the sum of squares (matrix
+// path) or for the fp16 conversion (generic path).  A window with
 // |s16| >= margin keeps the sign of s16; every other window (and every window
-// of a chunk holding a sample with |x| >= 2^14 or a non-finite one) is queued
+// of an item holding a sample with |x| >= 2^14 or a non-finite one) is queued
 // and recomputed exactly like the reference, one window per lane, in float64.
 // Queued windows are drained in rounds of 64 so a round keeps the whole wave
 // busy (each lane loads its window's samples 16 at a time); a repaired 1 is
@@ -37,7 +41,6 @@ typedef _Float16 h2 __attribute__((ext_vector_type(2)));
 struct FilterArgs {
   float r[SSH_MAX_W];                // float32 filter, float64 repair path
   uint32_t even[SSH_MAX_W / 2 + 2];  // fp16 pairs (r[2p], r[2p+1]), r[W] = 0
-  uint32_t odd[SSH_MAX_W / 2 + 2];   // fp16 pairs (r[2p-1], r[2p]), r[-1] = r[W] = 0
   float c1;                          // relative margin factor
   float c2;                          // underflow margin factor
   float rnorm;                       // ||r||_2, rounded up
@@ -145,15 +148,6 @@ __device__ __forceinline__ void push_flags(RepairQueue q, uint32_t flags, uint32
   }
 }
 
-// lane's R bits at chunk-relative window position wl into the LDS words bw
-template <int R>
-__device__ __forceinline__ void or_bits(uint32_t* bw, int wl, uint32_t b) {
-  if (!b) return;
-  int word = wl >> 5, sh = wl & 31;
-  atomicOr(bw + word, b << sh);
-  if (sh + R > 32) atomicOr(bw + word + 1, b >> (32 - sh));
-}
-
 constexpr int kWavesPerBlock = 4;
 
 // ---------------------------------------------------------------------------
@@ -248,41 +242,93 @@ __device__ __forceinline__ void load_chunk(const float* __restrict__ x, const Ch
   }
 }
 
-template <int W, int D, int R>
-__global__ __launch_bounds__(256) void sketch_fast_kernel(
+// ---------------------------------------------------------------------------
+// fast path on the matrix cores
+// ---------------------------------------------------------------------------
+// A work item is SUB = 256 windows of one series: 16 rows of 16 windows.
+// Window 16 a + b (row a, column b) is the inner product of r with samples
+// [D (16 a + b), + W), i.e. with samples k of row a's run [16 D a, + K) at
+// k = D b + u (u < W).  So the item's sums are one matrix product
+//     S[b][a] = sum_k F[b][k] X[k][a],  F[b][k] = r[k - D b] (0 off the band),
+//                                       X[k][a] = x[16 D a + k],
+// K = 16 ceil((15 D + W) / 16), done as K / 16 steps of the 16x16x16 fp16
+// MFMA (products exact in fp32, fp32 accumulation).  The same product of the
+// 0/1 band with bf16(x^2) gives every window's sum of squares, the norm the
+// margin needs.  With F as the A operand, lane L ends up holding the four
+// consecutive windows 16 (L % 16) + 4 (L / 16) + i, i = 0..3.
+typedef _Float16 half4 __attribute__((ext_vector_type(4)));
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float float4v __attribute__((ext_vector_type(4)));
+
+typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
+typedef _Float16 f16x2v __attribute__((ext_vector_type(2)));
+typedef float f32x2v __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ uint32_t pack_bf16(float a, float b) {
+  const f32x2v v = {a, b};
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2v));
+}
+
+__device__ __forceinline__ uint32_t pack_f16(float a, float b) {
+  const f32x2v v = {a, b};
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, f16x2v));
+}
+
+// Upper bound of the float64-vs-fast-path error for a window whose bf16
+// sum of squares (fp32-accumulated) is E.  bf16 rounding of a square is below
+// 2^-7 relative whatever the rounding direction, and the fp32 accumulation far
+// below that, so ||w||^2 <= E (1 + 2^-6); the W 2^-28 term covers squares
+// that underflow.
+template <int W>
+__device__ __forceinline__ float mfma_margin(const FilterArgs& fa, float E) {
+  const float slack = 1.0f + 0x1p-20f;
+  const float wn = __builtin_sqrtf(E * (1.0f + 0x1p-6f) + (float)W * 0x1p-28f) * slack;
+  const float m = fa.c1 * fa.rnorm * wn + fa.c2 * fa.sqrtW * (fa.rnorm + wn);
+  return m * slack;
+}
+
+template <int W, int D>
+__global__ __launch_bounds__(256) void sketch_mfma_kernel(
     const float* __restrict__ x, const int64_t* __restrict__ x_off, int64_t N, FilterArgs fa,
     uint64_t* __restrict__ bits, const int64_t* __restrict__ bit_word_off,
     int32_t* __restrict__ nbits_out, unsigned long long* repair_count, int* err) {
-  constexpr int SUB = kWave * R;          // windows per chunk
-  constexpr int XCAP = (SUB - 1) * D + W; // samples a chunk's windows touch
-  constexpr int SPAN = D * (R - 1) + W;   // samples of one lane's R windows
-  constexpr int NP = (SPAN + 1) / 2;      // fp16 pairs a lane holds
-  constexpr int PE = (W + 1) / 2;         // pairs of an even-aligned window
-  constexpr int PO = W / 2 + 1;           // pairs of an odd-aligned window
-  constexpr int NPAIR = XCAP / 2 + 2;     // pairs per copy (sample XCAP included)
+  constexpr int SUB = 256;                 // windows per item
+  constexpr int RS = 16 * D;               // samples between rows
+  constexpr int KS = (15 * D + W + 15) / 16;  // k-steps
+  constexpr int NS = 15 * RS + 16 * KS;    // samples an item reads
+  constexpr int NPAIR = NS / 2;
   constexpr int PF = (NPAIR + kWave - 1) / kWave;
   constexpr int QCAP = SUB + kWave;
-  static_assert(R <= 32, "R bits per lane must fit a word");
+  static_assert(NS % 4 == 0 && RS % 4 == 0, "8-byte operand reads");
 
-  __shared__ uint32_t ev[kWavesPerBlock][PF * kWave];
-  __shared__ uint32_t od[kWavesPerBlock][PF * kWave];
+  __shared__ uint32_t xh[kWavesPerBlock][PF * kWave];  // fp16 pairs of the samples
+  __shared__ uint32_t xq[kWavesPerBlock][PF * kWave];  // bf16 pairs of their squares
   __shared__ uint32_t qser[kWavesPerBlock][QCAP];
   __shared__ uint32_t qwin[kWavesPerBlock][QCAP];
-  __shared__ uint32_t bw[kWavesPerBlock][2 * R];
+  __shared__ uint16_t bw[kWavesPerBlock][16];
   __shared__ int qn[kWavesPerBlock];
-  // fp16 filter pairs (even[p], odd[p]) side by side: read with a uniform
-  // address at the point of use rather than held in scalar registers across
-  // the whole loop
-  __shared__ uint2 filt[(PE > PO ? PE : PO)];
 
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave-uniform
   const int lane = lane_id();
+  const int col = lane & 15, grp = lane >> 4;
   RepairQueue q{qser[w], qwin[w], &qn[w]};
   uint32_t* bits32 = reinterpret_cast<uint32_t*>(bits);
-  for (int p = threadIdx.x; p < (PE > PO ? PE : PO); p += blockDim.x)
-    filt[p] = make_uint2(fa.even[p], fa.odd[p]);
   if (lane == 0) qn[w] = 0;
-  __syncthreads();
+
+  // A operands: F[b][k] and the 0/1 band, b = lane % 16, k = 16 t + 4 (lane / 16) + e
+  half4 fr[KS];
+  bf16x4 fo[KS];
+#pragma unroll
+  for (int t = 0; t < KS; ++t) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int u = 16 * t + 4 * grp + e - D * col;
+      const bool in = u >= 0 && u < W;
+      fr[t][e] = in ? (_Float16)fa.r[in ? u : 0] : (_Float16)0.0f;
+      fo[t][e] = in ? (short)0x3F80 : (short)0;
+    }
+  }
+  wave_sync_lds();
 
   const int64_t stride = (int64_t)gridDim.x * kWavesPerBlock;
   const int64_t s0 = (int64_t)blockIdx.x * kWavesPerBlock + w;
@@ -296,77 +342,62 @@ __global__ __launch_bounds__(256) void sketch_fast_kernel(
   if (cur.s < N) load_chunk<PF>(x, cur, (int64_t)cur.c * SUB * D, pa, pb);
 
   while (cur.s < N) {
-    // stage the chunk as fp16 pairs; flag it when a sample it uses could
-    // overflow the fp16 products or is not finite
+    // stage the item's samples; flag it when one could overflow the fp16
+    // products or is not finite
     bool bad = false;
 #pragma unroll
     for (int i = 0; i < PF; ++i) {
       const int p = lane + kWave * i;
-      // x[2p-1]: the lane before's x[2p+1]; for lane 0, lane 63's of the previous pair
-      // row (both shuffles run on the whole wave before the select)
-      const float up = __shfl_up(pb[i], 1, kWave);
-      const float last = i == 0 ? 0.0f : __shfl(pb[i == 0 ? 0 : i - 1], kWave - 1, kWave);
-      const float prev = lane == 0 ? last : up;
-      ev[w][p] = __builtin_bit_cast(uint32_t, pack_h2(pa[i], pb[i]));
-      od[w][p] = __builtin_bit_cast(uint32_t, pack_h2(prev, pa[i]));
-      bad |= (2 * p <= XCAP && !(__builtin_fabsf(pa[i]) < 16384.0f)) ||
-             (2 * p + 1 <= XCAP && !(__builtin_fabsf(pb[i]) < 16384.0f));
+      xh[w][p] = pack_f16(pa[i], pb[i]);
+      xq[w][p] = pack_bf16(pa[i] * pa[i], pb[i] * pb[i]);
+      bad |= !(__builtin_fabsf(pa[i]) < 16384.0f) || !(__builtin_fabsf(pb[i]) < 16384.0f);
     }
     const bool unsafe = ballot64(bad) != 0;
-    if (lane < 2 * R) bw[w][lane] = 0;
     wave_sync_lds();
 
-    // start loading the next chunk; it is consumed at the top of the next iteration
+    // start loading the next item; it is consumed at the top of the next iteration
     const ChunkItem nxt = next_item<W, D, SUB>(cur, N, stride, x_off, bit_word_off, nbits_out, err);
     if (nxt.s < N) load_chunk<PF>(x, nxt, (int64_t)nxt.c * SUB * D, pa, pb);
 
+    // B operands X[k][a], a = lane % 16, k = 16 t + 4 (lane / 16) + e: four
+    // consecutive samples from sample 16 D a + 16 t + 4 (lane / 16)
+    float4v S = {0.0f, 0.0f, 0.0f, 0.0f}, E = {0.0f, 0.0f, 0.0f, 0.0f};
+    const uint2* xh2 = reinterpret_cast<const uint2*>(xh[w]);
+    const uint2* xq2 = reinterpret_cast<const uint2*>(xq[w]);
+    const int b0 = (RS * col + 4 * grp) / 4;  // in 8-byte units
+#pragma unroll
+    for (int t = 0; t < KS; ++t) {
+      const uint2 hv = xh2[b0 + 4 * t];
+      const uint2 qv = xq2[b0 + 4 * t];
+      S = __builtin_amdgcn_mfma_f32_16x16x16f16(fr[t], __builtin_bit_cast(half4, hv), S, 0, 0, 0);
+      E = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(fo[t], __builtin_bit_cast(bf16x4, qv), E, 0, 0, 0);
+    }
+
     const int nb = cur.nb;
     const int c = cur.c;
-    const int wl = lane * R;
+    const int wl = 16 * col + 4 * grp;  // item-relative window of S[0]
     const int nvalid = nb - c * SUB - wl;
-    if (nvalid > 0) {
-      const int a = wl * D;  // first sample of the lane's span
-      const uint32_t* src = (a & 1) ? od[w] + (a + 1) / 2 : ev[w] + a / 2;
-      h2 pr[NP];
+    uint32_t nib = 0, flags = 0;
 #pragma unroll
-      for (int p = 0; p < NP; ++p) pr[p] = as_h2(src[p]);
-      float E = 0.0f;
-#pragma unroll
-      for (int p = 0; p < NP; ++p) E = fdot2(pr[p], pr[p], E);
-      const float M = window_margin(fa, E, 2 * NP);
-      float acc[R];
-#pragma unroll
-      for (int rho = 0; rho < R; ++rho) acc[rho] = 0.0f;
-#pragma unroll
-      for (int p = 0; p < (PE > PO ? PE : PO); ++p) {
-        const uint2 f = filt[p];
-#pragma unroll
-        for (int rho = 0; rho < R; ++rho) {
-          if (((D * rho) & 1) == 0) {
-            if (p < PE) acc[rho] = fdot2(pr[(D * rho) / 2 + p], as_h2(f.x), acc[rho]);
-          } else {
-            if (p < PO) acc[rho] = fdot2(pr[(D * rho - 1) / 2 + p], as_h2(f.y), acc[rho]);
-          }
-        }
-        if ((p & 7) == 7) asm volatile("" ::: "memory");
+    for (int i = 0; i < 4; ++i) {
+      if (i < nvalid) {
+        const float M = mfma_margin<W>(fa, E[i]);
+        if (unsafe || !(__builtin_fabsf(S[i]) >= M)) flags |= 1u << i;
+        else if (S[i] >= 0.0f) nib |= 1u << i;
       }
-      uint32_t mybits = 0, myflags = 0;
-#pragma unroll
-      for (int rho = 0; rho < R; ++rho) {
-        if (rho < nvalid) {
-          const bool flag = unsafe || !(__builtin_fabsf(acc[rho]) >= M);
-          if (flag) myflags |= 1u << rho;
-          else if (acc[rho] >= 0.0f) mybits |= 1u << rho;
-        }
-      }
-      or_bits<R>(bw[w], wl, mybits);
-      push_flags<R>(q, myflags, (uint32_t)cur.s, (uint32_t)(c * SUB + wl));
     }
+    // bits of windows 16 col .. + 15 from the four lanes sharing col
+    uint32_t v = nib << (4 * grp);
+    v |= __shfl_xor(v, 16, kWave);
+    v |= __shfl_xor(v, 32, kWave);
+    if (grp == 0) bw[w][col] = (uint16_t)v;
+    if (flags) push_flags<4>(q, flags, (uint32_t)cur.s, (uint32_t)(c * SUB + wl));
     wave_sync_lds();
     const int nwords = (nb + 63) / 64;
-    if (lane < 2 * R) {
-      const int64_t wd = (int64_t)c * R + (lane >> 1);
-      if (wd < nwords) bits32[2 * (cur.wo + wd) + (lane & 1)] = bw[w][lane];
+    if (lane < 8) {
+      const int64_t wd = (int64_t)c * 4 + (lane >> 1);
+      if (wd < nwords)
+        bits32[2 * (cur.wo + wd) + (lane & 1)] = reinterpret_cast<const uint32_t*>(bw[w])[lane];
     }
     while (qn[w] >= kWave) repair_round(fa, x, x_off, bits32, bit_word_off, q, repair_count);
     cur = nxt;
@@ -468,7 +499,6 @@ static ssh_status make_filter_args(const float* r, int W, int delta, FilterArgs&
   auto rk = [&](int k) -> float { return (k >= 0 && k < W) ? r[k] : 0.0f; };
   for (int p = 0; p < SSH_MAX_W / 2 + 2; ++p) {
     fa.even[p] = (uint32_t)to_half_bits(rk(2 * p)) | ((uint32_t)to_half_bits(rk(2 * p + 1)) << 16);
-    fa.odd[p] = (uint32_t)to_half_bits(rk(2 * p - 1)) | ((uint32_t)to_half_bits(rk(2 * p)) << 16);
   }
   const double u = 0x1p-11;               // fp16 unit roundoff (nearest)
   const double e32 = 0x1p-23;              // per-rounding fp32 error, counted generously
@@ -521,18 +551,18 @@ ssh_status sketch_launch(const float* x, const int64_t* x_off, int64_t N, const 
   unsigned long long* rc = reinterpret_cast<unsigned long long*>(repair_count);
   const unsigned grid = grid_for(N, kWavesPerBlock, 1 << 16);
   const dim3 blk(256);
-#define SSH_FAST(WW, DD, RR)                                                                   \
+#define SSH_FAST(WW, DD)                                                                       \
   if (!force_generic && W == WW && delta == DD) {                                              \
     const unsigned fgrid = resident_grid(reinterpret_cast<const void*>(                        \
-        &sketch_fast_kernel<WW, DD, RR>), N);                                                  \
-    sketch_fast_kernel<WW, DD, RR><<<fgrid, blk, 0, stream>>>(x, x_off, N, fa, bits,          \
-                                                              bit_word_off, nbits, rc, err);  \
+        &sketch_mfma_kernel<WW, DD>), N);                                                      \
+    sketch_mfma_kernel<WW, DD><<<fgrid, blk, 0, stream>>>(x, x_off, N, fa, bits,              \
+                                                          bit_word_off, nbits, rc, err);      \
     return check_launch("ssh_sketch");                                                         \
   }
-  SSH_FAST(80, 3, 5)
-  SSH_FAST(64, 4, 2)
-  SSH_FAST(128, 4, 8)
-  SSH_FAST(30, 5, 4)
+  SSH_FAST(80, 3)
+  SSH_FAST(64, 4)
+  SSH_FAST(128, 4)
+  SSH_FAST(30, 5)
 #undef SSH_FAST
   const int XCAP = (kWave - 1) * delta + W + 2;
   const size_t per_wave = (size_t)XCAP * 4 + 2 * 2 * kWave * 4 + 2 * 4 + 4;
