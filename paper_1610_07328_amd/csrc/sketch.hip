@@ -151,14 +151,9 @@ __device__ __forceinline__ void push_flags(RepairQueue q, uint32_t flags, uint32
 constexpr int kWavesPerBlock = 4;
 
 // ---------------------------------------------------------------------------
-// fast path: compile-time W, delta and R windows per lane
+// work items of the fast path: chunks of SUB consecutive windows of a series,
+// walked by a wave striding over series
 // ---------------------------------------------------------------------------
-// A work item is one chunk of SUB = 64 R windows of one series.  The chunk's
-// samples are staged in LDS as fp16 pairs, converted once: ev[p] holds
-// (x[2p], x[2p+1]) and od[p] holds (x[2p-1], x[2p]) (chunk-relative indices),
-// so a lane whose span starts at an even sample reads ev and one starting at
-// an odd sample reads od.  While a chunk is computed, the samples of the
-// wave's next chunk are already being loaded into registers.
 struct ChunkItem {
   int64_t s;     // series (>= N: no item)
   int c;         // chunk of the series
@@ -219,29 +214,6 @@ __device__ __forceinline__ ChunkItem next_item(ChunkItem it, int64_t N, int64_t 
   return it;
 }
 
-// Samples 2p and 2p+1 (p = lane + 64 i) of a chunk starting at sample sb,
-// read through a buffer resource whose range ends at the series' last sample
-// (or past what the chunk needs), so samples past the series read as zero
-// without any per-load bounds arithmetic.
-template <int PF>
-__device__ __forceinline__ void load_chunk(const float* __restrict__ x, const ChunkItem& it,
-                                           int64_t sb, float (&pa)[PF], float (&pb)[PF]) {
-  const int lane = lane_id();
-  const int64_t rem = it.m - sb;  // > 0 for an item's chunk
-  const int64_t need = 2 * kWave * PF;
-  const int nrec = (int)((rem < need ? rem : need) * 4);
-  const __amdgpu_buffer_rsrc_t rs =
-      __builtin_amdgcn_make_buffer_rsrc((void*)(x + it.base + sb), 0, nrec, 0x00020000);
-  const int voff = 8 * lane;
-#pragma unroll
-  for (int i = 0; i < PF; ++i) {
-    // per-lane offset in a register, the row offset as a scalar offset
-    const int soff = 2 * kWave * i * 4;
-    pa[i] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, voff, soff, 0));
-    pb[i] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, voff + 4, soff, 0));
-  }
-}
-
 // ---------------------------------------------------------------------------
 // fast path on the matrix cores
 // ---------------------------------------------------------------------------
@@ -287,6 +259,28 @@ __device__ __forceinline__ float mfma_margin(const FilterArgs& fa, float E) {
   return m * slack;
 }
 
+// Samples 4p .. 4p + 3 (p = lane + 64 i) of an item starting at sample sb, one
+// 16-byte load each, through a buffer resource whose range ends at the
+// series' last sample (or past what the item needs): samples past the series
+// read as zero (each dword is range-checked on its own).
+template <int PF4>
+__device__ __forceinline__ void load_item4(const float* __restrict__ x, const ChunkItem& it,
+                                           int64_t sb, float (&pv)[PF4][4]) {
+  const int lane = lane_id();
+  const int64_t rem = it.m - sb;  // > 0 for an item
+  const int64_t need = 4 * kWave * PF4;
+  const int nrec = (int)((rem < need ? rem : need) * 4);
+  const __amdgpu_buffer_rsrc_t rs =
+      __builtin_amdgcn_make_buffer_rsrc((void*)(x + it.base + sb), 0, nrec, 0x00020000);
+#pragma unroll
+  for (int i = 0; i < PF4; ++i) {
+    // the builtin's own vector type, indexed directly
+    const auto v = __builtin_amdgcn_raw_buffer_load_b128(rs, 16 * lane, 4 * kWave * i * 4, 0);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) pv[i][e] = __builtin_bit_cast(float, (uint32_t)v[e]);
+  }
+}
+
 template <int W, int D>
 __global__ __launch_bounds__(256) void sketch_mfma_kernel(
     const float* __restrict__ x, const int64_t* __restrict__ x_off, int64_t N, FilterArgs fa,
@@ -296,13 +290,12 @@ __global__ __launch_bounds__(256) void sketch_mfma_kernel(
   constexpr int RS = 16 * D;               // samples between rows
   constexpr int KS = (15 * D + W + 15) / 16;  // k-steps
   constexpr int NS = 15 * RS + 16 * KS;    // samples an item reads
-  constexpr int NPAIR = NS / 2;
-  constexpr int PF = (NPAIR + kWave - 1) / kWave;
+  constexpr int PF4 = (NS + 4 * kWave - 1) / (4 * kWave);  // rows of 256 samples
   constexpr int QCAP = SUB + kWave;
   static_assert(NS % 4 == 0 && RS % 4 == 0, "8-byte operand reads");
 
-  __shared__ uint32_t xh[kWavesPerBlock][PF * kWave];  // fp16 pairs of the samples
-  __shared__ uint32_t xq[kWavesPerBlock][PF * kWave];  // bf16 pairs of their squares
+  __shared__ uint2 xh[kWavesPerBlock][PF4 * kWave];  // fp16 quads of the samples
+  __shared__ uint2 xq[kWavesPerBlock][PF4 * kWave];  // bf16 quads of their squares
   __shared__ uint32_t qser[kWavesPerBlock][QCAP];
   __shared__ uint32_t qwin[kWavesPerBlock][QCAP];
   __shared__ uint16_t bw[kWavesPerBlock][16];
@@ -338,32 +331,34 @@ __global__ __launch_bounds__(256) void sketch_mfma_kernel(
     cur = series_item<W, D>(s0, x_off, bit_word_off, nbits_out, err);
     if (cur.nb == 0) cur = next_item<W, D, SUB>(cur, N, stride, x_off, bit_word_off, nbits_out, err);
   }
-  float pa[PF], pb[PF];
-  if (cur.s < N) load_chunk<PF>(x, cur, (int64_t)cur.c * SUB * D, pa, pb);
+  float pv[PF4][4];
+  if (cur.s < N) load_item4<PF4>(x, cur, (int64_t)cur.c * SUB * D, pv);
 
   while (cur.s < N) {
     // stage the item's samples; flag it when one could overflow the fp16
     // products or is not finite
     bool bad = false;
 #pragma unroll
-    for (int i = 0; i < PF; ++i) {
+    for (int i = 0; i < PF4; ++i) {
       const int p = lane + kWave * i;
-      xh[w][p] = pack_f16(pa[i], pb[i]);
-      xq[w][p] = pack_bf16(pa[i] * pa[i], pb[i] * pb[i]);
-      bad |= !(__builtin_fabsf(pa[i]) < 16384.0f) || !(__builtin_fabsf(pb[i]) < 16384.0f);
+      xh[w][p] = make_uint2(pack_f16(pv[i][0], pv[i][1]), pack_f16(pv[i][2], pv[i][3]));
+      xq[w][p] = make_uint2(pack_bf16(pv[i][0] * pv[i][0], pv[i][1] * pv[i][1]),
+                            pack_bf16(pv[i][2] * pv[i][2], pv[i][3] * pv[i][3]));
+#pragma unroll
+      for (int e = 0; e < 4; ++e) bad |= !(__builtin_fabsf(pv[i][e]) < 16384.0f);
     }
     const bool unsafe = ballot64(bad) != 0;
     wave_sync_lds();
 
     // start loading the next item; it is consumed at the top of the next iteration
     const ChunkItem nxt = next_item<W, D, SUB>(cur, N, stride, x_off, bit_word_off, nbits_out, err);
-    if (nxt.s < N) load_chunk<PF>(x, nxt, (int64_t)nxt.c * SUB * D, pa, pb);
+    if (nxt.s < N) load_item4<PF4>(x, nxt, (int64_t)nxt.c * SUB * D, pv);
 
     // B operands X[k][a], a = lane % 16, k = 16 t + 4 (lane / 16) + e: four
     // consecutive samples from sample 16 D a + 16 t + 4 (lane / 16)
     float4v S = {0.0f, 0.0f, 0.0f, 0.0f}, E = {0.0f, 0.0f, 0.0f, 0.0f};
-    const uint2* xh2 = reinterpret_cast<const uint2*>(xh[w]);
-    const uint2* xq2 = reinterpret_cast<const uint2*>(xq[w]);
+    const uint2* xh2 = xh[w];
+    const uint2* xq2 = xq[w];
     const int b0 = (RS * col + 4 * grp) / 4;  // in 8-byte units
 #pragma unroll
     for (int t = 0; t < KS; ++t) {
