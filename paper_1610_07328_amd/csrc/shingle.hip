@@ -16,8 +16,8 @@
 //      LDS count buffer), and the token is written at its rank of `codes`,
 //      so tokens come out ascending without sorting;
 //   4. counts are copied out and the bitmap and counts are cleared.
-// Bitmap word w (and its rank base) sits at slot w + w/16, so the per-lane
-// scans of step 2 hit distinct LDS banks.
+// Lane L's bitmap words and rank bases sit in padded per-lane runs, read and
+// cleared with 16-byte LDS accesses that fall on distinct banks.
 // A token is the n bits in stream order read most significant first.
 #include "common.hpp"
 
@@ -27,17 +27,22 @@ constexpr int kCountCap = 512;  // distinct tokens whose counts stay in LDS
 constexpr int kShWaves = 4;     // wavefronts per workgroup
 
 __host__ __device__ inline int shingle_bitmap_words(int n) { return n > 5 ? 1 << (n - 5) : 1; }
+__host__ __device__ inline int shingle_wpl(int n) {  // bitmap words per lane
+  const int bw = shingle_bitmap_words(n);
+  return bw >= kWave ? bw / kWave : 1;
+}
+// Lane L owns bitmap words [L WPL, (L + 1) WPL), stored from slot L BS, and
+// their rank bases (u16) from slot L PS: strides padded so that the lanes'
+// 16-byte accesses of one instruction fall on distinct LDS banks.
+__host__ __device__ inline int shingle_bs(int wpl) { return wpl + (wpl >= 8 ? 4 : 0); }
+__host__ __device__ inline int shingle_ps(int wpl) { return wpl + (wpl >= 16 ? 8 : 0); }
 
-// Bitmap word w and its rank base are stored at slot w + w / 16: a lane that
-// scans 16 or more consecutive words then starts on a different LDS bank
-// than its neighbours.
-__host__ __device__ inline int pad_slot(int w) { return w + (w >> 4); }
-__host__ __device__ inline int shingle_slots(int n) { return pad_slot(shingle_bitmap_words(n) - 1) + 1; }
-
-// LDS bytes of one wave: bitmap (u32), rank bases (u16, padded to 16 bytes), counts (u32)
+// LDS bytes of one wave: bitmap (u32), rank bases (u16, to 16 bytes), counts (u32)
 __host__ __device__ inline size_t shingle_lds_bytes(int n) {
-  const size_t bs = (size_t)shingle_slots(n);
-  return bs * 4 + ((bs * 2 + 15) & ~(size_t)15) + (size_t)kCountCap * 4;
+  const int wpl = shingle_wpl(n);
+  const size_t bm = (size_t)kWave * shingle_bs(wpl) * 4;
+  const size_t pre = ((size_t)kWave * shingle_ps(wpl) * 2 + 15) & ~(size_t)15;
+  return bm + pre + (size_t)kCountCap * 4;
 }
 
 // 32 stream bits starting at bit b0 (bit j of the result is stream bit b0 + j;
@@ -50,25 +55,46 @@ __device__ __forceinline__ uint32_t stream_window(const uint32_t* __restrict__ w
   return __builtin_amdgcn_alignbit(hi, lo, (uint32_t)(b0 & 31));
 }
 
+// Inclusive prefix sum over the wave by DPP: Hillis-Steele shifts inside each
+// row of 16 lanes, then the row totals through row_bcast:15 and row_bcast:31.
+// Every lane must be active.
+__device__ __forceinline__ uint32_t wave_incl_scan_dpp(uint32_t v) {
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xF, 0xF, true);  // row_shr:1
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xF, 0xF, true);  // row_shr:2
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xF, 0xF, true);  // row_shr:4
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xF, 0xF, true);  // row_shr:8
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xA, 0xF, false); // row_bcast:15
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xC, 0xF, false); // row_bcast:31
+  return v;
+}
+
 template <int WPL>
 __global__ __launch_bounds__(kShWaves * kWave) void shingle_kernel(
     const uint64_t* __restrict__ bits, const int64_t* __restrict__ bit_word_off,
     const int32_t* __restrict__ nbits, int64_t N, int n, uint32_t* __restrict__ codes,
     uint32_t* __restrict__ counts, const int64_t* __restrict__ hist_off,
     int32_t* __restrict__ n_distinct, int* err) {
-  extern __shared__ uint32_t smem32[];
+  constexpr int BS = WPL + (WPL >= 8 ? 4 : 0);    // shingle_bs
+  constexpr int PS = WPL + (WPL >= 16 ? 8 : 0);   // shingle_ps
+  constexpr int LW = WPL == 1 ? 0 : (WPL == 2 ? 1 : (WPL == 4 ? 2 : (WPL == 8 ? 3 : (WPL == 16 ? 4 : 5))));
+  extern __shared__ __attribute__((aligned(16))) uint32_t smem32[];
   const int BW = shingle_bitmap_words(n);
-  const int BS = shingle_slots(n);
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave-uniform
   const int lane = lane_id();
   uint32_t* bm = smem32 + (shingle_lds_bytes(n) / 4) * w;
-  uint16_t* pre = reinterpret_cast<uint16_t*>(bm + BS);
-  uint32_t* cnt = bm + BS + ((BS * 2 + 15) & ~15) / 4;
-  for (int i = lane; i < BS; i += kWave) bm[i] = 0;
+  uint16_t* pre = reinterpret_cast<uint16_t*>(bm + kWave * BS);
+  uint32_t* cnt = bm + kWave * BS + ((kWave * PS * 2 + 15) & ~15) / 4;
+  // this lane's words exist (WPL > 1: the bitmap is exactly 64 WPL words)
+  const bool own = WPL > 1 || lane < BW;
+  uint32_t* mybm = bm + lane * BS;
+  uint16_t* mypre = pre + lane * PS;
+  for (int i = lane; i < kWave * BS; i += kWave) bm[i] = 0;
   for (int i = lane; i < kCountCap; i += kWave) cnt[i] = 0;
   wave_sync_lds();
   const uint32_t mask = (1u << n) - 1u;  // n <= 16
-  const int w0 = lane * WPL;             // first bitmap word of this lane
+  // slots of word t >> 5
+  auto bslot = [&](uint32_t wd) { return (int)((wd >> LW) * BS + (wd & (WPL - 1))); };
+  auto pslot = [&](uint32_t wd) { return (int)((wd >> LW) * PS + (wd & (WPL - 1))); };
 
   for (int64_t s = (int64_t)blockIdx.x * kShWaves + w; s < N; s += (int64_t)gridDim.x * kShWaves) {
     const int nb = nbits[s];
@@ -102,7 +128,7 @@ __global__ __launch_bounds__(kShWaves * kWave) void shingle_kernel(
         uint32_t prev = 0xFFFFFFFFu;
         for (int k = 0; k < kend; ++k) {
           const uint32_t t = (rev >> (32 - n - k)) & mask;
-          if (t != prev) atomicOr(bm + pad_slot(t >> 5), 1u << (t & 31));
+          if (t != prev) atomicOr(bm + bslot(t >> 5), 1u << (t & 31));
           prev = t;
         }
       }
@@ -111,20 +137,48 @@ __global__ __launch_bounds__(kShWaves * kWave) void shingle_kernel(
 
     // 2. rank of the first token of every bitmap word, and D
     uint32_t wv[WPL];
+    if constexpr (WPL >= 4) {
+#pragma unroll
+      for (int q = 0; q < WPL / 4; ++q) {
+        const uint4 v = reinterpret_cast<const uint4*>(mybm)[q];
+        wv[4 * q] = v.x; wv[4 * q + 1] = v.y; wv[4 * q + 2] = v.z; wv[4 * q + 3] = v.w;
+      }
+    } else if constexpr (WPL == 2) {
+      const uint2 v = reinterpret_cast<const uint2*>(mybm)[0];
+      wv[0] = v.x; wv[1] = v.y;
+    } else {
+      wv[0] = own ? mybm[0] : 0u;
+    }
     uint32_t c = 0;
 #pragma unroll
-    for (int j = 0; j < WPL; ++j) {
-      wv[j] = w0 + j < BW ? bm[pad_slot(w0 + j)] : 0u;
-      c += __builtin_popcount(wv[j]);
-    }
-    const uint32_t incl = wave_incl_scan(c);
+    for (int j = 0; j < WPL; ++j) c += __builtin_popcount(wv[j]);
+    const uint32_t incl = wave_incl_scan_dpp(c);
     uint32_t rk = incl - c;
+    uint16_t pv[WPL];
 #pragma unroll
     for (int j = 0; j < WPL; ++j) {
-      if (w0 + j < BW) pre[pad_slot(w0 + j)] = (uint16_t)rk;
+      pv[j] = (uint16_t)rk;
       rk += __builtin_popcount(wv[j]);
     }
-    const uint32_t D = wave_bcast(incl, kWave - 1);
+    if constexpr (WPL >= 8) {
+#pragma unroll
+      for (int q = 0; q < WPL / 8; ++q) {
+        uint4 v;
+        v.x = pv[8 * q] | ((uint32_t)pv[8 * q + 1] << 16);
+        v.y = pv[8 * q + 2] | ((uint32_t)pv[8 * q + 3] << 16);
+        v.z = pv[8 * q + 4] | ((uint32_t)pv[8 * q + 5] << 16);
+        v.w = pv[8 * q + 6] | ((uint32_t)pv[8 * q + 7] << 16);
+        reinterpret_cast<uint4*>(mypre)[q] = v;
+      }
+    } else if constexpr (WPL == 4) {
+      reinterpret_cast<uint2*>(mypre)[0] =
+          make_uint2(pv[0] | ((uint32_t)pv[1] << 16), pv[2] | ((uint32_t)pv[3] << 16));
+    } else if constexpr (WPL == 2) {
+      reinterpret_cast<uint32_t*>(mypre)[0] = pv[0] | ((uint32_t)pv[1] << 16);
+    } else {
+      if (own) mypre[0] = pv[0];
+    }
+    const uint32_t D = __builtin_amdgcn_readlane(incl, kWave - 1);
     const bool in_lds = D <= (uint32_t)kCountCap;
     if (!in_lds) {
       for (uint32_t i = lane; i < D; i += kWave) counts[ho + i] = 0;
@@ -135,8 +189,9 @@ __global__ __launch_bounds__(kShWaves * kWave) void shingle_kernel(
 
     // 3. counts by rank (runs of equal tokens in a lane counted at once), codes at their ranks
     auto flush = [&](uint32_t t, uint32_t run) {
-      const int slot = pad_slot((int)(t >> 5));
-      const uint32_t rank = (uint32_t)pre[slot] + __builtin_popcount(bm[slot] & ((1u << (t & 31)) - 1u));
+      const uint32_t wd = t >> 5;
+      const uint32_t rank =
+          (uint32_t)pre[pslot(wd)] + __builtin_popcount(bm[bslot(wd)] & ((1u << (t & 31)) - 1u));
       if (in_lds) atomicAdd(cnt + rank, run);
       else atomicAdd(counts + ho + rank, run);
       codes[ho + rank] = t;
@@ -170,9 +225,14 @@ __global__ __launch_bounds__(kShWaves * kWave) void shingle_kernel(
         cnt[i] = 0;
       }
     }
+    if constexpr (WPL >= 4) {
 #pragma unroll
-    for (int j = 0; j < WPL; ++j)
-      if (w0 + j < BW && wv[j]) bm[pad_slot(w0 + j)] = 0;
+      for (int q = 0; q < WPL / 4; ++q) reinterpret_cast<uint4*>(mybm)[q] = make_uint4(0u, 0u, 0u, 0u);
+    } else if constexpr (WPL == 2) {
+      reinterpret_cast<uint2*>(mybm)[0] = make_uint2(0u, 0u);
+    } else {
+      if (own) mybm[0] = 0u;
+    }
     wave_sync_lds();
     if (lane == 0) n_distinct[s] = (int32_t)D;
   }
@@ -194,8 +254,7 @@ ssh_status shingle_launch(const uint64_t* bits, const int64_t* bit_word_off, con
   int* err = nullptr;
   if (hipGetSymbolAddress((void**)&err, HIP_SYMBOL(g_shingle_err)) != hipSuccess)
     return fail(SSH_EDEVICE, "ssh_shingle: cannot resolve error flag");
-  const int BW = shingle_bitmap_words(n);
-  const int wpl = BW >= kWave ? BW / kWave : 1;
+  const int wpl = shingle_wpl(n);
   const size_t shm = (size_t)kShWaves * shingle_lds_bytes(n);
   const unsigned grid = grid_for(N, kShWaves, 1 << 16);
   const dim3 block(kShWaves * kWave);
