@@ -45,8 +45,8 @@ MEASURED_TRAFFIC = {
     #          fetch scale, write scale); the 1 GiB copy read 524306.9 KiB on
     #          FETCH_SIZE and 1048576 KiB on WRITE_SIZE
     "cws_kernel": ("paper_1610_07328_amd/csrc/cws.hip",
-                   "9cb8e80520448ba43b46edd5b6d20372741b66a5634cf2ef13b34543c45cba5d",
-                   3784249.375, 926747.125, 1048576.0 / 524306.9375, 1.0),
+                   "db00d1f403483950bb4245a4823a74444d3b47138db3a41f011bcf48d75e13d2",
+                   3770756.6875, 926856.28125, 1048576.0 / 524306.9375, 1.0),
 }
 
 
