@@ -191,6 +191,10 @@ size_t ssh_table_workspace_bytes(int64_t N, int32_t L);
 ssh_status ssh_table_build(const uint64_t* keys, int64_t N, int32_t L, uint64_t* tab_keys,
                            uint32_t* tab_ids, void* ws, size_t ws_bytes, void* stream);
 
+/* [host] Workspace bytes needed by ssh_probe for nq queries, L tables and C
+ * candidates. */
+size_t ssh_probe_workspace_bytes(int32_t nq, int32_t L, int32_t C);
+
 /* Probe (Algorithm 2).  For query q the retrieved set R is the union over
  * tables l of the bucket with key q_keys[q*L + l].  Members of R are ranked by
  * the number of the H hash values they share with the query (ties to the
@@ -202,11 +206,15 @@ ssh_status ssh_table_build(const uint64_t* keys, int64_t N, int32_t L, uint64_t*
  *   C            1..SSH_MAX_C
  *   cand         int64 [nq * C] output: ranked ids, -1 after ncand[q]
  *   ncand        int32 [nq] output: min(|R|, C)
- *   r_size       int64 [nq] output: |R| */
+ *   r_size       int64 [nq] output: |R|
+ *   ws, ws_bytes device workspace, at least ssh_probe_workspace_bytes(nq, L, C);
+ *                each query's entries are split over several workgroups whose
+ *                partial rankings are merged there */
 ssh_status ssh_probe(const uint64_t* tab_keys, const uint32_t* tab_ids, int64_t N, int32_t L,
                      const uint64_t* db_keys, const uint64_t* db_hv, int32_t H,
                      const uint64_t* q_keys, const uint64_t* q_hv, int32_t nq, int32_t C,
-                     int64_t* cand, int32_t* ncand, int64_t* r_size, void* stream);
+                     int64_t* cand, int32_t* ncand, int64_t* r_size, void* ws, size_t ws_bytes,
+                     void* stream);
 
 /* [host] Workspace bytes needed by dtw_rerank. */
 size_t ssh_rerank_workspace_bytes(int32_t nq, int32_t C);

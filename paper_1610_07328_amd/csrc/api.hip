@@ -41,7 +41,9 @@ ssh_status table_build_launch(const uint64_t* keys, int64_t N, int L, uint64_t* 
 ssh_status probe_launch(const uint64_t* tab_keys, const uint32_t* tab_ids, int64_t N, int L,
                         const uint64_t* db_keys, const uint64_t* db_hv, int H,
                         const uint64_t* q_keys, const uint64_t* q_hv, int nq, int C, int64_t* cand,
-                        int32_t* ncand, int64_t* r_size, hipStream_t stream);
+                        int32_t* ncand, int64_t* r_size, void* ws, size_t ws_bytes,
+                        hipStream_t stream);
+size_t probe_workspace_bytes(int nq, int L, int C);
 size_t rerank_workspace_bytes(int nq, int C);
 ssh_status rerank_launch(const float* q, const int64_t* q_off, int nq, const float* db,
                          const int64_t* db_off, int64_t Ndb, const int64_t* cand,
@@ -202,18 +204,24 @@ ssh_status ssh_table_build(const uint64_t* keys, int64_t N, int32_t L, uint64_t*
   return table_build_launch(keys, N, L, tab_keys, tab_ids, ws, ws_bytes, as_stream(stream));
 }
 
+size_t ssh_probe_workspace_bytes(int32_t nq, int32_t L, int32_t C) {
+  if (nq < 0 || L < 1 || C < 1 || C > SSH_MAX_C) return 0;
+  return probe_workspace_bytes(nq, L, C);
+}
+
 ssh_status ssh_probe(const uint64_t* tab_keys, const uint32_t* tab_ids, int64_t N, int32_t L,
                      const uint64_t* db_keys, const uint64_t* db_hv, int32_t H,
                      const uint64_t* q_keys, const uint64_t* q_hv, int32_t nq, int32_t C,
-                     int64_t* cand, int32_t* ncand, int64_t* r_size, void* stream) {
+                     int64_t* cand, int32_t* ncand, int64_t* r_size, void* ws, size_t ws_bytes,
+                     void* stream) {
   SSH_REQUIRE(N >= 0 && N <= (int64_t)UINT32_MAX - 1, "ssh_probe: N out of range");
   SSH_REQUIRE(L >= 1 && H >= 1 && nq >= 0, "ssh_probe: L, H or nq out of range");
   SSH_REQUIRE(C >= 1 && C <= SSH_MAX_C, "ssh_probe: C out of [1, SSH_MAX_C]");
   if (nq == 0) return SSH_OK;
-  SSH_REQUIRE(q_keys && q_hv && cand && ncand && r_size, "ssh_probe: null pointer");
+  SSH_REQUIRE(q_keys && q_hv && cand && ncand && r_size && ws, "ssh_probe: null pointer");
   SSH_REQUIRE(N == 0 || (tab_keys && tab_ids && db_keys && db_hv), "ssh_probe: null table pointer");
   return probe_launch(tab_keys, tab_ids, N, L, db_keys, db_hv, H, q_keys, q_hv, nq, C, cand, ncand,
-                      r_size, as_stream(stream));
+                      r_size, ws, ws_bytes, as_stream(stream));
 }
 
 size_t ssh_rerank_workspace_bytes(int32_t nq, int32_t C) {

@@ -112,12 +112,14 @@ class QueryBatch:
         self.dist = torch.empty((max(nq, 1), p.k), dtype=torch.float32, device=dev)
         self.ws = torch.empty(max(ssh.rerank_workspace_bytes(nq, p.C), 1), dtype=torch.uint8,
                               device=dev)
+        self.pws = torch.empty(max(ssh.probe_workspace_bytes(nq, p.L, p.C), 1), dtype=torch.uint8,
+                               device=dev)
 
     def probe(self):
         ix, db, q = self.index, self.index.db, self.qh
         N = db.N
         ssh.probe(ix.tab_keys[:, :N], ix.tab_ids[:, :N], db.keys[:N], db.hv[:N], q.keys[: q.N],
-                  q.hv[: q.N], q.p.C, out=(self.cand, self.ncand, self.rsize))
+                  q.hv[: q.N], q.p.C, out=(self.cand, self.ncand, self.rsize), ws=self.pws)
 
     def rerank(self, q_len: int, db_len: int):
         db, q = self.index.db, self.qh

@@ -58,8 +58,9 @@ SIGNATURES = {
     "ssh_band_keys": (_i32, [_vp, _i64, _i32, _i32, _u64, _vp, _vp]),
     "ssh_table_workspace_bytes": (_sz, [_i64, _i32]),
     "ssh_table_build": (_i32, [_vp, _i64, _i32, _vp, _vp, _vp, _sz, _vp]),
+    "ssh_probe_workspace_bytes": (_sz, [_i32, _i32, _i32]),
     "ssh_probe": (_i32, [_vp, _vp, _i64, _i32, _vp, _vp, _i32, _vp, _vp, _i32, _i32, _vp, _vp,
-                         _vp, _vp]),
+                         _vp, _vp, _sz, _vp]),
     "ssh_rerank_workspace_bytes": (_sz, [_i32, _i32]),
     "dtw_rerank": (_i32, [_vp, _vp, _i32, _vp, _vp, _i64, _vp, _vp, _i32, _f32, _i64, _i64,
                           _i32, _vp, _vp, _vp, _sz, _vp]),
@@ -256,12 +257,19 @@ def table_build(keys: torch.Tensor, ws: torch.Tensor | None = None, out=None):
     return tk[:, :N], ti[:, :N]
 
 
-def probe(tab_keys, tab_ids, db_keys, db_hv, q_keys, q_hv, C: int, out=None):
+def probe_workspace_bytes(nq: int, L: int, C: int) -> int:
+    return int(lib().ssh_probe_workspace_bytes(nq, L, C))
+
+
+def probe(tab_keys, tab_ids, db_keys, db_hv, q_keys, q_hv, C: int, out=None, ws=None):
     """Returns (cand int64 [nq, C], ncand int32 [nq], r_size int64 [nq])."""
     L, N = tab_keys.shape
     H = db_hv.shape[1]
     nq = q_keys.shape[0]
     dev = q_keys.device
+    need = probe_workspace_bytes(nq, L, C)
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
     if out is None:
         cand = torch.empty((max(nq, 1), C), dtype=torch.int64, device=dev)
         ncand = torch.empty(max(nq, 1), dtype=torch.int32, device=dev)
@@ -274,7 +282,8 @@ def probe(tab_keys, tab_ids, db_keys, db_hv, q_keys, q_hv, C: int, out=None):
                            _dev(db_keys, torch.uint64, "db_keys"), _dev(db_hv, torch.uint64, "db_hv"),
                            H, _dev(q_keys, torch.uint64, "q_keys"), _dev(q_hv, torch.uint64, "q_hv"),
                            nq, C, _dev(cand, torch.int64, "cand"), _dev(ncand, torch.int32, "ncand"),
-                           _dev(rs, torch.int64, "r_size"), _stream()), "ssh_probe")
+                           _dev(rs, torch.int64, "r_size"), _dev(ws, torch.uint8, "ws"),
+                           ws.numel(), _stream()), "ssh_probe")
     return cand[:nq], ncand[:nq], rs[:nq]
 
 

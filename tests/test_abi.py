@@ -84,9 +84,12 @@ def test_validation_rejects_without_device_work(ssh):
     assert L.ssh_shingle(dummy, dummy, dummy, 4, 17, dummy, dummy, dummy, dummy, None) == EINVAL
     # probe cap, rerank k and band
     assert L.ssh_probe(dummy, dummy, 10, 2, dummy, dummy, 4, dummy, dummy, 1, 0, dummy, dummy,
-                       dummy, None) == EINVAL
+                       dummy, dummy, 1 << 20, None) == EINVAL
     assert L.ssh_probe(dummy, dummy, 10, 2, dummy, dummy, 4, dummy, dummy, 1, 5000, dummy, dummy,
-                       dummy, None) == EINVAL
+                       dummy, dummy, 1 << 20, None) == EINVAL
+    # too small a probe workspace
+    assert L.ssh_probe(dummy, dummy, 10, 2, dummy, dummy, 4, dummy, dummy, 3, 50, dummy, dummy,
+                       dummy, dummy, 8, None) == EINVAL
     assert L.dtw_rerank(dummy, dummy, 1, dummy, dummy, 10, dummy, dummy, 8, 0.1, 100, 100, 9,
                         dummy, dummy, dummy, 1 << 20, None) == EINVAL
     assert L.dtw_rerank(dummy, dummy, 1, dummy, dummy, 10, dummy, dummy, 8, 1.5, 100, 100, 4,
@@ -105,3 +108,6 @@ def test_validation_rejects_without_device_work(ssh):
 def test_workspace_sizes(ssh):
     assert ssh.table_workspace_bytes(1_000_000, 10) >= 1_000_000 * 10 * 12
     assert ssh.rerank_workspace_bytes(50, 50) >= 50 * 50 * 4
+    # the partial rankings of every part of every query, and the runs
+    assert ssh.probe_workspace_bytes(1000, 10, 50) >= 1000 * 8 * 50 * 8 + 1000 * 21 * 8
+    assert ssh.probe_workspace_bytes(1, 10, 4096) >= 4096 * 8

@@ -388,11 +388,13 @@ def test_c1_probe_exact(ssh, c1):
         assert cand[P["nq"] + t, 0] == t
 
 
-def test_probe_large_retrieved_sets_with_ties(ssh):
-    """|R| far above C and a tie level larger than the in-LDS tie buffer."""
-    _announce("probe large R with ties")
+@pytest.mark.parametrize("C", [1, 7, 100, 600, 4096])
+def test_probe_large_retrieved_sets_with_ties(ssh, C):
+    """|R| far above C, a tie level larger than a part's in-LDS tie buffer, and
+    every split of a query's entries (8 parts for small C down to 1 for C = 4096)."""
+    _announce(f"probe large R with ties C={C}")
     rng = np.random.default_rng(21)
-    N, L, H, C = 20000, 2, 8, 100
+    N, L, H = 20000, 2, 8
     hv = rng.integers(0, 2, size=(N, H), dtype=np.int64).astype(np.uint64)
     keys = np.stack([np.where(rng.random(N) < 0.5, np.uint64(11), np.uint64(22)),
                      np.where(rng.random(N) < 0.5, np.uint64(33), np.uint64(44))], 1).astype(np.uint64)
