@@ -3,8 +3,8 @@
 // bit i of a series = [ r . x[i*delta .. i*delta + W) >= 0 ].
 //
 // Fast path (W, delta) in {(80, 3), (64, 4), (128, 4), (30, 5)}: the windows
-// of a work item (256 windows of one series) are one matrix product on the
-// matrix cores: with windows laid out as 16 rows of 16, window 16 a + b is
+// of a work item (320 or 256 windows of one series) are matrix products on the
+// matrix cores: with windows laid out in rows of 16, window 16 a + b is
 // sum_k F[b][k] X[k][a], F[b][k] = r[k - delta b] (the filter on a band),
 // X[k][a] = x[16 delta a + k], computed by 16x16x16 fp16 MFMAs (fp16 x fp16
 // products exact in fp32, fp32 accumulation).  The same product of the 0/1
@@ -217,7 +217,8 @@ __device__ __forceinline__ ChunkItem next_item(ChunkItem it, int64_t N, int64_t 
 // ---------------------------------------------------------------------------
 // fast path on the matrix cores
 // ---------------------------------------------------------------------------
-// A work item is SUB = 256 windows of one series: 16 rows of 16 windows.
+// A work item is SUB = 16 ROWS windows of one series: ROWS rows of 16
+// windows, computed 16 rows (one MFMA tile) at a time.
 // Window 16 a + b (row a, column b) is the inner product of r with samples
 // [D (16 a + b), + W), i.e. with samples k of row a's run [16 D a, + K) at
 // k = D b + u (u < W).  So the item's sums are one matrix product
@@ -227,7 +228,7 @@ __device__ __forceinline__ ChunkItem next_item(ChunkItem it, int64_t N, int64_t 
 // MFMA (products exact in fp32, fp32 accumulation).  The same product of the
 // 0/1 band with bf16(x^2) gives every window's sum of squares, the norm the
 // margin needs.  With F as the A operand, lane L ends up holding the four
-// consecutive windows 16 (L % 16) + 4 (L / 16) + i, i = 0..3.
+// consecutive windows 16 (L % 16) + 4 (L / 16) + i, i = 0..3, of the tile.
 typedef _Float16 half4 __attribute__((ext_vector_type(4)));
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef float float4v __attribute__((ext_vector_type(4)));
@@ -281,24 +282,26 @@ __device__ __forceinline__ void load_item4(const float* __restrict__ x, const Ch
   }
 }
 
-template <int W, int D>
+template <int W, int D, int ROWS>
 __global__ __launch_bounds__(256) void sketch_mfma_kernel(
     const float* __restrict__ x, const int64_t* __restrict__ x_off, int64_t N, FilterArgs fa,
     uint64_t* __restrict__ bits, const int64_t* __restrict__ bit_word_off,
     int32_t* __restrict__ nbits_out, unsigned long long* repair_count, int* err) {
-  constexpr int SUB = 256;                 // windows per item
+  constexpr int SUB = 16 * ROWS;           // windows per item: ROWS rows of 16
+  constexpr int TILES = (ROWS + 15) / 16;  // MFMA tiles of 16 rows
   constexpr int RS = 16 * D;               // samples between rows
   constexpr int KS = (15 * D + W + 15) / 16;  // k-steps
-  constexpr int NS = 15 * RS + 16 * KS;    // samples an item reads
+  constexpr int NS = (ROWS - 1) * RS + 16 * KS;  // samples an item reads
   constexpr int PF4 = (NS + 4 * kWave - 1) / (4 * kWave);  // rows of 256 samples
   constexpr int QCAP = SUB + kWave;
   static_assert(NS % 4 == 0 && RS % 4 == 0, "8-byte operand reads");
+  static_assert(ROWS % 4 == 0, "whole stream words per item");
 
   __shared__ uint2 xh[kWavesPerBlock][PF4 * kWave];  // fp16 quads of the samples
   __shared__ uint2 xq[kWavesPerBlock][PF4 * kWave];  // bf16 quads of their squares
   __shared__ uint32_t qser[kWavesPerBlock][QCAP];
   __shared__ uint32_t qwin[kWavesPerBlock][QCAP];
-  __shared__ uint16_t bw[kWavesPerBlock][16];
+  __shared__ uint16_t bw[kWavesPerBlock][ROWS];
   __shared__ int qn[kWavesPerBlock];
 
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave-uniform
@@ -354,43 +357,48 @@ __global__ __launch_bounds__(256) void sketch_mfma_kernel(
     const ChunkItem nxt = next_item<W, D, SUB>(cur, N, stride, x_off, bit_word_off, nbits_out, err);
     if (nxt.s < N) load_item4<PF4>(x, nxt, (int64_t)nxt.c * SUB * D, pv);
 
-    // B operands X[k][a], a = lane % 16, k = 16 t + 4 (lane / 16) + e: four
-    // consecutive samples from sample 16 D a + 16 t + 4 (lane / 16)
-    float4v S = {0.0f, 0.0f, 0.0f, 0.0f}, E = {0.0f, 0.0f, 0.0f, 0.0f};
-    const uint2* xh2 = xh[w];
-    const uint2* xq2 = xq[w];
-    const int b0 = (RS * col + 4 * grp) / 4;  // in 8-byte units
-#pragma unroll
-    for (int t = 0; t < KS; ++t) {
-      const uint2 hv = xh2[b0 + 4 * t];
-      const uint2 qv = xq2[b0 + 4 * t];
-      S = __builtin_amdgcn_mfma_f32_16x16x16f16(fr[t], __builtin_bit_cast(half4, hv), S, 0, 0, 0);
-      E = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(fo[t], __builtin_bit_cast(bf16x4, qv), E, 0, 0, 0);
-    }
-
     const int nb = cur.nb;
     const int c = cur.c;
-    const int wl = 16 * col + 4 * grp;  // item-relative window of S[0]
-    const int nvalid = nb - c * SUB - wl;
-    uint32_t nib = 0, flags = 0;
+    const uint2* xh2 = xh[w];
+    const uint2* xq2 = xq[w];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      if (i < nvalid) {
-        const float M = mfma_margin<W>(fa, E[i]);
-        if (unsafe || !(__builtin_fabsf(S[i]) >= M)) flags |= 1u << i;
-        else if (S[i] >= 0.0f) nib |= 1u << i;
+    for (int tile = 0; tile < TILES; ++tile) {
+      // B operands X[k][a], a = 16 tile + lane % 16, k = 16 t + 4 (lane / 16) + e:
+      // four consecutive samples from sample 16 D a + 16 t + 4 (lane / 16); rows
+      // past the item read its last row (their windows are not used)
+      const int row = 16 * tile + col;
+      const int rowc = row < ROWS ? row : ROWS - 1;
+      float4v S = {0.0f, 0.0f, 0.0f, 0.0f}, E = {0.0f, 0.0f, 0.0f, 0.0f};
+      const int b0 = (RS * rowc + 4 * grp) / 4;  // in 8-byte units
+#pragma unroll
+      for (int t = 0; t < KS; ++t) {
+        const uint2 hv = xh2[b0 + 4 * t];
+        const uint2 qv = xq2[b0 + 4 * t];
+        S = __builtin_amdgcn_mfma_f32_16x16x16f16(fr[t], __builtin_bit_cast(half4, hv), S, 0, 0, 0);
+        E = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(fo[t], __builtin_bit_cast(bf16x4, qv), E, 0, 0, 0);
       }
+      const int wl = 16 * row + 4 * grp;  // item-relative window of S[0]
+      const int nvalid = row < ROWS ? nb - c * SUB - wl : 0;
+      uint32_t nib = 0, flags = 0;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        if (i < nvalid) {
+          const float M = mfma_margin<W>(fa, E[i]);
+          if (unsafe || !(__builtin_fabsf(S[i]) >= M)) flags |= 1u << i;
+          else if (S[i] >= 0.0f) nib |= 1u << i;
+        }
+      }
+      // bits of windows 16 row .. + 15 from the four lanes sharing the row
+      uint32_t v = nib << (4 * grp);
+      v |= __shfl_xor(v, 16, kWave);
+      v |= __shfl_xor(v, 32, kWave);
+      if (grp == 0 && row < ROWS) bw[w][row] = (uint16_t)v;
+      if (flags) push_flags<4>(q, flags, (uint32_t)cur.s, (uint32_t)(c * SUB + wl));
     }
-    // bits of windows 16 col .. + 15 from the four lanes sharing col
-    uint32_t v = nib << (4 * grp);
-    v |= __shfl_xor(v, 16, kWave);
-    v |= __shfl_xor(v, 32, kWave);
-    if (grp == 0) bw[w][col] = (uint16_t)v;
-    if (flags) push_flags<4>(q, flags, (uint32_t)cur.s, (uint32_t)(c * SUB + wl));
     wave_sync_lds();
     const int nwords = (nb + 63) / 64;
-    if (lane < 8) {
-      const int64_t wd = (int64_t)c * 4 + (lane >> 1);
+    if (lane < ROWS / 2) {
+      const int64_t wd = (int64_t)c * (ROWS / 4) + (lane >> 1);
       if (wd < nwords)
         bits32[2 * (cur.wo + wd) + (lane & 1)] = reinterpret_cast<const uint32_t*>(bw[w])[lane];
     }
@@ -546,18 +554,20 @@ ssh_status sketch_launch(const float* x, const int64_t* x_off, int64_t N, const 
   unsigned long long* rc = reinterpret_cast<unsigned long long*>(repair_count);
   const unsigned grid = grid_for(N, kWavesPerBlock, 1 << 16);
   const dim3 blk(256);
-#define SSH_FAST(WW, DD)                                                                       \
+#define SSH_FAST(WW, DD, RR)                                                                   \
   if (!force_generic && W == WW && delta == DD) {                                              \
     const unsigned fgrid = resident_grid(reinterpret_cast<const void*>(                        \
-        &sketch_mfma_kernel<WW, DD>), N);                                                      \
-    sketch_mfma_kernel<WW, DD><<<fgrid, blk, 0, stream>>>(x, x_off, N, fa, bits,              \
-                                                          bit_word_off, nbits, rc, err);      \
+        &sketch_mfma_kernel<WW, DD, RR>), N);                                                  \
+    sketch_mfma_kernel<WW, DD, RR><<<fgrid, blk, 0, stream>>>(x, x_off, N, fa, bits,          \
+                                                              bit_word_off, nbits, rc, err);  \
     return check_launch("ssh_sketch");                                                         \
   }
-  SSH_FAST(80, 3)
-  SSH_FAST(64, 4)
-  SSH_FAST(128, 4)
-  SSH_FAST(30, 5)
+  // rows of 16 windows per item: 20 rows hold the 315 windows of a 1024-sample
+  // series (W = 80, delta = 3) in one item
+  SSH_FAST(80, 3, 20)
+  SSH_FAST(64, 4, 16)
+  SSH_FAST(128, 4, 16)
+  SSH_FAST(30, 5, 16)
 #undef SSH_FAST
   const int XCAP = (kWave - 1) * delta + W + 2;
   const size_t per_wave = (size_t)XCAP * 4 + 2 * 2 * kWave * 4 + 2 * 4 + 4;
