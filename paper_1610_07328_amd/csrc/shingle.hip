@@ -16,14 +16,16 @@
 //      LDS count buffer), and the token is written at its rank of `codes`,
 //      so tokens come out ascending without sorting;
 //   4. counts are copied out and the bitmap and counts are cleared.
-// Lane L's bitmap words and rank bases sit in padded per-lane runs, read and
-// cleared with 16-byte LDS accesses that fall on distinct banks.
+// Lane L's bitmap words sit in a padded per-lane run, read and cleared with
+// 16-byte LDS accesses that fall on distinct banks; for n >= 13 the padding
+// holds the lane's rank bases, so the wave's LDS stays small (6 KB at n = 15)
+// and more waves fit a CU.
 // A token is the n bits in stream order read most significant first.
 #include "common.hpp"
 
 namespace ssh {
 
-constexpr int kCountCap = 512;  // distinct tokens whose counts stay in LDS
+constexpr int kCountCap = 256;  // distinct tokens whose counts stay in LDS
 constexpr int kShWaves = 4;     // wavefronts per workgroup
 
 __host__ __device__ inline int shingle_bitmap_words(int n) { return n > 5 ? 1 << (n - 5) : 1; }
@@ -31,17 +33,20 @@ __host__ __device__ inline int shingle_wpl(int n) {  // bitmap words per lane
   const int bw = shingle_bitmap_words(n);
   return bw >= kWave ? bw / kWave : 1;
 }
-// Lane L owns bitmap words [L WPL, (L + 1) WPL), stored from slot L BS, and
-// their rank bases (u16) from slot L PS: strides padded so that the lanes'
-// 16-byte accesses of one instruction fall on distinct LDS banks.
+// Lane L owns bitmap words [L WPL, (L + 1) WPL), stored from slot L BS; the
+// stride is padded so that the lanes' 16-byte accesses of one instruction
+// fall on distinct LDS banks.  With WPL >= 8 the four padding words hold the
+// lane's rank bases: 8 u16, one per group of WPL / 8 words.  With fewer words
+// per lane the bases (one per word) sit in an array of their own.
 __host__ __device__ inline int shingle_bs(int wpl) { return wpl + (wpl >= 8 ? 4 : 0); }
-__host__ __device__ inline int shingle_ps(int wpl) { return wpl + (wpl >= 16 ? 8 : 0); }
+__host__ __device__ inline int shingle_pre_u16(int wpl) { return wpl >= 8 ? 0 : kWave * wpl; }
 
-// LDS bytes of one wave: bitmap (u32), rank bases (u16, to 16 bytes), counts (u32)
+// LDS bytes of one wave: bitmap (u32) and rank bases, separate bases (u16, to
+// 16 bytes), counts (u32)
 __host__ __device__ inline size_t shingle_lds_bytes(int n) {
   const int wpl = shingle_wpl(n);
   const size_t bm = (size_t)kWave * shingle_bs(wpl) * 4;
-  const size_t pre = ((size_t)kWave * shingle_ps(wpl) * 2 + 15) & ~(size_t)15;
+  const size_t pre = ((size_t)shingle_pre_u16(wpl) * 2 + 15) & ~(size_t)15;
   return bm + pre + (size_t)kCountCap * 4;
 }
 
@@ -75,26 +80,38 @@ __global__ __launch_bounds__(kShWaves * kWave) void shingle_kernel(
     uint32_t* __restrict__ counts, const int64_t* __restrict__ hist_off,
     int32_t* __restrict__ n_distinct, int* err) {
   constexpr int BS = WPL + (WPL >= 8 ? 4 : 0);    // shingle_bs
-  constexpr int PS = WPL + (WPL >= 16 ? 8 : 0);   // shingle_ps
+  constexpr bool PAD = WPL >= 8;                  // rank bases in the padding words
+  constexpr int GS = PAD ? WPL / 8 : 1;           // words per rank base
   constexpr int LW = WPL == 1 ? 0 : (WPL == 2 ? 1 : (WPL == 4 ? 2 : (WPL == 8 ? 3 : (WPL == 16 ? 4 : 5))));
   extern __shared__ __attribute__((aligned(16))) uint32_t smem32[];
   const int BW = shingle_bitmap_words(n);
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave-uniform
   const int lane = lane_id();
   uint32_t* bm = smem32 + (shingle_lds_bytes(n) / 4) * w;
-  uint16_t* pre = reinterpret_cast<uint16_t*>(bm + kWave * BS);
-  uint32_t* cnt = bm + kWave * BS + ((kWave * PS * 2 + 15) & ~15) / 4;
+  uint16_t* pre = reinterpret_cast<uint16_t*>(bm + kWave * BS);  // separate bases (!PAD)
+  uint32_t* cnt = bm + kWave * BS + ((shingle_pre_u16(WPL) * 2 + 15) & ~15) / 4;
   // this lane's words exist (WPL > 1: the bitmap is exactly 64 WPL words)
   const bool own = WPL > 1 || lane < BW;
   uint32_t* mybm = bm + lane * BS;
-  uint16_t* mypre = pre + lane * PS;
+  uint16_t* mypre = PAD ? reinterpret_cast<uint16_t*>(mybm + WPL) : pre + lane * WPL;
   for (int i = lane; i < kWave * BS; i += kWave) bm[i] = 0;
   for (int i = lane; i < kCountCap; i += kWave) cnt[i] = 0;
   wave_sync_lds();
   const uint32_t mask = (1u << n) - 1u;  // n <= 16
-  // slots of word t >> 5
+  // slot of word wd, and the rank of its first token
   auto bslot = [&](uint32_t wd) { return (int)((wd >> LW) * BS + (wd & (WPL - 1))); };
-  auto pslot = [&](uint32_t wd) { return (int)((wd >> LW) * PS + (wd & (WPL - 1))); };
+  auto word_rank = [&](uint32_t wd) -> uint32_t {
+    const int sl = bslot(wd);
+    const int j = (int)(wd & (WPL - 1));
+    if constexpr (PAD) {
+      const uint16_t* lp = reinterpret_cast<const uint16_t*>(bm + (wd >> LW) * BS + WPL);
+      uint32_t r = lp[j / GS];
+      for (int i = j - j % GS; i < j; ++i) r += __builtin_popcount(bm[sl - j + i]);
+      return r;
+    } else {
+      return pre[(wd >> LW) * WPL + j];
+    }
+  };
 
   for (int64_t s = (int64_t)blockIdx.x * kShWaves + w; s < N; s += (int64_t)gridDim.x * kShWaves) {
     const int nb = nbits[s];
@@ -160,16 +177,14 @@ __global__ __launch_bounds__(kShWaves * kWave) void shingle_kernel(
       pv[j] = (uint16_t)rk;
       rk += __builtin_popcount(wv[j]);
     }
-    if constexpr (WPL >= 8) {
-#pragma unroll
-      for (int q = 0; q < WPL / 8; ++q) {
-        uint4 v;
-        v.x = pv[8 * q] | ((uint32_t)pv[8 * q + 1] << 16);
-        v.y = pv[8 * q + 2] | ((uint32_t)pv[8 * q + 3] << 16);
-        v.z = pv[8 * q + 4] | ((uint32_t)pv[8 * q + 5] << 16);
-        v.w = pv[8 * q + 6] | ((uint32_t)pv[8 * q + 7] << 16);
-        reinterpret_cast<uint4*>(mypre)[q] = v;
-      }
+    if constexpr (PAD) {
+      // the bases of word groups 0, GS, 2 GS, ... into the padding words
+      uint4 v;
+      v.x = pv[0] | ((uint32_t)pv[GS] << 16);
+      v.y = pv[2 * GS] | ((uint32_t)pv[3 * GS] << 16);
+      v.z = pv[4 * GS] | ((uint32_t)pv[5 * GS] << 16);
+      v.w = pv[6 * GS] | ((uint32_t)pv[7 * GS] << 16);
+      reinterpret_cast<uint4*>(mypre)[0] = v;
     } else if constexpr (WPL == 4) {
       reinterpret_cast<uint2*>(mypre)[0] =
           make_uint2(pv[0] | ((uint32_t)pv[1] << 16), pv[2] | ((uint32_t)pv[3] << 16));
@@ -190,8 +205,7 @@ __global__ __launch_bounds__(kShWaves * kWave) void shingle_kernel(
     // 3. counts by rank (runs of equal tokens in a lane counted at once), codes at their ranks
     auto flush = [&](uint32_t t, uint32_t run) {
       const uint32_t wd = t >> 5;
-      const uint32_t rank =
-          (uint32_t)pre[pslot(wd)] + __builtin_popcount(bm[bslot(wd)] & ((1u << (t & 31)) - 1u));
+      const uint32_t rank = word_rank(wd) + __builtin_popcount(bm[bslot(wd)] & ((1u << (t & 31)) - 1u));
       if (in_lds) atomicAdd(cnt + rank, run);
       else atomicAdd(counts + ho + rank, run);
       codes[ho + rank] = t;
