@@ -61,10 +61,10 @@ ssh_status band_keys_launch(const uint64_t* hv, int64_t N, int K, int L, uint64_
 // radix sort of (key, id) per table on key bits [32, 64)
 // ---------------------------------------------------------------------------
 constexpr int kRsThreads = 256;
-constexpr int kRsItems = 16;
-constexpr int kRsTile = kRsThreads * kRsItems;  // 4096
+constexpr int kRsItems = 8;
+constexpr int kRsTile = kRsThreads * kRsItems;  // 2048: a 30 KB LDS tile, five workgroups per CU
 constexpr int kRsWaves = kRsThreads / kWave;
-constexpr int kRsPerWave = kWave * kRsItems;   // 1024 contiguous elements per wave
+constexpr int kRsPerWave = kWave * kRsItems;   // 512 contiguous elements per wave
 
 struct RsIn {
   const uint64_t* keys;  // series-major [N * L] when sm, else table-major [L * N]
