@@ -20,40 +20,73 @@ __device__ __forceinline__ uint64_t mix64(uint64_t z) {
   return z ^ (z >> 31);
 }
 
+// Fold of table l's K hash values of series s (hv values in h, stride 1)
+__device__ __forceinline__ uint64_t band_fold(const uint64_t* h, int K, int l, uint64_t seed) {
+  uint64_t k = mix64(seed + (uint64_t)(l + 1) * 0x9E3779B97F4A7C15ull);
+  for (int t = 0; t < K; ++t) k = mix64(k ^ h[t]);
+  return k == SSH_KEY_EMPTY ? SSH_KEY_EMPTY - 1 : k;
+}
+
+constexpr int kBkMaxK = 16;  // bands staged in LDS up to this K
+
+// Item g = s L + l (series s, table l) folds hash values [g K, g K + K):
+// with H = K L the bands of consecutive items are consecutive.  Each wave
+// takes 64 items, loads their 64 K values with coalesced 8-byte loads into LDS
+// and then folds one item per lane.
 __global__ __launch_bounds__(256) void band_keys_kernel(const uint64_t* __restrict__ hv, int64_t N,
                                                         int K, int L, uint64_t seed,
                                                         uint64_t* __restrict__ keys) {
+  __shared__ __attribute__((aligned(16))) uint64_t st[4][kWave * kBkMaxK];
+  const int64_t total = N * (int64_t)L;
+  const int H = K * L;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int lane = lane_id();
+  for (int64_t g0 = ((int64_t)blockIdx.x * 4 + w) * kWave; g0 < total;
+       g0 += (int64_t)gridDim.x * 4 * kWave) {
+    const int n_items = total - g0 < kWave ? (int)(total - g0) : kWave;
+    const int nv = n_items * K;
+    const uint64_t* src = hv + g0 * K;
+    if ((((uintptr_t)src) & 15) == 0 && (nv & 1) == 0) {  // 16-byte loads of value pairs
+      const ulonglong2* s2 = reinterpret_cast<const ulonglong2*>(src);
+      ulonglong2* d2 = reinterpret_cast<ulonglong2*>(st[w]);
+      for (int j = lane; j < nv / 2; j += kWave) d2[j] = s2[j];
+    } else {
+      for (int j = lane; j < nv; j += kWave) st[w][j] = src[j];
+    }
+    wave_sync_lds();
+    if (lane < n_items) {
+      const int64_t g = g0 + lane;
+      const int64_t s = g / L;
+      const int l = (int)(g - s * L);
+      keys[g] = hv[s * H] == SSH_HV_EMPTY ? SSH_KEY_EMPTY : band_fold(&st[w][lane * K], K, l, seed);
+    }
+    wave_sync_lds();
+  }
+}
+
+// K > kBkMaxK: one thread per item, straight from global memory
+__global__ __launch_bounds__(256) void band_keys_wide_kernel(const uint64_t* __restrict__ hv,
+                                                             int64_t N, int K, int L, uint64_t seed,
+                                                             uint64_t* __restrict__ keys) {
   const int64_t total = N * (int64_t)L;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int H = K * L;
   for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += stride) {
     const int64_t s = g / L;
     const int l = (int)(g - s * L);
-    const uint64_t* h = hv + s * H + (int64_t)l * K;
-    if (hv[s * H] == SSH_HV_EMPTY) {
-      keys[g] = SSH_KEY_EMPTY;
-      continue;
-    }
-    uint64_t k = mix64(seed + (uint64_t)(l + 1) * 0x9E3779B97F4A7C15ull);
-    int t = 0;
-    if ((((uintptr_t)h) & 15) == 0) {  // 16-byte aligned band: two values per load
-      const ulonglong2* h2 = reinterpret_cast<const ulonglong2*>(h);
-      for (; t + 2 <= K; t += 2) {
-        const ulonglong2 v = h2[t / 2];
-        k = mix64(k ^ v.x);
-        k = mix64(k ^ v.y);
-      }
-    }
-    for (; t < K; ++t) k = mix64(k ^ h[t]);
-    keys[g] = k == SSH_KEY_EMPTY ? SSH_KEY_EMPTY - 1 : k;
+    keys[g] = hv[s * H] == SSH_HV_EMPTY ? SSH_KEY_EMPTY : band_fold(hv + g * K, K, l, seed);
   }
 }
 
 ssh_status band_keys_launch(const uint64_t* hv, int64_t N, int K, int L, uint64_t seed,
                             uint64_t* keys, hipStream_t stream) {
   if (N == 0) return SSH_OK;
-  band_keys_kernel<<<grid_for(N * (int64_t)L, 256, 1 << 16), 256, 0, stream>>>(hv, N, K, L, seed,
-                                                                              keys);
+  if (K <= kBkMaxK)
+    band_keys_kernel<<<grid_for(N * (int64_t)L, 256, 1 << 16), 256, 0, stream>>>(hv, N, K, L, seed,
+                                                                                keys);
+  else
+    band_keys_wide_kernel<<<grid_for(N * (int64_t)L, 256, 1 << 16), 256, 0, stream>>>(hv, N, K, L,
+                                                                                     seed, keys);
   return check_launch("ssh_band_keys");
 }
 
