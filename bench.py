@@ -46,7 +46,7 @@ MEASURED_TRAFFIC = {
     #          FETCH_SIZE and 1048576 KiB on WRITE_SIZE
     "cws_kernel": ("paper_1610_07328_amd/csrc/cws.hip",
                    "db00d1f403483950bb4245a4823a74444d3b47138db3a41f011bcf48d75e13d2",
-                   3770756.6875, 926856.28125, 1048576.0 / 524306.9375, 1.0),
+                   3767494.0625, 926830.15625, 1048576.0 / 524306.9375, 1.0),
 }
 
 
