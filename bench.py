@@ -45,8 +45,8 @@ MEASURED_TRAFFIC = {
     #          fetch scale, write scale); the 1 GiB copy read 524306.9 KiB on
     #          FETCH_SIZE and 1048576 KiB on WRITE_SIZE
     "cws_kernel": ("paper_1610_07328_amd/csrc/cws.hip",
-                   "db00d1f403483950bb4245a4823a74444d3b47138db3a41f011bcf48d75e13d2",
-                   3767494.0625, 926830.15625, 1048576.0 / 524306.9375, 1.0),
+                   "e9049779b67760bf1a545bc96c30f9365858ecab1873cd3fa6b026f80a22103e",
+                   3576059.5, 798727.53125, 1048576.0 / 524306.9375, 1.0),
 }
 
 

@@ -227,7 +227,7 @@ struct CwsDev {
 };
 
 constexpr int kCwsWaves = 4;  // wavefronts per workgroup
-constexpr int kPassA = 8;     // keyed tokens whose keys are loaded together
+constexpr int kPassA = 16;     // keyed tokens whose keys are loaded together
 constexpr int kHeavyCap = 64; // heavy tokens listed per series in LDS
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 
@@ -254,7 +254,7 @@ struct Best {
   double t;
 };
 
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) void cws_kernel(const uint32_t* __restrict__ codes,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void cws_kernel(const uint32_t* __restrict__ codes,
                                                   const uint32_t* __restrict__ counts,
                                                   const int64_t* __restrict__ hist_off,
                                                   const int32_t* __restrict__ n_distinct, int64_t N,
