@@ -248,7 +248,8 @@ def main():
         "shingle": N * (8 * words + 4 + 4) + 16 * (N + 1) + 8 * sum_d,
         "cws": 8 * sum_d + N * (8 * p.H + 4 + 8),
         "band_keys": N * (8 * p.H + 8 * p.L),
-        "table_build": 4 * N * p.L * (8 + 12 + 12),
+        # radix passes over the top 24 bits (N <= 2^20) or 32: keys and ids read twice, written once
+        "table_build": (3 if N <= (1 << 20) else 4) * N * p.L * (8 + 12 + 12),
     }
     stage_roofline = {}
     for name, b in bytes_stage.items():

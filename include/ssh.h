@@ -181,9 +181,10 @@ ssh_status ssh_band_keys(const uint64_t* hv, int64_t N, int32_t K, int32_t L, ui
 size_t ssh_table_workspace_bytes(int64_t N, int32_t L);
 
 /* Hash tables (Algorithm 1).  Table l lists every (key, id) pair of the batch
- * ordered by the high 32 bits of the key, ids ascending among equal high
- * halves (a stable sort of ids 0..N-1).  A bucket is the set of ids with one
- * full key.
+ * ordered by the top B bits of the key, B = 24 when N <= 2^20 and 32
+ * otherwise, ids ascending among equal top bits (a stable sort of ids
+ * 0..N-1).  A bucket is the set of ids with one full key; ssh_probe finds it
+ * inside the run of its top B bits.
  *   keys         uint64 [N * L] from ssh_band_keys; N <= 2^32 - 1
  *   tab_keys     uint64 [L * N] output, table-major
  *   tab_ids      uint32 [L * N] output, table-major

@@ -28,6 +28,7 @@ from .ssh_oracle import (  # noqa: F401
     hv_encode,
     mix64,
     band_keys,
+    table_sort_bits,
     build_tables,
     probe,
     band_radius,

@@ -208,18 +208,26 @@ def band_keys(hv, K: int, L: int, seed: int) -> np.ndarray:
     return keys
 
 
-def build_tables(keys):
-    """Per table l: every (key, id) pair, ordered by the high 32 bits of the key.
+def table_sort_bits(N: int) -> int:
+    """Top bits of a key the tables are ordered by: 24 for N <= 2^20, else 32."""
+    return 24 if N <= (1 << 20) else 32
 
-    The order among equal high halves is ascending id.  Returns
-    (tab_keys [L, N] uint64, tab_ids [L, N] uint32).
+
+def build_tables(keys):
+    """Per table l: every (key, id) pair, ordered by the top B bits of the key
+    (B = table_sort_bits(N)).
+
+    The tables only have to let a bucket (the ids of one full key) be found;
+    the order is the library's layout contract.  The order among equal top
+    bits is ascending id.  Returns (tab_keys [L, N] uint64, tab_ids [L, N] uint32).
     """
     keys = np.asarray(keys, dtype=np.uint64)
     N, L = keys.shape
+    sh = np.uint64(64 - table_sort_bits(N))
     tk = np.empty((L, N), np.uint64)
     ti = np.empty((L, N), np.uint32)
     for l in range(L):
-        order = np.argsort(keys[:, l] >> np.uint64(32), kind="stable")
+        order = np.argsort(keys[:, l] >> sh, kind="stable")
         tk[l] = keys[order, l]
         ti[l] = order.astype(np.uint32)
     return tk, ti

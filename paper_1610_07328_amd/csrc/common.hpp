@@ -32,6 +32,13 @@ inline unsigned grid_for(int64_t items, int64_t per_block, int64_t cap = 65536) 
   return (unsigned)g;
 }
 
+// Top bits of a band key that the hash tables are sorted on (and that the
+// probe searches): 24 while N <= 2^20, where a bucket's run holds on average
+// at most 1/16 of an entry of another key, else 32.
+__host__ __device__ inline int table_sort_bits(int64_t N) {
+  return N <= ((int64_t)1 << 20) ? 24 : 32;
+}
+
 // ---------------------------------------------------------------------------
 // device-side helpers
 // ---------------------------------------------------------------------------

@@ -3,8 +3,9 @@
 //
 // Three launches:
 //  1. runs: one wavefront per query.  Per table, two searches (lanes 0-31 the
-//     start, lanes 32-63 the end) find the run of entries whose high key half
-//     equals the query's; the runs of all tables, concatenated, are the
+//     start, lanes 32-63 the end) find the run of entries whose top key bits
+//     (the bits the tables are sorted on) equal the query's; the runs of all
+//     tables, concatenated, are the
 //     query's G entries.  Entries of a run with the query's full key are the
 //     bucket.
 //  2. parts: the G entries of a query are cut into F contiguous slices, one
@@ -104,13 +105,14 @@ __global__ __launch_bounds__(kWave) void probe_runs_kernel(ProbeCtx c,
     const int l = l0 + t;
     int64_t bound = 0;
     if (l < c.L && !empty) {
-      // half 0: first entry with high half >= the query's; half 1: first > it
+      // half 0: first entry whose top bits are >= the query's; half 1: first >
       const uint64_t* tk = c.tab_keys + (int64_t)l * c.N;
-      const uint32_t hi = (uint32_t)(qk[l] >> 32);
+      const int sh = 64 - table_sort_bits(c.N);
+      const uint64_t hi = qk[l] >> sh;
       int64_t a = 0, b = c.N;
       while (a < b) {
         const int64_t mid = (a + b) >> 1;
-        const uint32_t v = (uint32_t)(tk[mid] >> 32);
+        const uint64_t v = tk[mid] >> sh;
         if (half == 0 ? v < hi : v <= hi) a = mid + 1;
         else b = mid;
       }

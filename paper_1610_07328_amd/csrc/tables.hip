@@ -3,8 +3,10 @@
 //
 // Keys: table l folds its K hash values with the SplitMix64 output function.
 // Tables: the keys [N][L] are first transposed to table-major [L][N]; then,
-// per table, a stable LSD radix sort of (key, id) on the high 32 bits of the
-// key, four 8-bit digit passes.  Each pass is four launches over all tables at
+// per table, a stable LSD radix sort of (key, id) on the top B bits of the
+// key (table_sort_bits: 24 for N <= 2^20, else 32), B / 8 digit passes: the
+// probe finds a bucket by the run of its top B bits, and 24 bits keep runs
+// short at that size.  Each pass is four launches over all tables at
 // once: per-tile digit histograms, a segmented reduce and then scan of the
 // (digit, tile) counts, and a stable scatter.  The scatter ranks elements
 // inside a wavefront with a ballot-based match of equal digits, keeps one
@@ -360,30 +362,27 @@ ssh_status table_build_launch(const uint64_t* keys, int64_t N, int L, uint64_t* 
   const int64_t seg = (ceil_div(n, nseg) + 3) & ~(int64_t)3;
   nseg = (int)ceil_div(n, seg);
   const dim3 sgrid(nseg, L);
-  // With L <= kTrMaxL the keys are first transposed into tab_keys, so every
-  // pass reads table-major: (keys ->) tab -> alt -> tab -> alt -> tab.
-  // Otherwise pass 0 reads the series-major keys: keys -> alt -> tab -> alt -> tab.
+  // The passes alternate between the output (tab) and the workspace (alt),
+  // the last one writing tab.  With L <= kTrMaxL the keys are first
+  // transposed into the buffer pass 0 does not write, so every pass reads
+  // table-major; otherwise pass 0 reads the series-major keys.
+  const int passes = table_sort_bits(N) / 8;
+  auto to_tab = [&](int pass) { return (passes - 1 - pass) % 2 == 0; };
   const bool transposed = L <= kTrMaxL;
+  uint64_t* tr = to_tab(0) ? alt_keys : tab_keys;
   if (transposed)
-    keys_transpose_kernel<<<(unsigned)ceil_div(N, kTrRows), 256, 0, stream>>>(keys, N, L, tab_keys);
-  for (int pass = 0; pass < 4; ++pass) {
-    const int shift = 32 + 8 * pass;
+    keys_transpose_kernel<<<(unsigned)ceil_div(N, kTrRows), 256, 0, stream>>>(keys, N, L, tr);
+  for (int pass = 0; pass < passes; ++pass) {
+    const int shift = 64 - 8 * passes + 8 * pass;
     RsIn in;
-    uint64_t* ok;
-    uint32_t* oi;
-    if (pass == 0) {
-      in = transposed ? RsIn{tab_keys, nullptr, true, false} : RsIn{keys, nullptr, true, true};
-      ok = alt_keys;
-      oi = alt_ids;
-    } else if (pass % 2 == 1) {
+    if (pass == 0)
+      in = transposed ? RsIn{tr, nullptr, true, false} : RsIn{keys, nullptr, true, true};
+    else if (to_tab(pass))
       in = RsIn{alt_keys, alt_ids, false, false};
-      ok = tab_keys;
-      oi = tab_ids;
-    } else {
+    else
       in = RsIn{tab_keys, tab_ids, false, false};
-      ok = alt_keys;
-      oi = alt_ids;
-    }
+    uint64_t* ok = to_tab(pass) ? tab_keys : alt_keys;
+    uint32_t* oi = to_tab(pass) ? tab_ids : alt_ids;
     rs_hist_kernel<<<grid, kRsThreads, 0, stream>>>(in, N, L, shift, nblk, hist);
     rs_reduce_kernel<<<sgrid, kRsThreads, 0, stream>>>(hist, n, seg, seg_sum);
     rs_scan_kernel<<<sgrid, kRsThreads, 0, stream>>>(hist, n, seg, seg_sum);

@@ -4,7 +4,7 @@ The oracle computes sampled outputs one by one: the bits, tokens, hash values
 and keys of sampled series and queries, and the DTW re-rank of sampled queries.
 What it cannot compute at this size is checked through properties that hold at
 any size:
-* every hash table is a stable order of (key, id) by the key's high half;
+* every hash table is a stable order of (key, id) by the key's top bits;
 * every query's candidates are exactly the first C members of its retrieved
   set, ranked by (shared hash values desc, id asc), which torch recomputes from
   the same keys and hash values.
@@ -78,12 +78,14 @@ def _check_sampled_hash(hb: HashBatch, x, off, r, draws, p: Params, sample):
 
 
 def _check_tables(ix: Index, N: int, L: int):
-    """Each table: a permutation of the ids, keys in place, stable by the high half."""
+    """Each table: a permutation of the ids, keys in place, stable by the top
+    table_sort_bits(N) bits."""
     keys = ix.db.keys[:N].view(torch.int64)
+    B = oracle.table_sort_bits(N)
     for l in range(L):
         tk = ix.tab_keys[l, :N].view(torch.int64)
         ti = ix.tab_ids[l, :N].view(torch.int32).to(torch.int64)  # ids < 2^31
-        hi = (tk >> 32) & 0xFFFFFFFF
+        hi = (tk >> (64 - B)) & ((1 << B) - 1)
         assert bool((hi[1:] >= hi[:-1]).all()), l
         eq = hi[1:] == hi[:-1]
         assert bool((ti[1:][eq] > ti[:-1][eq]).all()), l

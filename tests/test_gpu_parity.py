@@ -348,8 +348,12 @@ def test_c1_hash_values_and_keys_exact(ssh, c1):
     assert torch.equal(hv.cpu(), hv2.cpu()) and torch.equal(keys.cpu(), keys2.cpu())
 
 
-@pytest.mark.parametrize("N,L,distinct", [(2000, 5, None), (10007, 3, 50), (4096, 2, 1)])
+@pytest.mark.parametrize("N,L,distinct", [(2000, 5, None), (10007, 3, 50), (4096, 2, 1),
+                                          (3000, 65, 40), (1 << 20, 2, 300),
+                                          ((1 << 20) + 1, 2, 300)])
 def test_table_build_exact(ssh, N, L, distinct):
+    """Tables sorted on the top 24 bits (three passes, N <= 2^20) or 32 bits (four),
+    table-major or, for L > 64, straight from the series-major keys."""
     _announce(f"table build N={N} L={L}")
     rng = np.random.default_rng(N)
     if distinct is None:
@@ -364,6 +368,16 @@ def test_table_build_exact(ssh, N, L, distinct):
     otk, oti = oracle.build_tables(keys)
     assert np.array_equal(to_np(tk), otk)
     assert np.array_equal(to_np(ti), oti)
+    if N > 1 << 20:  # the probe's search over the 32-bit order, against the brute-force oracle
+        hv = rng.integers(0, 4, size=(N, 6), dtype=np.int64).astype(np.uint64)
+        qs = [0, 1, 5, N - 1]
+        cand, ncand, rs = ssh.probe(tk, ti, to_dev(keys), to_dev(hv), to_dev(keys[qs]),
+                                    to_dev(hv[qs]), 20)
+        torch.cuda.synchronize()
+        cand, ncand, rs = to_np(cand), to_np(ncand), to_np(rs)
+        for i, qi in enumerate(qs):
+            oc, orr = oracle.probe(keys, hv, keys[qi], hv[qi], 20)
+            assert rs[i] == orr and np.array_equal(cand[i, : ncand[i]], oc), qi
 
 
 def test_c1_probe_exact(ssh, c1):

@@ -326,12 +326,14 @@ def _tiny_index(seed=12, N=60, L=3, H=6):
     return keys, hv
 
 
-def test_tables_are_stable_order_by_high_half():
+def test_tables_are_stable_order_by_top_bits():
     keys, _ = _tiny_index()
     tk, ti = oracle.build_tables(keys)
     N, L = keys.shape
+    assert oracle.table_sort_bits(N) == 24 and oracle.table_sort_bits(1 << 20) == 24
+    assert oracle.table_sort_bits((1 << 20) + 1) == 32
     for l in range(L):
-        want = sorted(range(N), key=lambda i: (int(keys[i, l]) >> 32, i))
+        want = sorted(range(N), key=lambda i: (int(keys[i, l]) >> 40, i))
         assert ti[l].tolist() == want
         assert tk[l].tolist() == [int(keys[i, l]) for i in want]
 
