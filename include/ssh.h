@@ -10,6 +10,7 @@
  *   ssh_cws        weighted MinHash values by consistent weighted sampling
  *                  (Section 4.3; Section 2, eqs. WJaccardDef / CollProb)
  *   ssh_band_keys  one key per hash table from K hash values     (Algorithm 1)
+ *   ssh_cws_band_keys  the two above in one pass
  *   ssh_table_build  the L hash tables                           (Algorithm 1)
  *   ssh_probe      retrieved set R of each query, ranked         (Algorithm 2)
  *   dtw_rerank     top-k of R by banded DTW distance             (Section 2.1,
@@ -176,6 +177,17 @@ ssh_status ssh_cws(const uint32_t* codes, const uint32_t* counts, const int64_t*
  *   keys         uint64 [N * L] output, series-major */
 ssh_status ssh_band_keys(const uint64_t* hv, int64_t N, int32_t K, int32_t L, uint64_t seed,
                          uint64_t* keys, void* stream);
+
+/* ssh_cws and ssh_band_keys in one pass (Section 4.3, then Algorithm 1): hv
+ * and keys are exactly what ssh_cws followed by ssh_band_keys(hv, N, K, L,
+ * seed) write, with the keys folded from the hash values while the CWS kernel
+ * still holds them, so hv is not read back.  Shapes with H > 640 run the two
+ * steps as separate kernels.  Arguments as for those two calls; additionally
+ * returns SSH_EINVAL unless K * L == tab->H. */
+ssh_status ssh_cws_band_keys(const uint32_t* codes, const uint32_t* counts,
+                             const int64_t* hist_off, const int32_t* n_distinct, int64_t N,
+                             const ssh_cws_tables* tab, int32_t K, int32_t L, uint64_t seed,
+                             uint64_t* hv, uint64_t* keys, void* stream);
 
 /* [host] Workspace bytes needed by ssh_table_build for N series and L tables. */
 size_t ssh_table_workspace_bytes(int64_t N, int32_t L);

@@ -32,7 +32,7 @@ ssh_status shingle_launch(const uint64_t* bits, const int64_t* bit_word_off, con
 ssh_status cws_prepare_launch(const ssh_cws_tables* tab, hipStream_t stream);
 ssh_status cws_launch(const uint32_t* codes, const uint32_t* counts, const int64_t* hist_off,
                       const int32_t* n_distinct, int64_t N, const ssh_cws_tables* tab, uint64_t* hv,
-                      hipStream_t stream);
+                      uint64_t* keys, int K, int L, uint64_t seed, hipStream_t stream);
 ssh_status band_keys_launch(const uint64_t* hv, int64_t N, int K, int L, uint64_t seed,
                             uint64_t* keys, hipStream_t stream);
 size_t table_workspace_bytes(int64_t N, int L);
@@ -178,7 +178,24 @@ ssh_status ssh_cws(const uint32_t* codes, const uint32_t* counts, const int64_t*
   SSH_REQUIRE(N >= 0, "ssh_cws: N < 0");
   if (N == 0) return SSH_OK;
   SSH_REQUIRE(codes && counts && hist_off && n_distinct && hv, "ssh_cws: null pointer");
-  return cws_launch(codes, counts, hist_off, n_distinct, N, tab, hv, as_stream(stream));
+  return cws_launch(codes, counts, hist_off, n_distinct, N, tab, hv, nullptr, 0, 0, 0,
+                    as_stream(stream));
+}
+
+ssh_status ssh_cws_band_keys(const uint32_t* codes, const uint32_t* counts,
+                             const int64_t* hist_off, const int32_t* n_distinct, int64_t N,
+                             const ssh_cws_tables* tab, int32_t K, int32_t L, uint64_t seed,
+                             uint64_t* hv, uint64_t* keys, void* stream) {
+  ssh_status st = check_tables(tab, "ssh_cws_band_keys");
+  if (st != SSH_OK) return st;
+  SSH_REQUIRE(N >= 0, "ssh_cws_band_keys: N < 0");
+  SSH_REQUIRE(K >= 1 && L >= 1, "ssh_cws_band_keys: K or L < 1");
+  SSH_REQUIRE((int64_t)K * L == tab->H, "ssh_cws_band_keys: K * L != H");
+  if (N == 0) return SSH_OK;
+  SSH_REQUIRE(codes && counts && hist_off && n_distinct && hv && keys,
+              "ssh_cws_band_keys: null pointer");
+  return cws_launch(codes, counts, hist_off, n_distinct, N, tab, hv, keys, K, L, seed,
+                    as_stream(stream));
 }
 
 ssh_status ssh_band_keys(const uint64_t* hv, int64_t N, int32_t K, int32_t L, uint64_t seed,

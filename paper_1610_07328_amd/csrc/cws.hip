@@ -30,9 +30,10 @@
 //     their ln S (beyond that, pass B relists them one chunk at a time); every
 //     lane evaluates each of them exactly for its two hashes and compares by
 //     (ln a, k) with the pass-A winner, whose ln a is then evaluated exactly.
+#include <algorithm>
 #include <cmath>
 
-#include "common.hpp"
+#include "band.hpp"
 
 namespace ssh {
 
@@ -229,6 +230,7 @@ struct CwsDev {
 constexpr int kCwsWaves = 4;  // wavefronts per workgroup
 constexpr int kPassA = 16;     // keyed tokens whose keys are loaded together
 constexpr int kHeavyCap = 64; // heavy tokens listed per series in LDS
+constexpr int kBandLds = 640; // hash values kept per wave in LDS for the fused band keys
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 
 // median of three; with a <= b it is the second smallest of {a, b, c}
@@ -254,16 +256,29 @@ struct Best {
   double t;
 };
 
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void cws_kernel(const uint32_t* __restrict__ codes,
-                                                  const uint32_t* __restrict__ counts,
-                                                  const int64_t* __restrict__ hist_off,
-                                                  const int32_t* __restrict__ n_distinct, int64_t N,
-                                                  CwsDev t, uint64_t* __restrict__ hv, int* err) {
+// Band keys computed by the CWS kernel from the hash values it holds (H = K L,
+// H <= kBandLds): the same fold as the band-key kernel.  A wave keeps the hash
+// values of G consecutive series of its own in LDS and folds their G L bands
+// at once, one band per lane.
+struct BandOut {
+  uint64_t* keys;  // [N][L]
+  int K, L;
+  uint64_t seed;
+  int G;  // series per fold: min(64 / L, kBandLds / H), at least 1
+};
+
+template <bool KEYS>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void cws_kernel(
+    const uint32_t* __restrict__ codes, const uint32_t* __restrict__ counts,
+    const int64_t* __restrict__ hist_off, const int32_t* __restrict__ n_distinct, int64_t N,
+    CwsDev t, uint64_t* __restrict__ hv, int* err, BandOut bo) {
   // per wave: keyed-token list (row byte offset, position), padded to whole
   // groups with the padding row, and the heavy-token list (position)
   __shared__ uint4 klist[kCwsWaves][kWave / 2];
   // heavy tokens of the series: (code, count, ln count as two words)
   __shared__ uint4 hl[kCwsWaves][kHeavyCap];
+  // hash values of the last G series, for the band keys
+  __shared__ uint64_t hvs[kCwsWaves][KEYS ? kBandLds : 1];
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave-uniform
   const int lane = lane_id();
   const int H = t.H;
@@ -274,12 +289,33 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void c
       (void*)t.k16, 0, (int)(pad_row + row_bytes), 0x00020000);
   uint2* klist2 = reinterpret_cast<uint2*>(klist[w]);
   const uint64_t lt_mask = (1ull << lane) - 1ull;
-  for (int64_t s = (int64_t)blockIdx.x * kCwsWaves + w; s < N;
-       s += (int64_t)gridDim.x * kCwsWaves) {
+  const int64_t stride = (int64_t)gridDim.x * kCwsWaves;
+  int slot = 0;  // series held in hvs since the last fold
+  // after series s: fold the held series once G are held or s is the wave's last
+  auto band_step = [&](int64_t s) {
+    if constexpr (KEYS) {
+      if (++slot < bo.G && s + stride < N) return;
+      wave_sync_lds();
+      for (int i = lane; i < slot * bo.L; i += kWave) {
+        const int g = i / bo.L, l = i - g * bo.L;
+        const uint64_t* hr = &hvs[w][g * H];
+        const int64_t sg = s - (int64_t)(slot - 1 - g) * stride;
+        bo.keys[sg * bo.L + l] =
+            hr[0] == SSH_HV_EMPTY ? SSH_KEY_EMPTY : band_fold(hr + l * bo.K, bo.K, l, bo.seed);
+      }
+      wave_sync_lds();
+      slot = 0;
+    }
+  };
+  for (int64_t s = (int64_t)blockIdx.x * kCwsWaves + w; s < N; s += stride) {
     const int D = n_distinct[s];
     uint64_t* out = hv + s * H;
+    uint64_t* held = KEYS ? &hvs[w][slot * H] : nullptr;
     if (D <= 0) {
       for (int j = lane; j < H; j += kWave) out[j] = SSH_HV_EMPTY;
+      if constexpr (KEYS)
+        if (lane == 0) held[0] = SSH_HV_EMPTY;  // the fold tests the first value only
+      band_step(s);
       continue;
     }
     const int64_t ho = hist_off[s];
@@ -449,10 +485,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void c
       for (int h = 0; h < 2; ++h) {
         if (h ? v1 : v0) {
           const uint64_t tq = (uint64_t)(b[h].t < tmax ? b[h].t : tmax);
-          out[h ? j1 : j0] = (tq << 16) | (uint64_t)b[h].k;
+          const uint64_t v = (tq << 16) | (uint64_t)b[h].k;
+          out[h ? j1 : j0] = v;
+          if constexpr (KEYS) held[h ? j1 : j0] = v;
         }
       }
     }
+    band_step(s);
   }
 }
 
@@ -475,9 +514,14 @@ ssh_status cws_prepare_launch(const ssh_cws_tables* tab, hipStream_t stream) {
   return check_launch("ssh_cws_prepare");
 }
 
+ssh_status band_keys_launch(const uint64_t* hv, int64_t N, int K, int L, uint64_t seed,
+                            uint64_t* keys, hipStream_t stream);
+
+// keys == nullptr: hash values only; else also the band keys of (K, L, seed),
+// in the same kernel while H fits its LDS copy, else by the band-key kernel
 ssh_status cws_launch(const uint32_t* codes, const uint32_t* counts, const int64_t* hist_off,
                       const int32_t* n_distinct, int64_t N, const ssh_cws_tables* tab, uint64_t* hv,
-                      hipStream_t stream) {
+                      uint64_t* keys, int K, int L, uint64_t seed, hipStream_t stream) {
   if (N == 0) return SSH_OK;
   int* err = nullptr;
   if (hipGetSymbolAddress((void**)&err, HIP_SYMBOL(g_cws_err)) != hipSuccess)
@@ -487,9 +531,19 @@ ssh_status cws_launch(const uint32_t* codes, const uint32_t* counts, const int64
   if (key_rows(tab->n) * H2 * 2 >= (1ll << 31))
     return fail(SSH_EUNSUPPORTED, "ssh_cws: key table of 2 GiB or more");
   CwsDev t{tab->r, tab->lnc, tab->beta, tab->a1, tab->lnS, tab->k16, tab->H, H2, tab->n};
-  cws_kernel<<<grid_for(N, kCwsWaves, 1 << 16), 256, 0, stream>>>(codes, counts, hist_off,
-                                                                   n_distinct, N, t, hv, err);
-  return check_launch("ssh_cws");
+  const unsigned grid = grid_for(N, kCwsWaves, 1 << 16);
+  const bool fused = keys != nullptr && tab->H <= kBandLds;
+  if (fused) {
+    const int G = std::max(1, std::min(kWave / L, kBandLds / tab->H));
+    cws_kernel<true><<<grid, 256, 0, stream>>>(codes, counts, hist_off, n_distinct, N, t, hv, err,
+                                               BandOut{keys, K, L, seed, G});
+  } else {
+    cws_kernel<false><<<grid, 256, 0, stream>>>(codes, counts, hist_off, n_distinct, N, t, hv, err,
+                                                BandOut{nullptr, 0, 0, 0, 1});
+  }
+  ssh_status st = check_launch("ssh_cws");
+  if (st != SSH_OK || keys == nullptr || fused) return st;
+  return band_keys_launch(hv, N, K, L, seed, keys, stream);
 }
 
 }  // namespace ssh

@@ -26,7 +26,7 @@
 namespace ssh {
 
 constexpr int kCountCap = 256;  // distinct tokens whose counts stay in LDS
-constexpr int kShWaves = 4;     // wavefronts per workgroup
+constexpr int kShWaves = 1;     // wavefronts per workgroup
 
 __host__ __device__ inline int shingle_bitmap_words(int n) { return n > 5 ? 1 << (n - 5) : 1; }
 __host__ __device__ inline int shingle_wpl(int n) {  // bitmap words per lane

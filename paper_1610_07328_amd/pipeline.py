@@ -72,11 +72,15 @@ class HashBatch:
     def band_keys(self):
         ssh.band_keys(self.hv[: self.N], self.p.K, self.p.L, self.p.key_seed, out=self.keys)
 
+    def cws_band_keys(self, tables: ssh.CwsTables):
+        """CWS and band keys in one kernel pass (same results as cws() then band_keys())."""
+        ssh.cws_band_keys(self.codes, self.counts, self.hoff, self.ndist, tables, self.p.K,
+                          self.p.L, self.p.key_seed, out=(self.hv, self.keys))
+
     def run(self, r: np.ndarray, tables: ssh.CwsTables):
         self.sketch(r)
         self.shingle()
-        self.cws(tables)
-        self.band_keys()
+        self.cws_band_keys(tables)
         return self.hv[: self.N], self.keys[: self.N]
 
 

@@ -56,6 +56,8 @@ SIGNATURES = {
     "ssh_cws_prepare": (_i32, [ctypes.POINTER(_CwsTablesC), _vp]),
     "ssh_cws": (_i32, [_vp, _vp, _vp, _vp, _i64, ctypes.POINTER(_CwsTablesC), _vp, _vp]),
     "ssh_band_keys": (_i32, [_vp, _i64, _i32, _i32, _u64, _vp, _vp]),
+    "ssh_cws_band_keys": (_i32, [_vp, _vp, _vp, _vp, _i64, ctypes.POINTER(_CwsTablesC), _i32,
+                                 _i32, _u64, _vp, _vp, _vp]),
     "ssh_table_workspace_bytes": (_sz, [_i64, _i32]),
     "ssh_table_build": (_i32, [_vp, _i64, _i32, _vp, _vp, _vp, _sz, _vp]),
     "ssh_probe_workspace_bytes": (_sz, [_i32, _i32, _i32]),
@@ -232,6 +234,24 @@ def band_keys(hv: torch.Tensor, K: int, L: int, seed: int, out=None):
     _check(lib().ssh_band_keys(_dev(hv, torch.uint64, "hv"), N, K, L, seed & ((1 << 64) - 1),
                                _dev(keys, torch.uint64, "keys"), _stream()), "ssh_band_keys")
     return keys[:N]
+
+
+def cws_band_keys(codes, counts, hist_off, n_distinct, tables: CwsTables, K: int, L: int,
+                  seed: int, out=None):
+    """CWS hash values and band keys in one pass; returns (hv [N, H], keys [N, L])."""
+    N = hist_off.numel() - 1
+    dev = codes.device
+    hv, keys = out if out is not None else (
+        torch.empty((max(N, 1), tables.H), dtype=torch.uint64, device=dev),
+        torch.empty((max(N, 1), L), dtype=torch.uint64, device=dev))
+    if hv.numel() < N * tables.H or keys.numel() < N * L:
+        raise SSHError("cws_band_keys: output buffers too small")
+    _check(lib().ssh_cws_band_keys(
+        _dev(codes, torch.uint32, "codes"), _dev(counts, torch.uint32, "counts"),
+        _dev(hist_off, torch.int64, "hist_off"), _dev(n_distinct, torch.int32, "n_distinct"), N,
+        ctypes.byref(tables._c), K, L, seed & ((1 << 64) - 1), _dev(hv, torch.uint64, "hv"),
+        _dev(keys, torch.uint64, "keys"), _stream()), "ssh_cws_band_keys")
+    return hv.view(-1)[: N * tables.H].view(N, tables.H), keys.view(-1)[: N * L].view(N, L)
 
 
 def table_workspace_bytes(N: int, L: int) -> int:

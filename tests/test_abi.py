@@ -33,7 +33,7 @@ def _declared_functions():
 
 def test_header_declares_the_pipeline():
     names = _declared_functions()
-    for want in ["ssh_sketch", "ssh_shingle", "ssh_cws", "ssh_band_keys", "dtw_rerank",
+    for want in ["ssh_sketch", "ssh_shingle", "ssh_cws", "ssh_band_keys", "ssh_cws_band_keys", "dtw_rerank",
                  "ssh_table_build", "ssh_probe", "ssh_plan", "ssh_cws_prepare"]:
         assert want in names
 
@@ -102,6 +102,17 @@ def test_validation_rejects_without_device_work(ssh):
     # CWS tables with n out of range
     t = ssh._CwsTablesC(17, 4, 16, 16, 16, 16, 16, 16)
     assert L.ssh_cws_prepare(ctypes.byref(t), None) == EINVAL
+    # fused CWS + band keys: K * L must equal H, and no null output
+    t = ssh._CwsTablesC(4, 12, 16, 16, 16, 16, 16, 16)
+    assert L.ssh_cws_band_keys(dummy, dummy, dummy, dummy, 4, ctypes.byref(t), 5, 2, 7, dummy,
+                               dummy, None) == EINVAL
+    assert b"K * L" in L.ssh_last_error()
+    assert L.ssh_cws_band_keys(dummy, dummy, dummy, dummy, 4, ctypes.byref(t), 0, 12, 7, dummy,
+                               dummy, None) == EINVAL
+    assert L.ssh_cws_band_keys(dummy, dummy, dummy, dummy, 4, ctypes.byref(t), 3, 4, 7, dummy,
+                               None, None) == EINVAL
+    assert L.ssh_cws_band_keys(None, None, None, None, 0, ctypes.byref(t), 3, 4, 7, None,
+                               None, None) == 0
     assert L.ssh_status_str(EUNSUP) == b"SSH_EUNSUPPORTED"
 
 

@@ -157,8 +157,7 @@ def _run_index_and_queries(ssh, X, Q, p: Params, seed: int):
     # the benchmark's step, launch for launch
     db.sketch(r)
     db.shingle()
-    db.cws(tables)
-    db.band_keys()
+    db.cws_band_keys(tables)
     ix.build()
     qh.run(r, tables)
     qb.probe()

@@ -298,6 +298,84 @@ def test_cws_key_rows_at_their_limits(ssh):
         _cws_case(ssh, n, H, sets, seed=30 + n)
 
 
+@pytest.mark.parametrize("n,K,L", [(12, 4, 5), (8, 1, 130), (10, 8, 25), (6, 20, 15),
+                                   (6, 50, 13)])
+def test_cws_band_keys_fused_exact(ssh, n, K, L):
+    """CWS with the band keys folded in, against the oracle's CWS then band keys:
+    H = 20 (one chunk of hash values), L = 130 (more tables than lanes), H = 200
+    and 300 (two and three chunks of 128), and H = 650 (beyond the kernel's LDS
+    copy: two kernels), with empty sets among ragged ones."""
+    _announce(f"cws + band keys fused n={n} K={K} L={L}")
+    H = K * L
+    seed = 0xDEADBEEFCAFEBABE
+    rng = np.random.default_rng(40 + n)
+    sets = []
+    for i in range(150):
+        if i % 37 == 0:
+            sets.append((np.zeros(0, np.uint32), np.zeros(0, np.uint32)))
+            continue
+        D = int(rng.integers(1, min(300, 1 << n) + 1))
+        c = np.sort(rng.choice(1 << n, size=D, replace=False)).astype(np.uint32)
+        k = (rng.integers(1, 4, size=D) if i % 2 else rng.integers(1, 400, size=D)).astype(np.uint32)
+        sets.append((c, k))
+    r, lnc, beta = datagen.cws_draws(n, H, seed=n)
+    tabs = ssh.CwsTables(r, lnc, beta, n)
+    codes = np.concatenate([c for c, _ in sets]).astype(np.uint32)
+    counts = np.concatenate([k for _, k in sets]).astype(np.uint32)
+    ho = np.zeros(len(sets) + 1, np.int64)
+    np.cumsum([len(c) for c, _ in sets], out=ho[1:])
+    nd = np.array([len(c) for c, _ in sets], np.int32)
+    hv, keys = ssh.cws_band_keys(to_dev(codes), to_dev(counts), to_dev(ho), to_dev(nd), tabs, K,
+                                 L, seed)
+    torch.cuda.synchronize()
+    ssh.check_device_errors()
+    lnS = oracle.ln_table(int(counts.max()))
+    ohv = np.stack([oracle.cws(c, k, r, lnc, beta, lnS)[2] for c, k in sets])
+    assert np.array_equal(to_np(hv), ohv)
+    assert np.array_equal(to_np(keys), oracle.band_keys(ohv, K, L, seed))
+
+
+@pytest.mark.parametrize("K,L", [(4, 5), (10, 10), (3, 30)])
+def test_cws_band_keys_fused_many_series_per_wave(ssh, K, L):
+    """600,000 short sets, so that every wave hashes two or three series and
+    folds the bands of several at once: the fused pass against the separate CWS
+    and band-key kernels on every series, and against the oracle on a sample."""
+    _announce(f"cws + band keys fused, 600k series, K={K} L={L}")
+    n, N, H, seed = 10, 600_000, K * L, 12345
+    rng = np.random.default_rng(K * 100 + L)
+    D = rng.integers(0, 31, size=N)
+    D[rng.random(N) < 0.02] = 0
+    ho = np.zeros(N + 1, np.int64)
+    np.cumsum(D, out=ho[1:])
+    total = int(ho[-1])
+    sid = np.repeat(np.arange(N), D)
+    pos = np.arange(total) - ho[sid]
+    a = rng.integers(0, 1 << n, size=N)
+    b = rng.integers(0, 1 << (n - 1), size=N) * 2 + 1  # odd step: distinct codes per set
+    codes = ((a[sid] + pos * b[sid]) & ((1 << n) - 1)).astype(np.uint32)
+    codes = codes[np.lexsort((codes, sid))]  # ascending within each set, as shingling gives
+    counts = np.where(rng.random(total) < 0.9, rng.integers(1, 7, size=total),
+                      rng.integers(7, 500, size=total)).astype(np.uint32)
+    r, lnc, beta = datagen.cws_draws(n, H, seed=K + L)
+    tabs = ssh.CwsTables(r, lnc, beta, n)
+    dc, dk, dho = to_dev(codes), to_dev(counts), to_dev(ho)
+    dnd = to_dev(D.astype(np.int32))
+    hv, keys = ssh.cws_band_keys(dc, dk, dho, dnd, tabs, K, L, seed)
+    hv2 = ssh.cws(dc, dk, dho, dnd, tabs)
+    keys2 = ssh.band_keys(hv2, K, L, seed)
+    torch.cuda.synchronize()
+    ssh.check_device_errors()
+    hv, keys = to_np(hv), to_np(keys)
+    assert np.array_equal(hv, to_np(hv2))
+    assert np.array_equal(keys, to_np(keys2))
+    lnS = oracle.ln_table(int(counts.max()))
+    sample = np.concatenate([np.nonzero(D == 0)[0][:20], rng.choice(N, 980, replace=False)])
+    ohv = np.stack([oracle.cws(codes[ho[s]:ho[s + 1]], counts[ho[s]:ho[s + 1]], r, lnc, beta,
+                               lnS)[2] for s in sample])
+    assert np.array_equal(hv[sample], ohv)
+    assert np.array_equal(keys[sample], oracle.band_keys(ohv, K, L, seed))
+
+
 # --------------------------------------------------------------------------
 # full pipeline pieces on C1-shaped data
 # --------------------------------------------------------------------------
@@ -315,15 +393,18 @@ def c1(ssh):
     return X, r, Q, draws
 
 
-def _gpu_hash(ssh, X, r, draws, P):
+def _gpu_hash(ssh, X, r, draws, P, fused=False):
     x, off = datagen.csr(X)
     p = ssh.plan(off, P["W"], P["delta"], P["n"])
     offd = to_dev(off)
     bits, nb, _ = ssh.sketch(to_dev(x), offd, r, P["W"], P["delta"], to_dev(p.bit_word_off))
     codes, counts, nd = ssh.shingle(bits, to_dev(p.bit_word_off), nb, P["n"], to_dev(p.hist_off))
     tabs = ssh.CwsTables(*draws, P["n"])
-    hv = ssh.cws(codes, counts, to_dev(p.hist_off), nd, tabs)
-    keys = ssh.band_keys(hv, P["K"], P["L"], seed=7)
+    if fused:
+        hv, keys = ssh.cws_band_keys(codes, counts, to_dev(p.hist_off), nd, tabs, P["K"], P["L"], 7)
+    else:
+        hv = ssh.cws(codes, counts, to_dev(p.hist_off), nd, tabs)
+        keys = ssh.band_keys(hv, P["K"], P["L"], seed=7)
     torch.cuda.synchronize()
     return hv, keys
 
@@ -346,6 +427,9 @@ def test_c1_hash_values_and_keys_exact(ssh, c1):
     # deterministic: the same launch twice gives the same bits
     hv2, keys2 = _gpu_hash(ssh, X, r, draws, C1)
     assert torch.equal(hv.cpu(), hv2.cpu()) and torch.equal(keys.cpu(), keys2.cpu())
+    # the fused CWS + band-key pass writes the same values
+    hv3, keys3 = _gpu_hash(ssh, X, r, draws, C1, fused=True)
+    assert torch.equal(hv.cpu(), hv3.cpu()) and torch.equal(keys.cpu(), keys3.cpu())
 
 
 @pytest.mark.parametrize("N,L,distinct", [(2000, 5, None), (10007, 3, 50), (4096, 2, 1),
