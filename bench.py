@@ -45,8 +45,8 @@ MEASURED_TRAFFIC = {
     #          fetch scale, write scale); the 1 GiB copy read 524306.9 KiB on
     #          FETCH_SIZE and 1048576 KiB on WRITE_SIZE
     "cws_kernel": ("paper_1610_07328_amd/csrc/cws.hip",
-                   "e9049779b67760bf1a545bc96c30f9365858ecab1873cd3fa6b026f80a22103e",
-                   3576059.5, 798727.53125, 1048576.0 / 524306.9375, 1.0),
+                   "93ded3941c67d2e7eb0f095d6b8acc03550018db0801e84fa9437130d442dc7f",
+                   3570903.125, 903889.4375, 1048576.0 / 524306.9375, 1.0),
 }
 
 
