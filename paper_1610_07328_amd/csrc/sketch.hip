@@ -297,8 +297,9 @@ __global__ __launch_bounds__(256) void sketch_mfma_kernel(
   static_assert(NS % 4 == 0 && RS % 4 == 0, "8-byte operand reads");
   static_assert(ROWS % 4 == 0, "whole stream words per item");
 
-  __shared__ uint2 xh[kWavesPerBlock][PF4 * kWave];  // fp16 quads of the samples
-  __shared__ uint2 xq[kWavesPerBlock][PF4 * kWave];  // bf16 quads of their squares
+  // quad u of the item sits at slot u + u / 4 (one pad slot per four)
+  __shared__ uint2 xh[kWavesPerBlock][PF4 * kWave * 5 / 4];  // fp16 quads of the samples
+  __shared__ uint2 xq[kWavesPerBlock][PF4 * kWave * 5 / 4];  // bf16 quads of their squares
   __shared__ uint32_t qser[kWavesPerBlock][QCAP];
   __shared__ uint32_t qwin[kWavesPerBlock][QCAP];
   __shared__ uint16_t bw[kWavesPerBlock][ROWS];
@@ -343,7 +344,7 @@ __global__ __launch_bounds__(256) void sketch_mfma_kernel(
     bool bad = false;
 #pragma unroll
     for (int i = 0; i < PF4; ++i) {
-      const int p = lane + kWave * i;
+      const int p = lane + (lane >> 2) + kWave * 5 / 4 * i;  // slot of quad lane + 64 i
       xh[w][p] = make_uint2(pack_f16(pv[i][0], pv[i][1]), pack_f16(pv[i][2], pv[i][3]));
       xq[w][p] = make_uint2(pack_bf16(pv[i][0] * pv[i][0], pv[i][1] * pv[i][1]),
                             pack_bf16(pv[i][2] * pv[i][2], pv[i][3] * pv[i][3]));
@@ -369,11 +370,12 @@ __global__ __launch_bounds__(256) void sketch_mfma_kernel(
       const int row = 16 * tile + col;
       const int rowc = row < ROWS ? row : ROWS - 1;
       float4v S = {0.0f, 0.0f, 0.0f, 0.0f}, E = {0.0f, 0.0f, 0.0f, 0.0f};
-      const int b0 = (RS * rowc + 4 * grp) / 4;  // in 8-byte units
+      const int b0 = (RS * rowc + 4 * grp) / 4;  // quad of the first sample
+      const int b0s = b0 + (b0 >> 2);             // its slot; quad b0 + 4 t at b0s + 5 t
 #pragma unroll
       for (int t = 0; t < KS; ++t) {
-        const uint2 hv = xh2[b0 + 4 * t];
-        const uint2 qv = xq2[b0 + 4 * t];
+        const uint2 hv = xh2[b0s + 5 * t];
+        const uint2 qv = xq2[b0s + 5 * t];
         S = __builtin_amdgcn_mfma_f32_16x16x16f16(fr[t], __builtin_bit_cast(half4, hv), S, 0, 0, 0);
         E = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(fo[t], __builtin_bit_cast(bf16x4, qv), E, 0, 0, 0);
       }
