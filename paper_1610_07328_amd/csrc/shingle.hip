@@ -21,6 +21,8 @@
 // holds the lane's rank bases, so the wave's LDS stays small (6 KB at n = 15)
 // and more waves fit a CU.
 // A token is the n bits in stream order read most significant first.
+#include <type_traits>
+
 #include "common.hpp"
 
 namespace ssh {
@@ -50,13 +52,13 @@ __host__ __device__ inline size_t shingle_lds_bytes(int n) {
   return bm + pre + (size_t)kCountCap * 4;
 }
 
-// 32 stream bits starting at bit b0 (bit j of the result is stream bit b0 + j;
-// words at or past nw32 read as zero)
-__device__ __forceinline__ uint32_t stream_window(const uint32_t* __restrict__ w32, int nw32,
-                                                  int b0) {
+// 32 stream bits starting at bit b0 (bit j of the result is stream bit b0 + j),
+// through a buffer resource over the series' stream words: words past its
+// range read as zero
+__device__ __forceinline__ uint32_t stream_window(__amdgpu_buffer_rsrc_t ws, int b0) {
   const int i = b0 >> 5;
-  const uint32_t lo = i < nw32 ? w32[i] : 0u;
-  const uint32_t hi = i + 1 < nw32 ? w32[i + 1] : 0u;
+  const uint32_t lo = __builtin_amdgcn_raw_buffer_load_b32(ws, 4 * i, 0, 0);
+  const uint32_t hi = __builtin_amdgcn_raw_buffer_load_b32(ws, 4 * i + 4, 0, 0);
   return __builtin_amdgcn_alignbit(hi, lo, (uint32_t)(b0 & 31));
 }
 
@@ -101,12 +103,16 @@ __global__ __launch_bounds__(kShWaves * kWave) void shingle_kernel(
   // slot of word wd, and the rank of its first token
   auto bslot = [&](uint32_t wd) { return (int)((wd >> LW) * BS + (wd & (WPL - 1))); };
   auto word_rank = [&](uint32_t wd) -> uint32_t {
-    const int sl = bslot(wd);
     const int j = (int)(wd & (WPL - 1));
     if constexpr (PAD) {
-      const uint16_t* lp = reinterpret_cast<const uint16_t*>(bm + (wd >> LW) * BS + WPL);
-      uint32_t r = lp[j / GS];
-      for (int i = j - j % GS; i < j; ++i) r += __builtin_popcount(bm[sl - j + i]);
+      const uint32_t* run = bm + (wd >> LW) * BS;
+      uint32_t r = reinterpret_cast<const uint16_t*>(run + WPL)[j / GS];
+      if constexpr (GS > 1) {
+        const int j0 = j - j % GS;
+#pragma unroll
+        for (int i = 0; i < GS - 1; ++i)
+          if (j0 + i < j) r += __builtin_popcount(run[j0 + i]);
+      }
       return r;
     } else {
       return pre[(wd >> LW) * WPL + j];
@@ -130,17 +136,21 @@ __global__ __launch_bounds__(kShWaves * kWave) void shingle_kernel(
       }
       continue;
     }
-    const uint32_t* w32 = reinterpret_cast<const uint32_t*>(bits + wo);
-    const int nw32 = 2 * nw;
+    const __amdgpu_buffer_rsrc_t ws = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)(bits + wo), 0, 8 * nw, 0x00020000);
+    uint32_t* const codes_s = codes + ho;
+    uint32_t* const counts_s = counts + ho;
     int P = (S + kWave - 1) / kWave;
     if (P > 33 - n) P = 33 - n;
     const int per_round = kWave * P;
 
-    // 1. mark the tokens
+    // 1. mark the tokens (the first round's stream window is kept for step 3)
+    uint32_t rev0 = 0;
     for (int base = 0; base < S; base += per_round) {
       const int b0 = base + lane * P;
       if (b0 < S) {
-        const uint32_t rev = __builtin_bitreverse32(stream_window(w32, nw32, b0));
+        const uint32_t rev = __builtin_bitreverse32(stream_window(ws, b0));
+        if (base == 0) rev0 = rev;
         const int kend = S - b0 < P ? S - b0 : P;
         uint32_t prev = 0xFFFFFFFFu;
         for (int k = 0; k < kend; ++k) {
@@ -196,46 +206,55 @@ __global__ __launch_bounds__(kShWaves * kWave) void shingle_kernel(
     const uint32_t D = __builtin_amdgcn_readlane(incl, kWave - 1);
     const bool in_lds = D <= (uint32_t)kCountCap;
     if (!in_lds) {
-      for (uint32_t i = lane; i < D; i += kWave) counts[ho + i] = 0;
+      for (uint32_t i = lane; i < D; i += kWave) counts_s[i] = 0;
       // this wave's zero stores complete before its atomics below
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     }
     wave_sync_lds();
 
-    // 3. counts by rank (runs of equal tokens in a lane counted at once), codes at their ranks
-    auto flush = [&](uint32_t t, uint32_t run) {
-      const uint32_t wd = t >> 5;
-      const uint32_t rank = word_rank(wd) + __builtin_popcount(bm[bslot(wd)] & ((1u << (t & 31)) - 1u));
-      if (in_lds) atomicAdd(cnt + rank, run);
-      else atomicAdd(counts + ho + rank, run);
-      codes[ho + rank] = t;
-    };
-    for (int base = 0; base < S; base += per_round) {
-      const int b0 = base + lane * P;
-      if (b0 < S) {
-        const uint32_t rev = __builtin_bitreverse32(stream_window(w32, nw32, b0));
-        const int kend = S - b0 < P ? S - b0 : P;
-        uint32_t prev = (rev >> (32 - n)) & mask;
-        uint32_t run = 1;
-        for (int k = 1; k < kend; ++k) {
-          const uint32_t t = (rev >> (32 - n - k)) & mask;
-          if (t == prev) {
-            ++run;
-            continue;
+    // 3. counts by rank (runs of equal tokens in a lane counted at once), codes
+    // at their ranks; counts in LDS or (more than kCountCap tokens) in memory,
+    // two copies of the loop so that each uses its own kind of atomic
+    auto step3 = [&](auto lds_counts) {
+      constexpr bool LDS_COUNTS = decltype(lds_counts)::value;
+      auto flush = [&](uint32_t t, uint32_t run) {
+        const uint32_t wd = t >> 5;
+        const uint32_t rank =
+            word_rank(wd) + __builtin_popcount(bm[bslot(wd)] & ((1u << (t & 31)) - 1u));
+        if constexpr (LDS_COUNTS) atomicAdd(cnt + rank, run);
+        else atomicAdd(counts_s + rank, run);
+        codes_s[rank] = t;
+      };
+      for (int base = 0; base < S; base += per_round) {
+        const int b0 = base + lane * P;
+        if (b0 < S) {
+          const uint32_t rev =
+              base == 0 ? rev0 : __builtin_bitreverse32(stream_window(ws, b0));
+          const int kend = S - b0 < P ? S - b0 : P;
+          uint32_t prev = (rev >> (32 - n)) & mask;
+          uint32_t run = 1;
+          for (int k = 1; k < kend; ++k) {
+            const uint32_t t = (rev >> (32 - n - k)) & mask;
+            if (t == prev) {
+              ++run;
+              continue;
+            }
+            flush(prev, run);
+            prev = t;
+            run = 1;
           }
           flush(prev, run);
-          prev = t;
-          run = 1;
         }
-        flush(prev, run);
       }
-    }
+    };
+    if (in_lds) step3(std::true_type{});
+    else step3(std::false_type{});
     wave_sync_lds();
 
     // 4. counts out; clear the bitmap words and counts that were used
     if (in_lds) {
       for (uint32_t i = lane; i < D; i += kWave) {
-        counts[ho + i] = cnt[i];
+        counts_s[i] = cnt[i];
         cnt[i] = 0;
       }
     }
