@@ -48,6 +48,18 @@ __device__ __forceinline__ int lane_id() {
 
 __device__ __forceinline__ uint64_t ballot64(bool p) { return __ballot(p); }
 
+// Linear workgroup index renumbered so that each XCD owns a contiguous range.
+// Workgroups are dispatched to the 8 XCDs in turn by linear id g (XCD g mod
+// 8); this returns the bijection of [0, G) that gives XCD x the indexes
+// x per + min(x, rem) .. + per (+1 for x < rem), per = G / 8, rem = G mod 8.
+// Work that consecutive indexes write side by side then meets in one L2.
+__device__ __forceinline__ int64_t xcd_linear_block() {
+  const int64_t G = (int64_t)gridDim.x * gridDim.y;
+  const int64_t g = blockIdx.x + (int64_t)gridDim.x * blockIdx.y;
+  const int64_t xcd = g & 7, per = G >> 3, rem = G & 7;
+  return xcd * per + (xcd < rem ? xcd : rem) + (g >> 3);
+}
+
 // all lanes of the wave see each other's LDS writes issued before this point
 __device__ __forceinline__ void wave_sync_lds() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");

@@ -106,10 +106,20 @@ __device__ __forceinline__ void rs_load(const RsIn in, int64_t e, int64_t N, int
   }
 }
 
+// (table l, tile b) of this workgroup in a (nblk, L) grid, taken in
+// XCD-contiguous order (xcd_linear_block), so that what consecutive tiles
+// write next to each other (count columns, digit runs) goes through one L2.
+__device__ __forceinline__ void xcd_tile(int nblk, int& l, int& b) {
+  const int64_t v = xcd_linear_block();
+  l = (int)(v / nblk);
+  b = (int)(v - (int64_t)l * nblk);
+}
+
 __global__ __launch_bounds__(kRsThreads) void rs_hist_kernel(RsIn in, int64_t N, int L, int shift,
                                                              int nblk, uint32_t* __restrict__ hist) {
   __shared__ uint32_t h[256];
-  const int l = blockIdx.y, b = blockIdx.x;
+  int l, b;
+  xcd_tile(nblk, l, b);
   h[threadIdx.x] = 0;
   __syncthreads();
   const int64_t base = (int64_t)b * kRsTile;
@@ -209,7 +219,8 @@ __global__ __launch_bounds__(kRsThreads) void rs_scatter_kernel(RsIn in, int64_t
   __shared__ uint32_t gbase[256];
   __shared__ uint64_t skeys[kRsTile];
   __shared__ uint32_t sids[kRsTile];
-  const int l = blockIdx.y, b = blockIdx.x;
+  int l, b;
+  xcd_tile(nblk, l, b);
   const int w = threadIdx.x / kWave;
   const int lane = lane_id();
   for (int i = threadIdx.x; i < kRsWaves * 256; i += kRsThreads) (&wcnt[0][0])[i] = 0;
