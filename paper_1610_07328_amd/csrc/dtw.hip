@@ -91,13 +91,11 @@ __device__ __forceinline__ void step_masked(DtwLane& d, float (&V)[G], float (&x
 }
 
 // Steady-state step: every lane's row is inside [0, lq).  Logical slot g is
-// physical register (g + ROT) % G of the x ring.  With IN, the x index this
-// step loads is inside [0, lx) on every lane and is read unchecked.
-template <int G, int ROT, bool IN>
-__device__ __forceinline__ void step_full(DtwLane& d, float (&V)[G], float (&xr)[G], int T,
-                                          const float (&cb)[G]) {
-  const int i = T - d.L;
-  const float qv = d.qs[i];
+// physical register (g + ROT) % G of the x ring.  The row's q value and the x
+// value entering the ring were loaded one block of G steps earlier.
+template <int G, int ROT>
+__device__ __forceinline__ void step_full(DtwLane& d, float (&V)[G], float (&xr)[G], float qv,
+                                          float xin, const float (&cb)[G]) {
   float nv[G];
   const float leftN = dpp_from_left(V[G - 1]);
   float t = qv - xr[(0 + ROT) % G];
@@ -112,16 +110,33 @@ __device__ __forceinline__ void step_full(DtwLane& d, float (&V)[G], float (&xr)
   nv[G - 1] = __builtin_fmaf(t, t, fminf(fminf(nv[G - 2], upN), V[G - 1])) + cb[G - 1];
 #pragma unroll
   for (int g = 0; g < G; ++g) V[g] = nv[g];
-  xr[ROT % G] = IN ? d.xs[d.jn] : x_at(d, d.jn);
+  xr[ROT % G] = xin;
   d.jn += 1;
 }
 
-template <int G, int ROT, bool IN>
-__device__ __forceinline__ void steps_full(DtwLane& d, float (&V)[G], float (&xr)[G], int T0,
+template <int G, int ROT>
+__device__ __forceinline__ void steps_full(DtwLane& d, float (&V)[G], float (&xr)[G],
+                                           const float (&qb)[G], const float (&xb)[G],
                                            const float (&cb)[G]) {
   if constexpr (ROT < G) {
-    step_full<G, ROT, IN>(d, V, xr, T0 + ROT, cb);
-    steps_full<G, ROT + 1, IN>(d, V, xr, T0, cb);
+    step_full<G, ROT>(d, V, xr, qb[ROT], xb[ROT], cb);
+    steps_full<G, ROT + 1>(d, V, xr, qb, xb, cb);
+  }
+}
+
+// The q values and incoming x values of the G steps from T0 (whose first x
+// index is jn): x unchecked when IN (inside [0, lx) on every lane).
+template <int G>
+__device__ __forceinline__ void load_block(const DtwLane& d, int T0, int jn, bool in,
+                                           float (&qb)[G], float (&xb)[G]) {
+#pragma unroll
+  for (int s = 0; s < G; ++s) qb[s] = d.qs[T0 + s - d.L];
+  if (in) {
+#pragma unroll
+    for (int s = 0; s < G; ++s) xb[s] = d.xs[jn + s];
+  } else {
+#pragma unroll
+    for (int s = 0; s < G; ++s) xb[s] = x_at(d, jn + s);
   }
 }
 
@@ -197,10 +212,20 @@ __global__ __launch_bounds__(256) void dtw_kernel(const float* __restrict__ q,
     const int lmin = lx < lq ? lx : lq;
     const int in_lo = r - G;
     const int in_hi = lmin + (kSegLanes - 1) - (kSegLanes + 1) * G + r;  // last T0 allowed
-    int T0 = kPrologue;
-    for (; T0 < T_end && T0 < in_lo; T0 += G) steps_full<G, 0, false>(d, V, xr, T0, cb);
-    for (; T0 < T_end && T0 <= in_hi; T0 += G) steps_full<G, 0, true>(d, V, xr, T0, cb);
-    for (; T0 < T_end; T0 += G) steps_full<G, 0, false>(d, V, xr, T0, cb);
+    // each block's loads are issued one block ahead, while the previous block
+    // computes
+    // two buffers in turn, so that no values are copied between blocks
+    float qa[G], xa[G], qc[G], xc[G];
+    auto in_at = [&](int T0) { return T0 >= in_lo && T0 <= in_hi; };
+    if (kPrologue < T_end) load_block<G>(d, kPrologue, d.jn, in_at(kPrologue), qa, xa);
+    for (int T0 = kPrologue; T0 < T_end; T0 += 2 * G) {
+      const int T1 = T0 + G, T2 = T0 + 2 * G;
+      if (T1 < T_end) load_block<G>(d, T1, d.jn + G, in_at(T1), qc, xc);
+      steps_full<G, 0>(d, V, xr, qa, xa, cb);
+      if (T1 >= T_end) break;
+      if (T2 < T_end) load_block<G>(d, T2, d.jn + G, in_at(T2), qa, xa);
+      steps_full<G, 0>(d, V, xr, qc, xc, cb);
+    }
     T = T_end;
   }
   for (; T < Ttot; ++T) step_masked<G>(d, V, xr, T, cb);
