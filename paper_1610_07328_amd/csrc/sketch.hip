@@ -45,6 +45,8 @@ struct FilterArgs {
   float c2;                          // underflow margin factor
   float rnorm;                       // ||r||_2, rounded up
   float sqrtW;                       // sqrt(W), rounded up
+  float a2;                          // (c1 rnorm + c2 sqrtW)^2 (1 + 2^-18), rounded up
+  float b0;                          // c2 sqrtW rnorm (1 + 2^-20), rounded up
   int32_t W;
   int32_t delta;
 };
@@ -247,17 +249,23 @@ __device__ __forceinline__ uint32_t pack_f16(float a, float b) {
   return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, f16x2v));
 }
 
-// Upper bound of the float64-vs-fast-path error for a window whose bf16
-// sum of squares (fp32-accumulated) is E.  bf16 rounding of a square is below
+// Whether the fast sum S of a window whose bf16 sum of squares (fp32-
+// accumulated) is E has a trusted sign.  bf16 rounding of a square is below
 // 2^-7 relative whatever the rounding direction, and the fp32 accumulation far
-// below that, so ||w||^2 <= E (1 + 2^-6); the W 2^-28 term covers squares
-// that underflow.
+// below that, so ||w||^2 <= Q = E (1 + 2^-6) + W 2^-28 (the last term covers
+// squares that underflow).  The error bound is alpha ||w|| + beta with
+// alpha = c1 ||r|| + c2 sqrt(W) and beta = c2 sqrt(W) ||r||, so the sign is
+// trusted when |S| - beta > 0 and (|S| - beta)^2 > alpha^2 Q.  In float32:
+// y = |S| - b0 (b0 >= beta) and the test y > 0, y^2 > a2 Q.  Each of the
+// five roundings (y, y^2, the fused Q, a2 Q, and a2 itself) is within 2^-24
+// relative, and a2 carries a factor 1 + 2^-18 over alpha^2 that exceeds them
+// all, so a pass implies |S| > alpha ||w|| + beta exactly.  No overflow:
+// |S| < 2^35 and Q < 2^36 for the samples the fast path accepts (|x| < 2^14).
 template <int W>
-__device__ __forceinline__ float mfma_margin(const FilterArgs& fa, float E) {
-  const float slack = 1.0f + 0x1p-20f;
-  const float wn = __builtin_sqrtf(E * (1.0f + 0x1p-6f) + (float)W * 0x1p-28f) * slack;
-  const float m = fa.c1 * fa.rnorm * wn + fa.c2 * fa.sqrtW * (fa.rnorm + wn);
-  return m * slack;
+__device__ __forceinline__ bool mfma_sign_trusted(const FilterArgs& fa, float S, float E) {
+  const float Q = __builtin_fmaf(E, 1.0f + 0x1p-6f, (float)W * 0x1p-28f);
+  const float y = __builtin_fabsf(S) - fa.b0;
+  return y > 0.0f && y * y > fa.a2 * Q;
 }
 
 // Samples 4p .. 4p + 3 (p = lane + 64 i) of an item starting at sample sb, one
@@ -385,8 +393,7 @@ __global__ __launch_bounds__(256) void sketch_mfma_kernel(
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         if (i < nvalid) {
-          const float M = mfma_margin<W>(fa, E[i]);
-          if (unsafe || !(__builtin_fabsf(S[i]) >= M)) flags |= 1u << i;
+          if (unsafe || !mfma_sign_trusted<W>(fa, S[i], E[i])) flags |= 1u << i;
           else if (S[i] >= 0.0f) nib |= 1u << i;
         }
       }
@@ -514,6 +521,9 @@ static ssh_status make_filter_args(const float* r, int W, int delta, FilterArgs&
   fa.c2 = round_up_f32(0x1p-14 * (1 + u) * 1.01);
   fa.rnorm = round_up_f32(__builtin_sqrt(n2) * (1 + 0x1p-40));
   fa.sqrtW = round_up_f32(__builtin_sqrt((double)W));
+  const double alpha = (double)fa.c1 * fa.rnorm + (double)fa.c2 * fa.sqrtW;
+  fa.a2 = round_up_f32(alpha * alpha * (1 + 0x1p-18));
+  fa.b0 = round_up_f32((double)fa.c2 * fa.sqrtW * fa.rnorm * (1 + 0x1p-20));
   fa.W = W;
   fa.delta = delta;
   return SSH_OK;
