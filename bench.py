@@ -303,6 +303,27 @@ def main():
                 "pairs": nq * p.C, "cells": full_cells,
                 "alu_frac": full_cells * 3 / t_full / VALU_LANE_OPS}
 
+    # the same batch through the LB_Keogh-pruned re-rank (same results, less work)
+    ws_lb = torch.empty(max(ssh.rerank_lb_workspace_bytes(nq, p.C, m), 1), dtype=torch.uint8,
+                        device=dev)
+    out_lb = (torch.empty_like(out_full[0]), torch.empty_like(out_full[1]))
+
+    def full_rerank_lb():
+        ssh.dtw_rerank(qb.x, qb.x_off, db.x, db.x_off, cand_full, ncand_full, p.band_frac, m, m,
+                       p.k, ws=ws_lb, out=out_lb, prune=True)
+
+    full_rerank_lb()
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        full_rerank_lb()
+    e1.record()
+    e1.synchronize()
+    t_lb = e0.elapsed_time(e1) / reps / 1e3
+    same = bool(torch.equal(out_lb[0], out_full[0]) and
+                torch.equal(out_lb[1].view(torch.int32), out_full[1].view(torch.int32)))
+    dtw_full["lb_pruned"] = {"ms": t_lb * 1e3, "speedup": t_full / t_lb, "same_results": same}
+
     # single-query latency with the index resident
     lat = []
     if args.latency_samples > 0:

@@ -15,6 +15,7 @@
  *   ssh_probe      retrieved set R of each query, ranked         (Algorithm 2)
  *   dtw_rerank     top-k of R by banded DTW distance             (Section 2.1,
  *                  last step of Algorithm 2)
+ *   dtw_rerank_lb  the same, LB_Keogh bounds skipping far candidates
  *
  * Conventions shared by every entry point:
  *   - Pointers are DEVICE pointers unless marked [host].  The caller owns every
@@ -252,6 +253,26 @@ ssh_status dtw_rerank(const float* q, const int64_t* q_off, int32_t nq, const fl
                       const int64_t* db_off, int64_t N, const int64_t* cand, const int32_t* ncand,
                       int32_t C, float band_frac, int64_t q_len, int64_t db_len, int32_t k,
                       int64_t* out_id, float* out_dist, void* ws, size_t ws_bytes, void* stream);
+
+/* [host] Workspace bytes needed by dtw_rerank_lb (db_len: the candidate length). */
+size_t ssh_rerank_lb_workspace_bytes(int32_t nq, int32_t C, int64_t db_len);
+
+/* dtw_rerank with lower-bound pruning (Section 2.1: DTW is costly, so cheap
+ * lower bounds discard candidates first).  Same arguments and the same
+ * outputs, bit for bit, as dtw_rerank; only the work differs.  Each candidate
+ * gets its LB_Keogh bound (squared distance of x_j to the envelope of the
+ * query values it may be aligned with); each query's k candidates of smallest
+ * bound are computed first, and a candidate whose bound exceeds the largest of
+ * their squared distances, times a factor covering every float32 rounding
+ * (about 1 + (q_len + 2 db_len) 2^-23), is not computed: its distance is above
+ * the k-th best.  Pays off when many candidates are far from the query; the
+ * two dependent DTW passes make it slower on small batches.
+ *   ws, ws_bytes at least ssh_rerank_lb_workspace_bytes(nq, C, db_len) */
+ssh_status dtw_rerank_lb(const float* q, const int64_t* q_off, int32_t nq, const float* db,
+                         const int64_t* db_off, int64_t N, const int64_t* cand,
+                         const int32_t* ncand, int32_t C, float band_frac, int64_t q_len,
+                         int64_t db_len, int32_t k, int64_t* out_id, float* out_dist, void* ws,
+                         size_t ws_bytes, void* stream);
 
 /* Same contract as ssh_sketch, always through the kernel that handles any W
  * and delta (ssh_sketch picks a register-blocked kernel for the filter shapes

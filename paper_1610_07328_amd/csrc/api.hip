@@ -45,6 +45,12 @@ ssh_status probe_launch(const uint64_t* tab_keys, const uint32_t* tab_ids, int64
                         hipStream_t stream);
 size_t probe_workspace_bytes(int nq, int L, int C);
 size_t rerank_workspace_bytes(int nq, int C);
+size_t rerank_lb_workspace_bytes(int nq, int C, int64_t lx);
+ssh_status rerank_lb_launch(const float* q, const int64_t* q_off, int nq, const float* db,
+                            const int64_t* db_off, int64_t Ndb, const int64_t* cand,
+                            const int32_t* ncand, int C, float band_frac, int64_t q_len,
+                            int64_t db_len, int k, int64_t* out_id, float* out_dist, void* ws,
+                            size_t ws_bytes, hipStream_t stream);
 ssh_status rerank_launch(const float* q, const int64_t* q_off, int nq, const float* db,
                          const int64_t* db_off, int64_t Ndb, const int64_t* cand,
                          const int32_t* ncand, int C, float band_frac, int64_t q_len,
@@ -261,6 +267,29 @@ ssh_status dtw_rerank(const float* q, const int64_t* q_off, int32_t nq, const fl
   SSH_REQUIRE(N == 0 || (db && db_off), "dtw_rerank: null series pointer");
   return rerank_launch(q, q_off, nq, db, db_off, N, cand, ncand, C, band_frac, q_len, db_len, k,
                        out_id, out_dist, ws, ws_bytes, as_stream(stream));
+}
+
+size_t ssh_rerank_lb_workspace_bytes(int32_t nq, int32_t C, int64_t db_len) {
+  if (nq < 0 || C < 1 || db_len < 1) return 0;
+  return rerank_lb_workspace_bytes(nq, C, db_len);
+}
+
+ssh_status dtw_rerank_lb(const float* q, const int64_t* q_off, int32_t nq, const float* db,
+                         const int64_t* db_off, int64_t N, const int64_t* cand,
+                         const int32_t* ncand, int32_t C, float band_frac, int64_t q_len,
+                         int64_t db_len, int32_t k, int64_t* out_id, float* out_dist, void* ws,
+                         size_t ws_bytes, void* stream) {
+  SSH_REQUIRE(nq >= 0 && N >= 0, "dtw_rerank_lb: nq or N < 0");
+  SSH_REQUIRE(C >= 1 && C <= SSH_MAX_C, "dtw_rerank_lb: C out of [1, SSH_MAX_C]");
+  SSH_REQUIRE(k >= 1 && k <= SSH_MAX_K && k <= C, "dtw_rerank_lb: k out of [1, min(C, SSH_MAX_K)]");
+  SSH_REQUIRE(band_frac >= 0.0f && band_frac <= 1.0f, "dtw_rerank_lb: band_frac out of [0, 1]");
+  SSH_REQUIRE(q_len >= 1 && q_len <= (1 << 30) && db_len >= 1 && db_len <= (1 << 30),
+              "dtw_rerank_lb: lengths out of range");
+  if (nq == 0) return SSH_OK;
+  SSH_REQUIRE(q && q_off && cand && ncand && out_id && out_dist && ws, "dtw_rerank_lb: null pointer");
+  SSH_REQUIRE(N == 0 || (db && db_off), "dtw_rerank_lb: null series pointer");
+  return rerank_lb_launch(q, q_off, nq, db, db_off, N, cand, ncand, C, band_frac, q_len, db_len, k,
+                          out_id, out_dist, ws, ws_bytes, as_stream(stream));
 }
 
 ssh_status ssh_check_device_errors(void) {

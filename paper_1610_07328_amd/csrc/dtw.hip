@@ -147,15 +147,22 @@ __global__ __launch_bounds__(256) void dtw_kernel(const float* __restrict__ q,
                                                   const int64_t* __restrict__ db_off, int64_t Ndb,
                                                   const int64_t* __restrict__ cand,
                                                   const int32_t* __restrict__ ncand, int C, int lq,
-                                                  int lx, int r, float* __restrict__ dist, int* err) {
+                                                  int lx, int r, float* __restrict__ dist, int* err,
+                                                  const int32_t* __restrict__ plist, int64_t nslots) {
   static_assert(G >= 2, "at least two offsets per lane");
   const int lane = lane_id();
   const int L = lane & (kSegLanes - 1);
-  const int64_t pair = ((int64_t)blockIdx.x * 4 + threadIdx.x / kWave) * 4 + (lane >> 4);
+  const int64_t slot = ((int64_t)blockIdx.x * 4 + threadIdx.x / kWave) * 4 + (lane >> 4);
   const int64_t npairs = (int64_t)nq * C;
-  const int64_t qi = pair < npairs ? pair / C : nq - 1;
-  const int ci = pair < npairs ? (int)(pair - qi * C) : 0;
-  bool live = pair < npairs && ci < ncand[qi];
+  // with a slot list, slot i computes pair plist[i] (-1: none) and writes only
+  // that pair's distance; without one, slot i is pair i
+  int64_t pair = slot;
+  if (plist != nullptr) pair = slot < nslots ? plist[slot] : -1;
+  const bool inb = plist != nullptr ? pair >= 0 : pair < npairs;
+  const int64_t qi = inb ? pair / C : nq - 1;
+  const int ci = inb ? (int)(pair - qi * C) : 0;
+  bool live = inb && ci < ncand[qi];
+  const bool writes = plist == nullptr ? inb : live;
   int64_t id = 0;
   if (live) {
     id = cand[pair];
@@ -166,7 +173,7 @@ __global__ __launch_bounds__(256) void dtw_kernel(const float* __restrict__ q,
     }
   }
   if (ballot64(live) == 0) {
-    if (pair < npairs && L == 0) dist[pair] = kInf;
+    if (writes && L == 0) dist[pair] = kInf;
     return;
   }
   // A lane without a pair borrows the query of the first live lane of its
@@ -232,7 +239,7 @@ __global__ __launch_bounds__(256) void dtw_kernel(const float* __restrict__ q,
 
   // D(lq-1, lx-1) sits at offset lx - lq
   const int of = lx - lq;
-  if (pair < npairs) {
+  if (writes) {
     float res = kInf;
     if (of >= -r && of <= r) {
       const int Lf = (of + r) / G, gf = (of + r) % G;
@@ -293,6 +300,196 @@ __global__ __launch_bounds__(256) void topk_kernel(const float* __restrict__ dis
   }
 }
 
+// ---------------------------------------------------------------------------
+// LB_Keogh pruning (the lower-bound step before exact DTW; Section 2.1 and the
+// pruning the paper's re-rank relies on).  For candidate value x_j the query
+// values it can be matched with are q_i, |i - j| <= r, so every warping path
+// pays at least the squared distance from x_j to [min, max] of that window:
+//     LB = sum_j dist(x_j, [Lo_j, U_j])^2 <= D (the DTW total cost).
+// A query's k candidates with the smallest LB are computed first; the largest
+// of their distances, tau, bounds the k-th best, and a candidate is skipped
+// when its LB exceeds tau^2 by more than every rounding involved can account
+// for (the factor passed as prune_f, see rerank_lb_launch), which leaves its
+// distance strictly above the k-th best: the top k are those of dtw_rerank.
+// ---------------------------------------------------------------------------
+
+constexpr int kLbLds = 4096;   // envelope values staged in LDS for the bounds
+
+// Envelope of each query over the candidate index j in [0, lx): the window
+// q[max(0, j - r), min(lq - 1, j + r)].  One workgroup per query and 256
+// consecutive j, with the query values their windows cover (at most 256 +
+// 2 SSH_MAX_BAND) staged in LDS.  An empty window (no alignment for x_j) gets
+// U = -inf, Lo = +inf.  A query whose length is not lq gets the widest
+// envelope (LB = 0: never skipped; the DTW step reports the length).
+constexpr int kEnvJ = 256;
+__global__ __launch_bounds__(kEnvJ) void lb_envelope_kernel(const float* __restrict__ q,
+                                                            const int64_t* __restrict__ q_off,
+                                                            int lq, int lx, int r,
+                                                            float* __restrict__ U,
+                                                            float* __restrict__ Lo) {
+  __shared__ float qsh[kEnvJ + 2 * SSH_MAX_BAND + 1];
+  const int jblocks = (lx + kEnvJ - 1) / kEnvJ;
+  const int qi = blockIdx.x / jblocks;
+  const int j0 = (blockIdx.x - qi * jblocks) * kEnvJ;
+  const bool ok = q_off[qi + 1] - q_off[qi] == lq;
+  const float* qs = q + q_off[qi];
+  const int s0 = j0 - r < 0 ? 0 : j0 - r;
+  const int s1 = j0 + kEnvJ + r < lq ? j0 + kEnvJ + r : lq;  // staged q[s0, s1)
+  if (ok)
+    for (int i = s0 + (int)threadIdx.x; i < s1; i += kEnvJ) qsh[i - s0] = qs[i];
+  __syncthreads();
+  const int j = j0 + (int)threadIdx.x;
+  if (j >= lx) return;
+  float mx = -kInf, mn = kInf;
+  if (ok) {
+    const int a = j - r < 0 ? 0 : j - r;
+    const int b = j + r < lq - 1 ? j + r : lq - 1;
+    for (int i = a; i <= b; ++i) {
+      const float v = qsh[i - s0];
+      mx = fmaxf(mx, v);
+      mn = fminf(mn, v);
+    }
+  } else {
+    mx = kInf;
+    mn = -kInf;
+  }
+  U[(int64_t)qi * lx + j] = mx;
+  Lo[(int64_t)qi * lx + j] = mn;
+}
+
+// LB_Keogh of every live pair (float32 sum): one workgroup per query and four
+// of its candidates, one wavefront each, the query's envelope in LDS when
+// lx <= kLbLds.  An invalid candidate (id or length) gets 0 and is left to the
+// DTW step.
+__global__ __launch_bounds__(256) void lb_keogh_kernel(const float* __restrict__ db,
+                                                       const int64_t* __restrict__ db_off,
+                                                       int64_t Ndb, const int64_t* __restrict__ cand,
+                                                       const int32_t* __restrict__ ncand, int C,
+                                                       int lx, const float* __restrict__ U,
+                                                       const float* __restrict__ Lo,
+                                                       float* __restrict__ lb) {
+  extern __shared__ float env[];  // U then Lo, lx each, when staged
+  const int groups = (C + 3) / 4;
+  const int qi = blockIdx.x / groups;
+  const int c0 = (blockIdx.x - qi * groups) * 4;
+  const int nc = ncand[qi] < C ? ncand[qi] : C;
+  if (c0 >= nc) return;  // no candidate here (uniform over the workgroup)
+  const bool staged = lx <= kLbLds;
+  const float* u = U + (int64_t)qi * lx;
+  const float* lo = Lo + (int64_t)qi * lx;
+  if (staged) {
+    for (int j = threadIdx.x; j < lx; j += blockDim.x) {
+      env[j] = u[j];
+      env[lx + j] = lo[j];
+    }
+    u = env;
+    lo = env + lx;
+  }
+  __syncthreads();
+  const int ci = c0 + threadIdx.x / kWave;
+  if (ci < nc) {
+    const int64_t pair = (int64_t)qi * C + ci;
+    const int64_t id = cand[pair];
+    const bool ok = id >= 0 && id < Ndb && db_off[id + 1] - db_off[id] == lx;
+    float s = 0.0f;
+    if (ok) {
+      const float* xs = db + db_off[id];
+      for (int j = lane_id(); j < lx; j += kWave) {
+        const float x = xs[j];
+        const float t = x > u[j] ? x - u[j] : (x < lo[j] ? lo[j] - x : 0.0f);
+        s = __builtin_fmaf(t, t, s);
+      }
+    }
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, kWave);
+    if (lane_id() == 0) lb[pair] = s;
+  }
+}
+
+// Per query: distances preset to +inf; the k live candidates with the
+// smallest LB (ties by column) marked 1 and listed in the first pass's slots
+// list1[qi k ..) (-1 past the live count), the other live candidates marked 2,
+// the rest 0.
+__global__ __launch_bounds__(256) void lb_select_kernel(const float* __restrict__ lb,
+                                                        const int32_t* __restrict__ ncand, int C,
+                                                        int k, uint8_t* __restrict__ mark,
+                                                        float* __restrict__ dist,
+                                                        int32_t* __restrict__ list1) {
+  __shared__ uint64_t a[SSH_MAX_C];
+  const int qi = blockIdx.x;
+  const int nc = ncand[qi] < C ? ncand[qi] : C;
+  int n2 = 1;
+  while (n2 < (nc > 0 ? nc : 1)) n2 <<= 1;
+  for (int i = threadIdx.x; i < n2; i += blockDim.x)
+    a[i] = i < nc ? ((uint64_t)__builtin_bit_cast(uint32_t, lb[(int64_t)qi * C + i]) << 32) | (uint32_t)i
+                  : ~0ull;
+  for (int i = threadIdx.x; i < C; i += blockDim.x) {
+    mark[(int64_t)qi * C + i] = i < nc ? 2 : 0;
+    dist[(int64_t)qi * C + i] = kInf;
+  }
+  __syncthreads();
+  for (int kk = 2; kk <= n2; kk <<= 1) {
+    for (int j = kk >> 1; j > 0; j >>= 1) {
+      for (int i = threadIdx.x; i < n2; i += blockDim.x) {
+        const int p = i ^ j;
+        if (p > i) {
+          const uint64_t x = a[i], y = a[p];
+          const bool up = (i & kk) == 0;
+          if ((x > y) == up) {
+            a[i] = y;
+            a[p] = x;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  const int first = nc < k ? nc : k;
+  for (int t = threadIdx.x; t < k; t += blockDim.x) {
+    if (t < first) {
+      const int ci = (int)(uint32_t)a[t];
+      mark[(int64_t)qi * C + ci] = 1;
+      list1[(int64_t)qi * k + t] = (int32_t)((int64_t)qi * C + ci);
+    } else {
+      list1[(int64_t)qi * k + t] = -1;
+    }
+  }
+}
+
+// Per query, after the first pass: tau = the largest first-pass distance;
+// the candidates marked 2 whose LB does not exceed tau^2 prune_f fill the
+// second pass's slots list2[qi (C - k) ..), the rest of which get -1 (a
+// dropped candidate keeps its +inf distance).
+__global__ __launch_bounds__(256) void lb_prune_kernel(const float* __restrict__ lb,
+                                                       const float* __restrict__ dist,
+                                                       const int32_t* __restrict__ ncand, int C,
+                                                       int k, float prune_f,
+                                                       const uint8_t* __restrict__ mark,
+                                                       int32_t* __restrict__ list2) {
+  __shared__ float tmax[256 / kWave];
+  __shared__ uint32_t nkeep;
+  const int qi = blockIdx.x;
+  const int nc = ncand[qi] < C ? ncand[qi] : C;
+  if (threadIdx.x == 0) nkeep = 0;
+  float t = -kInf;
+  for (int i = threadIdx.x; i < nc; i += blockDim.x)
+    if (mark[(int64_t)qi * C + i] == 1) t = fmaxf(t, dist[(int64_t)qi * C + i]);
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) t = fmaxf(t, __shfl_xor(t, o, kWave));
+  if (lane_id() == 0) tmax[threadIdx.x / kWave] = t;
+  __syncthreads();
+  float tau = -kInf;
+  for (int w = 0; w < (int)(blockDim.x / kWave); ++w) tau = fmaxf(tau, tmax[w]);
+  const float cut = tau * tau * prune_f;  // +inf when tau is +inf: nothing is dropped
+  int32_t* l2 = list2 + (int64_t)qi * (C - k);
+  for (int i = threadIdx.x; i < nc; i += blockDim.x) {
+    const int64_t p = (int64_t)qi * C + i;
+    if (mark[p] == 2 && !(lb[p] > cut)) l2[atomicAdd(&nkeep, 1u)] = (int32_t)p;
+  }
+  __syncthreads();
+  for (int i = (int)nkeep + threadIdx.x; i < C - k; i += blockDim.x) l2[i] = -1;
+}
+
 __device__ int g_dtw_err;
 
 int take_dtw_err() {
@@ -307,9 +504,33 @@ size_t rerank_workspace_bytes(int nq, int C) { return ((size_t)nq * C * sizeof(f
 template <int G>
 static void launch_g(unsigned grid, hipStream_t s, const float* q, const int64_t* q_off, int nq,
                      const float* db, const int64_t* db_off, int64_t Ndb, const int64_t* cand,
-                     const int32_t* ncand, int C, int lq, int lx, int r, float* dist, int* err) {
+                     const int32_t* ncand, int C, int lq, int lx, int r, float* dist, int* err,
+                     const int32_t* plist, int64_t nslots) {
   dtw_kernel<G><<<grid, 256, 0, s>>>(q, q_off, nq, db, db_off, Ndb, cand, ncand, C, lq, lx, r, dist,
-                                      err);
+                                      err, plist, nslots);
+}
+
+// The DTW kernel of the smallest lane width G that holds the band (16 G >=
+// 2 r + 2), over every pair (plist null) or the nslots pairs plist lists.
+static ssh_status launch_dtw(hipStream_t stream, const float* q, const int64_t* q_off, int nq,
+                             const float* db, const int64_t* db_off, int64_t Ndb,
+                             const int64_t* cand, const int32_t* ncand, int C, int lq, int lx,
+                             int r, float* dist, int* err, const int32_t* plist, int64_t nslots) {
+  const int64_t n = plist != nullptr ? nslots : (int64_t)nq * C;
+  if (n == 0) return SSH_OK;
+  const unsigned grid = (unsigned)ceil_div(n, 16);
+  const int need = 2 * r + 2;  // band offsets plus the +inf guard offset
+#define SSH_G(GG)                                                                                 \
+  if (kSegLanes * GG >= need) {                                                                   \
+    launch_g<GG>(grid, stream, q, q_off, nq, db, db_off, Ndb, cand, ncand, C, lq, lx, r, dist, err, \
+                 plist, nslots);                                                                  \
+  } else
+  SSH_G(2) SSH_G(3) SSH_G(4) SSH_G(5) SSH_G(6) SSH_G(7) SSH_G(8) SSH_G(10) SSH_G(12) SSH_G(14)
+  SSH_G(16) SSH_G(20) SSH_G(24) SSH_G(26) SSH_G(28) SSH_G(32) {
+    return fail(SSH_EUNSUPPORTED, "dtw_rerank: band too wide");
+  }
+#undef SSH_G
+  return check_launch("dtw_rerank");
 }
 
 ssh_status rerank_launch(const float* q, const int64_t* q_off, int nq, const float* db,
@@ -326,23 +547,81 @@ ssh_status rerank_launch(const float* q, const int64_t* q_off, int nq, const flo
   if (hipGetSymbolAddress((void**)&err, HIP_SYMBOL(g_dtw_err)) != hipSuccess)
     return fail(SSH_EDEVICE, "dtw_rerank: cannot resolve error flag");
   float* dist = reinterpret_cast<float*>(ws);
-  const int64_t npairs = (int64_t)nq * C;
-  const unsigned grid = (unsigned)ceil_div(npairs, 16);
-  const int need = 2 * r + 2;  // band offsets plus the +inf guard offset
   const int lq = (int)q_len, lx = (int)db_len;
-#define SSH_G(GG)                                                                                 \
-  if (kSegLanes * GG >= need) {                                                                   \
-    launch_g<GG>(grid, stream, q, q_off, nq, db, db_off, Ndb, cand, ncand, C, lq, lx, r, dist, err); \
-  } else
-  SSH_G(2) SSH_G(3) SSH_G(4) SSH_G(5) SSH_G(6) SSH_G(7) SSH_G(8) SSH_G(10) SSH_G(12) SSH_G(14)
-  SSH_G(16) SSH_G(20) SSH_G(24) SSH_G(26) SSH_G(28) SSH_G(32) {
-    return fail(SSH_EUNSUPPORTED, "dtw_rerank: band too wide");
-  }
-#undef SSH_G
-  ssh_status st = check_launch("dtw_rerank");
+  ssh_status st = launch_dtw(stream, q, q_off, nq, db, db_off, Ndb, cand, ncand, C, lq, lx, r,
+                             dist, err, nullptr, 0);
   if (st != SSH_OK) return st;
   topk_kernel<<<nq, 256, 0, stream>>>(dist, cand, ncand, C, k, out_id, out_dist);
   return check_launch("dtw_rerank");
+}
+
+// Workspace of the pruned re-rank: distances and LB [nq][C] (float32), marks
+// [nq][C] (u8), the two passes' slot lists (nq k, then nq (C - k), int32),
+// the query envelopes U and Lo [nq][lx] (float32).
+static inline size_t al256(size_t v) { return (v + 255) & ~(size_t)255; }
+size_t rerank_lb_workspace_bytes(int nq, int C, int64_t lx) {
+  const size_t pc = (size_t)nq * C;
+  return 3 * al256(pc * 4) + al256(pc) + 2 * al256((size_t)nq * lx * 4);
+}
+
+ssh_status rerank_lb_launch(const float* q, const int64_t* q_off, int nq, const float* db,
+                            const int64_t* db_off, int64_t Ndb, const int64_t* cand,
+                            const int32_t* ncand, int C, float band_frac, int64_t q_len,
+                            int64_t db_len, int k, int64_t* out_id, float* out_dist, void* ws,
+                            size_t ws_bytes, hipStream_t stream) {
+  if (nq == 0) return SSH_OK;
+  if (ws_bytes < rerank_lb_workspace_bytes(nq, C, db_len))
+    return fail(SSH_EINVAL, "dtw_rerank_lb: workspace too small");
+  if ((int64_t)nq * ((C + 3) / 4) > INT32_MAX || (int64_t)nq * ((db_len + 255) / 256) > INT32_MAX)
+    return fail(SSH_EUNSUPPORTED, "dtw_rerank_lb: batch too large for one launch");
+  const int64_t mx = q_len > db_len ? q_len : db_len;
+  const int r = (int)std::floor((double)band_frac * (double)mx);
+  if (r > SSH_MAX_BAND) return fail(SSH_EUNSUPPORTED, "dtw_rerank: band radius above SSH_MAX_BAND");
+  int* err = nullptr;
+  if (hipGetSymbolAddress((void**)&err, HIP_SYMBOL(g_dtw_err)) != hipSuccess)
+    return fail(SSH_EDEVICE, "dtw_rerank: cannot resolve error flag");
+  const int lq = (int)q_len, lx = (int)db_len;
+  const size_t pc = (size_t)nq * C;
+  char* p = static_cast<char*>(ws);
+  float* dist = reinterpret_cast<float*>(p);
+  p += al256(pc * 4);
+  float* lb = reinterpret_cast<float*>(p);
+  p += al256(pc * 4);
+  uint8_t* mark = reinterpret_cast<uint8_t*>(p);
+  p += al256(pc);
+  int32_t* list1 = reinterpret_cast<int32_t*>(p);  // nq k slots
+  int32_t* list2 = list1 + (size_t)nq * k;          // nq (C - k) slots
+  p += al256(pc * 4);
+  float* U = reinterpret_cast<float*>(p);
+  p += al256((size_t)nq * lx * 4);
+  float* Lo = reinterpret_cast<float*>(p);
+  // Skip factor.  The float32 DTW total of a path of P <= lq + lx - 1 cells is
+  // at least (1 - 2^-24)^(P + 2) times the exact one, the float32 LB at most
+  // (1 + 2^-24)^(lx + 4) times the exact LB, and tau^2 recomputed from the
+  // rounded square root is within 9 ulps of the total it came from; twice
+  // their sum, plus 2^-19 so that the rounded distances differ strictly.
+  const double m = (double)(q_len + 2 * db_len + 64) * 0x1p-23 + 0x1p-19;
+  float prune_f = (float)(1.0 + m);
+  if ((double)prune_f < 1.0 + m) prune_f = std::nextafter(prune_f, INFINITY);
+  lb_envelope_kernel<<<(unsigned)((int64_t)nq * ((lx + kEnvJ - 1) / kEnvJ)), kEnvJ, 0, stream>>>(
+      q, q_off, lq, lx, r, U, Lo);
+  const size_t lb_lds = lx <= kLbLds ? (size_t)lx * 8 : 0;
+  lb_keogh_kernel<<<(unsigned)((int64_t)nq * ((C + 3) / 4)), 256, lb_lds, stream>>>(
+      db, db_off, Ndb, cand, ncand, C, lx, U, Lo, lb);
+  lb_select_kernel<<<nq, 256, 0, stream>>>(lb, ncand, C, k, mark, dist, list1);
+  ssh_status st = check_launch("dtw_rerank_lb");
+  if (st != SSH_OK) return st;
+  st = launch_dtw(stream, q, q_off, nq, db, db_off, Ndb, cand, ncand, C, lq, lx, r, dist, err,
+                  list1, (int64_t)nq * k);
+  if (st != SSH_OK) return st;
+  if (C > k) {
+    lb_prune_kernel<<<nq, 256, 0, stream>>>(lb, dist, ncand, C, k, prune_f, mark, list2);
+    st = launch_dtw(stream, q, q_off, nq, db, db_off, Ndb, cand, ncand, C, lq, lx, r, dist, err,
+                    list2, (int64_t)nq * (C - k));
+    if (st != SSH_OK) return st;
+  }
+  topk_kernel<<<nq, 256, 0, stream>>>(dist, cand, ncand, C, k, out_id, out_dist);
+  return check_launch("dtw_rerank_lb");
 }
 
 }  // namespace ssh

@@ -66,6 +66,9 @@ SIGNATURES = {
     "ssh_rerank_workspace_bytes": (_sz, [_i32, _i32]),
     "dtw_rerank": (_i32, [_vp, _vp, _i32, _vp, _vp, _i64, _vp, _vp, _i32, _f32, _i64, _i64,
                           _i32, _vp, _vp, _vp, _sz, _vp]),
+    "ssh_rerank_lb_workspace_bytes": (_sz, [_i32, _i32, _i64]),
+    "dtw_rerank_lb": (_i32, [_vp, _vp, _i32, _vp, _vp, _i64, _vp, _vp, _i32, _f32, _i64, _i64,
+                             _i32, _vp, _vp, _vp, _sz, _vp]),
     "ssh_check_device_errors": (_i32, []),
 }
 
@@ -311,9 +314,14 @@ def rerank_workspace_bytes(nq: int, C: int) -> int:
     return int(lib().ssh_rerank_workspace_bytes(nq, C))
 
 
+def rerank_lb_workspace_bytes(nq: int, C: int, db_len: int) -> int:
+    return int(lib().ssh_rerank_lb_workspace_bytes(nq, C, db_len))
+
+
 def dtw_rerank(q, q_off, db, db_off, cand, ncand, band_frac: float, q_len: int, db_len: int,
-               k: int, ws: torch.Tensor | None = None, out=None):
-    """Returns (ids int64 [nq, k], dist float32 [nq, k])."""
+               k: int, ws: torch.Tensor | None = None, out=None, prune: bool = False):
+    """Returns (ids int64 [nq, k], dist float32 [nq, k]).  With prune, the same
+    results through dtw_rerank_lb (LB_Keogh bounds skip far candidates)."""
     nq, C = cand.shape
     N = db_off.numel() - 1
     dev = q.device
@@ -323,11 +331,13 @@ def dtw_rerank(q, q_off, db, db_off, cand, ncand, band_frac: float, q_len: int, 
     else:
         oid, od = out
     if ws is None:
-        ws = torch.empty(max(rerank_workspace_bytes(nq, C), 1), dtype=torch.uint8, device=dev)
-    _check(lib().dtw_rerank(_dev(q, torch.float32, "q"), _dev(q_off, torch.int64, "q_off"), nq,
-                            _dev(db, torch.float32, "db"), _dev(db_off, torch.int64, "db_off"), N,
-                            _dev(cand, torch.int64, "cand"), _dev(ncand, torch.int32, "ncand"), C,
-                            float(band_frac), q_len, db_len, k, _dev(oid, torch.int64, "out_id"),
-                            _dev(od, torch.float32, "out_dist"), _dev(ws, torch.uint8, "ws"),
-                            ws.numel(), _stream()), "dtw_rerank")
+        nws = rerank_lb_workspace_bytes(nq, C, db_len) if prune else rerank_workspace_bytes(nq, C)
+        ws = torch.empty(max(nws, 1), dtype=torch.uint8, device=dev)
+    fn = lib().dtw_rerank_lb if prune else lib().dtw_rerank
+    _check(fn(_dev(q, torch.float32, "q"), _dev(q_off, torch.int64, "q_off"), nq,
+              _dev(db, torch.float32, "db"), _dev(db_off, torch.int64, "db_off"), N,
+              _dev(cand, torch.int64, "cand"), _dev(ncand, torch.int32, "ncand"), C,
+              float(band_frac), q_len, db_len, k, _dev(oid, torch.int64, "out_id"),
+              _dev(od, torch.float32, "out_dist"), _dev(ws, torch.uint8, "ws"), ws.numel(),
+              _stream()), "dtw_rerank_lb" if prune else "dtw_rerank")
     return oid[:nq], od[:nq]

@@ -515,10 +515,15 @@ def test_probe_large_retrieved_sets_with_ties(ssh, C):
 def _rerank_case(ssh, Q, X, cand, ncand, band, k):
     q, qoff = datagen.csr(Q)
     db, dboff = datagen.csr(X)
-    ids, dist = ssh.dtw_rerank(to_dev(q), to_dev(qoff), to_dev(db), to_dev(dboff), to_dev(cand),
-                               to_dev(ncand), band, Q.shape[1], X.shape[1], k)
+    args = (to_dev(q), to_dev(qoff), to_dev(db), to_dev(dboff), to_dev(cand), to_dev(ncand), band,
+            Q.shape[1], X.shape[1], k)
+    ids, dist = ssh.dtw_rerank(*args)
+    # the LB_Keogh-pruned re-rank returns the same bits
+    ids_p, dist_p = ssh.dtw_rerank(*args, prune=True)
     torch.cuda.synchronize()
     ssh.check_device_errors()
+    assert np.array_equal(to_np(ids_p), to_np(ids))
+    assert np.array_equal(to_np(dist_p).view(np.uint32), to_np(dist).view(np.uint32))
     oids, odist, all_d = oracle.rerank(q, qoff, db, dboff, cand, ncand, band, k)
     compare_rerank(to_np(ids), to_np(dist), oids, odist, all_d, cand, ncand)
 
@@ -551,6 +556,47 @@ def test_rerank_band_shapes(ssh, m, band, lq):
     cand = rng.integers(0, N, size=(nq, C)).astype(np.int64)
     ncand = np.full(nq, C, np.int32)
     _rerank_case(ssh, Q, X, cand, ncand, band, min(10, C))
+
+
+def test_rerank_lb_prunes_far_candidates(ssh):
+    """Perturbed copies of database series among random candidates (the shape of
+    the benchmark's candidate lists), with repeated ids, short and empty lists:
+    the pruned re-rank matches the plain one and the oracle, and it does skip
+    pairs (read back from its workspace marks)."""
+    _announce("rerank with LB_Keogh pruning")
+    m, N, nq, C, k, band = 512, 400, 24, 50, 10, 0.05
+    X = datagen.random_walks(N, m, seed=11)
+    Q, src = datagen.perturbed_queries(X, nq, 0.1, seed=11)
+    rng = np.random.default_rng(11)
+    cand = rng.integers(0, N, size=(nq, C)).astype(np.int64)
+    cand[:, 0] = src
+    cand[:, 7] = cand[:, 3]  # the same series twice in one list
+    ncand = np.full(nq, C, np.int32)
+    ncand[1], ncand[2], ncand[3] = 3, 0, k
+    _rerank_case(ssh, Q, X, cand, ncand, band, k)
+    q, qoff = datagen.csr(Q)
+    db, dboff = datagen.csr(X)
+    ws = torch.empty(ssh.rerank_lb_workspace_bytes(nq, C, m), dtype=torch.uint8, device="cuda")
+    ssh.dtw_rerank(to_dev(q), to_dev(qoff), to_dev(db), to_dev(dboff), to_dev(cand), to_dev(ncand),
+                   band, m, m, k, ws=ws, prune=True)
+    torch.cuda.synchronize()
+    # workspace layout: dist, LB (float32 [nq][C]), marks (u8), slot lists (int32:
+    # the first pass's nq k, then the second pass's nq (C - k)), envelopes
+    al = lambda v: (v + 255) // 256 * 256  # noqa: E731
+    off = 2 * al(nq * C * 4)
+    marks = to_np(ws[off:off + nq * C]).reshape(nq, C)
+    off += al(nq * C)
+    lists = to_np(ws[off:off + nq * C * 4].view(torch.int32))
+    list1, list2 = lists[:nq * k].reshape(nq, k), lists[nq * k:].reshape(nq, C - k)
+    live = np.arange(C)[None, :] < ncand[:, None]
+    first = np.minimum(ncand, k)
+    assert np.all(marks[~live] == 0)
+    assert np.array_equal((marks == 1).sum(1), first)
+    assert np.array_equal((list1 >= 0).sum(1), first)
+    kept = (list2 >= 0).sum(1)
+    pruned = int(live.sum() - first.sum() - kept.sum())
+    print(f"pruned {pruned} of {int(live.sum())} live pairs", flush=True)
+    assert pruned > 0
 
 
 def test_rerank_reports_length_mismatch(ssh):
