@@ -47,6 +47,9 @@ struct FilterArgs {
   float sqrtW;                       // sqrt(W), rounded up
   float a2;                          // (c1 rnorm + c2 sqrtW)^2 (1 + 2^-18), rounded up
   float b0;                          // c2 sqrtW rnorm (1 + 2^-20), rounded up
+  float c1a;                         // relative factor of the L1 margin (no tiny r)
+  float c0a;                         // absolute term of the L1 margin
+  int32_t l1;                        // no r with 0 < |r| < 2^-14: the L1 margin applies
   int32_t W;
   int32_t delta;
 };
@@ -290,7 +293,12 @@ __device__ __forceinline__ void load_item4(const float* __restrict__ x, const Ch
   }
 }
 
-template <int W, int D, int ROWS>
+// L1 = true: the margin comes from A = sum over the window of |r^_k| |x^_k|
+// (fp16 values, an MFMA of the sign-cleared filter and samples), which needs
+// no second staged copy of the samples; see make_filter_args for the bound.
+// L1 = false (a filter with entries in fp16's subnormal range): the margin
+// from the bf16 sum of squares E.
+template <int W, int D, int ROWS, bool L1>
 __global__ __launch_bounds__(256) void sketch_mfma_kernel(
     const float* __restrict__ x, const int64_t* __restrict__ x_off, int64_t N, FilterArgs fa,
     uint64_t* __restrict__ bits, const int64_t* __restrict__ bit_word_off,
@@ -307,7 +315,7 @@ __global__ __launch_bounds__(256) void sketch_mfma_kernel(
 
   // quad u of the item sits at slot u + u / 4 (one pad slot per four)
   __shared__ uint2 xh[kWavesPerBlock][PF4 * kWave * 5 / 4];  // fp16 quads of the samples
-  __shared__ uint2 xq[kWavesPerBlock][PF4 * kWave * 5 / 4];  // bf16 quads of their squares
+  __shared__ uint2 xq[kWavesPerBlock][L1 ? 1 : PF4 * kWave * 5 / 4];  // bf16 quads of squares
   __shared__ uint32_t qser[kWavesPerBlock][QCAP];
   __shared__ uint32_t qwin[kWavesPerBlock][QCAP];
   __shared__ uint16_t bw[kWavesPerBlock][ROWS];
@@ -320,8 +328,10 @@ __global__ __launch_bounds__(256) void sketch_mfma_kernel(
   uint32_t* bits32 = reinterpret_cast<uint32_t*>(bits);
   if (lane == 0) qn[w] = 0;
 
-  // A operands: F[b][k] and the 0/1 band, b = lane % 16, k = 16 t + 4 (lane / 16) + e
+  // A operands: F[b][k] and either |F| (L1) or the 0/1 band, b = lane % 16,
+  // k = 16 t + 4 (lane / 16) + e
   half4 fr[KS];
+  half4 fa1[KS];
   bf16x4 fo[KS];
 #pragma unroll
   for (int t = 0; t < KS; ++t) {
@@ -330,6 +340,7 @@ __global__ __launch_bounds__(256) void sketch_mfma_kernel(
       const int u = 16 * t + 4 * grp + e - D * col;
       const bool in = u >= 0 && u < W;
       fr[t][e] = in ? (_Float16)fa.r[in ? u : 0] : (_Float16)0.0f;
+      fa1[t][e] = __builtin_fabsf16(fr[t][e]);
       fo[t][e] = in ? (short)0x3F80 : (short)0;
     }
   }
@@ -354,8 +365,9 @@ __global__ __launch_bounds__(256) void sketch_mfma_kernel(
     for (int i = 0; i < PF4; ++i) {
       const int p = lane + (lane >> 2) + kWave * 5 / 4 * i;  // slot of quad lane + 64 i
       xh[w][p] = make_uint2(pack_f16(pv[i][0], pv[i][1]), pack_f16(pv[i][2], pv[i][3]));
-      xq[w][p] = make_uint2(pack_bf16(pv[i][0] * pv[i][0], pv[i][1] * pv[i][1]),
-                            pack_bf16(pv[i][2] * pv[i][2], pv[i][3] * pv[i][3]));
+      if constexpr (!L1)
+        xq[w][p] = make_uint2(pack_bf16(pv[i][0] * pv[i][0], pv[i][1] * pv[i][1]),
+                              pack_bf16(pv[i][2] * pv[i][2], pv[i][3] * pv[i][3]));
 #pragma unroll
       for (int e = 0; e < 4; ++e) bad |= !(__builtin_fabsf(pv[i][e]) < 16384.0f);
     }
@@ -383,9 +395,15 @@ __global__ __launch_bounds__(256) void sketch_mfma_kernel(
 #pragma unroll
       for (int t = 0; t < KS; ++t) {
         const uint2 hv = xh2[b0s + 5 * t];
-        const uint2 qv = xq2[b0s + 5 * t];
         S = __builtin_amdgcn_mfma_f32_16x16x16f16(fr[t], __builtin_bit_cast(half4, hv), S, 0, 0, 0);
-        E = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(fo[t], __builtin_bit_cast(bf16x4, qv), E, 0, 0, 0);
+        if constexpr (L1) {
+          const uint2 av = make_uint2(hv.x & 0x7FFF7FFFu, hv.y & 0x7FFF7FFFu);  // |x^|
+          E = __builtin_amdgcn_mfma_f32_16x16x16f16(fa1[t], __builtin_bit_cast(half4, av), E, 0, 0, 0);
+        } else {
+          const uint2 qv = xq2[b0s + 5 * t];
+          E = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(fo[t], __builtin_bit_cast(bf16x4, qv), E, 0,
+                                                        0, 0);
+        }
       }
       const int wl = 16 * row + 4 * grp;  // item-relative window of S[0]
       const int nvalid = row < ROWS ? nb - c * SUB - wl : 0;
@@ -393,7 +411,9 @@ __global__ __launch_bounds__(256) void sketch_mfma_kernel(
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         if (i < nvalid) {
-          if (unsafe || !mfma_sign_trusted<W>(fa, S[i], E[i])) flags |= 1u << i;
+          const bool trusted = L1 ? __builtin_fabsf(S[i]) > __builtin_fmaf(fa.c1a, E[i], fa.c0a)
+                                  : mfma_sign_trusted<W>(fa, S[i], E[i]);
+          if (unsafe || !trusted) flags |= 1u << i;
           else if (S[i] >= 0.0f) nib |= 1u << i;
         }
       }
@@ -521,6 +541,31 @@ static ssh_status make_filter_args(const float* r, int W, int delta, FilterArgs&
   fa.c2 = round_up_f32(0x1p-14 * (1 + u) * 1.01);
   fa.rnorm = round_up_f32(__builtin_sqrt(n2) * (1 + 0x1p-40));
   fa.sqrtW = round_up_f32(__builtin_sqrt((double)W));
+  // L1 margin.  With r^ = fp16(r), x^ = fp16(x) and u = 2^-11: a filter entry
+  // is 0 or has |r| >= 2^-14 (else l1 = 0), so |r - r^| <= v |r^| with
+  // v = u / (1 - u); a sample has |x - x^| <= v |x^| or, below 2^-14 (flushed
+  // or subnormal), |x - x^| <= 2^-14.  Then |r x - r^ x^| <= (2v + v^2) |r^ x^|
+  // + 2^-14 (1 + v) |r^|.  The fast sum adds at most gam sum |r^ x^| of fp32
+  // rounding (gam as above), the oracle's float64 sum differs from the exact
+  // one by at most (W + 1) 2^-53 sum |r x|, and the MFMA's A is at least
+  // (1 - gam) sum |r^ x^|.  So |s16 - s64| <= c1a A + c0a with the constants
+  // below; the kernel trusts the sign when |s16| > fma(c1a, A, c0a), whose one
+  // rounding the factor 1 + 2^-20 covers.
+  {
+    bool tiny = false;
+    double l1r = 0.0;
+    for (int k = 0; k < W; ++k) {
+      const float a = __builtin_fabsf(r[k]);
+      if (a != 0.0f && a < 0x1p-14f) tiny = true;
+      l1r += __builtin_fabs((double)(_Float16)r[k]);
+    }
+    const double v = u / (1 - u);
+    const double e64 = (W + 1) * 0x1p-53;
+    const double rel = (2 * v + v * v + gam + e64 * (1 + v) * (1 + v)) / (1 - gam);
+    fa.c1a = round_up_f32(rel * 1.01 * (1 + 0x1p-20));
+    fa.c0a = round_up_f32(0x1p-14 * (1 + v) * (1 + e64) * l1r / (1 - gam) * 1.01 * (1 + 0x1p-20));
+    fa.l1 = tiny ? 0 : 1;
+  }
   const double alpha = (double)fa.c1 * fa.rnorm + (double)fa.c2 * fa.sqrtW;
   fa.a2 = round_up_f32(alpha * alpha * (1 + 0x1p-18));
   fa.b0 = round_up_f32((double)fa.c2 * fa.sqrtW * fa.rnorm * (1 + 0x1p-20));
@@ -568,10 +613,17 @@ ssh_status sketch_launch(const float* x, const int64_t* x_off, int64_t N, const 
   const dim3 blk(256);
 #define SSH_FAST(WW, DD, RR)                                                                   \
   if (!force_generic && W == WW && delta == DD) {                                              \
-    const unsigned fgrid = resident_grid(reinterpret_cast<const void*>(                        \
-        &sketch_mfma_kernel<WW, DD, RR>), N);                                                  \
-    sketch_mfma_kernel<WW, DD, RR><<<fgrid, blk, 0, stream>>>(x, x_off, N, fa, bits,          \
-                                                              bit_word_off, nbits, rc, err);  \
+    if (fa.l1) {                                                                               \
+      const unsigned fgrid = resident_grid(reinterpret_cast<const void*>(                      \
+          &sketch_mfma_kernel<WW, DD, RR, true>), N);                                          \
+      sketch_mfma_kernel<WW, DD, RR, true><<<fgrid, blk, 0, stream>>>(                         \
+          x, x_off, N, fa, bits, bit_word_off, nbits, rc, err);                                \
+    } else {                                                                                   \
+      const unsigned fgrid = resident_grid(reinterpret_cast<const void*>(                      \
+          &sketch_mfma_kernel<WW, DD, RR, false>), N);                                         \
+      sketch_mfma_kernel<WW, DD, RR, false><<<fgrid, blk, 0, stream>>>(                        \
+          x, x_off, N, fa, bits, bit_word_off, nbits, rc, err);                                \
+    }                                                                                          \
     return check_launch("ssh_sketch");                                                         \
   }
   // rows of 16 windows per item: 20 rows hold the 315 windows of a 1024-sample

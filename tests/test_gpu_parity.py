@@ -123,6 +123,20 @@ def test_sketch_adversarial_near_zero_windows(ssh, W, delta):
     assert rep > 0  # these windows must take the float64 path
 
 
+@pytest.mark.parametrize("W,delta", [(80, 3), (64, 4)])
+def test_sketch_filter_with_subnormal_fp16_entry(ssh, W, delta):
+    """A filter entry below 2^-14 (fp16's subnormal range) takes the fast path's
+    other margin (the sum of squares): near-zero windows and random walks."""
+    _announce(f"sketch tiny filter entry W={W}")
+    r, series = _near_zero_windows(W, 300, seed=W + 1)
+    r = r.copy()
+    r[3] = np.float32(3e-6)
+    r[W - 2] = np.float32(-2.0 ** -20)
+    series = series + list(datagen.random_walks(20, 1024, seed=W))
+    x, off = ragged(series)
+    assert _assert_sketch_equal(ssh, x, off, r, W, delta) > 0
+
+
 def test_sketch_huge_and_nonfinite_values(ssh):
     _announce("sketch huge / non-finite values")
     rng = np.random.default_rng(17)
