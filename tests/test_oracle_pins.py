@@ -439,3 +439,18 @@ def test_rerank_ties_and_padding():
     ids, d, _ = oracle.rerank(q, q_off, db, db_off, cand, ncand, 0.5, k=6)
     assert ids[0].tolist() == [0, 2, 1, 3, -1, -1]
     assert d[0, 0] == 0.0 and d[0, 1] == 0.0 and np.isinf(d[0, 4])
+
+
+def test_two_smallest_of_two_sorted_pairs():
+    """The merge rule for per-wave (smallest, second smallest) pairs of distinct
+    composites: for m1 <= m2 and o1 <= o2 the two smallest of {m1, m2, o1, o2}
+    are min(m1, o1) and med3(m1, o1, min(m2, o2)); brute force over small values
+    with repeats (the 'none' value 7 stands for an empty wave)."""
+    import itertools
+    vals = range(8)
+    for m1, m2, o1, o2 in itertools.product(vals, repeat=4):
+        if m1 > m2 or o1 > o2:
+            continue
+        srt = sorted([m1, m2, o1, o2])
+        assert min(m1, o1) == srt[0]
+        assert sorted([m1, o1, min(m2, o2)])[1] == srt[1], (m1, m2, o1, o2)
