@@ -231,6 +231,7 @@ constexpr int kCwsWaves = 4;  // wavefronts per workgroup
 constexpr int kPassA = 16;     // keyed tokens whose keys are loaded together
 constexpr int kHeavyCap = 64; // heavy tokens listed per series in LDS
 constexpr int kBandLds = 640; // hash values kept per wave in LDS for the fused band keys
+constexpr int64_t kSplitN = 4096;  // below this many series, a workgroup per series
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 
 // median of three; with a <= b it is the second smallest of {a, b, c}
@@ -267,7 +268,12 @@ struct BandOut {
   int G;  // series per fold: min(64 / L, kBandLds / H), at least 1
 };
 
-template <bool KEYS>
+// SPLIT (small batches): the four waves of a workgroup share one series.  Each
+// runs pass A over every fourth block of 64 tokens; their two smallest
+// composites per hash are merged through LDS (positions are the series' own,
+// so the merged pair is the pair pass A over all tokens gives), and wave 0
+// finishes the series: ties, pass B over the four heavy lists, output, keys.
+template <bool KEYS, bool SPLIT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void cws_kernel(
     const uint32_t* __restrict__ codes, const uint32_t* __restrict__ counts,
     const int64_t* __restrict__ hist_off, const int32_t* __restrict__ n_distinct, int64_t N,
@@ -279,6 +285,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void c
   __shared__ uint4 hl[kCwsWaves][kHeavyCap];
   // hash values of the last G series, for the band keys
   __shared__ uint64_t hvs[kCwsWaves][KEYS ? kBandLds : 1];
+  // SPLIT: each wave's (m1, m2) of its two hashes, heavy-token count and flag
+  __shared__ uint4 mm[SPLIT ? kCwsWaves : 1][SPLIT ? kWave : 1];
+  __shared__ int hn[kCwsWaves], ha[kCwsWaves];
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave-uniform
   const int lane = lane_id();
   const int H = t.H;
@@ -289,7 +298,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void c
       (void*)t.k16, 0, (int)(pad_row + row_bytes), 0x00020000);
   uint2* klist2 = reinterpret_cast<uint2*>(klist[w]);
   const uint64_t lt_mask = (1ull << lane) - 1ull;
-  const int64_t stride = (int64_t)gridDim.x * kCwsWaves;
+  const int64_t stride = SPLIT ? (int64_t)gridDim.x : (int64_t)gridDim.x * kCwsWaves;
+  const bool lead = !SPLIT || w == 0;  // the wave that finishes a series
   int slot = 0;  // series held in hvs since the last fold
   // after series s: fold the held series once G are held or s is the wave's last
   auto band_step = [&](int64_t s) {
@@ -307,15 +317,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void c
       slot = 0;
     }
   };
-  for (int64_t s = (int64_t)blockIdx.x * kCwsWaves + w; s < N; s += stride) {
+  for (int64_t s = SPLIT ? (int64_t)blockIdx.x : (int64_t)blockIdx.x * kCwsWaves + w; s < N;
+       s += stride) {
     const int D = n_distinct[s];
     uint64_t* out = hv + s * H;
     uint64_t* held = KEYS ? &hvs[w][slot * H] : nullptr;
     if (D <= 0) {
-      for (int j = lane; j < H; j += kWave) out[j] = SSH_HV_EMPTY;
-      if constexpr (KEYS)
-        if (lane == 0) held[0] = SSH_HV_EMPTY;  // the fold tests the first value only
-      band_step(s);
+      if (lead) {
+        for (int j = lane; j < H; j += kWave) out[j] = SSH_HV_EMPTY;
+        if constexpr (KEYS)
+          if (lane == 0) held[0] = SSH_HV_EMPTY;  // the fold tests the first value only
+        band_step(s);
+      }
       continue;
     }
     const int64_t ho = hist_off[s];
@@ -332,7 +345,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void c
         // ---- pass A over keyed tokens; the others (heavy) are listed ----
         uint32_t m1[2] = {kNone, kNone}, m2[2] = {kNone, kNone};
         int nhl = 0;  // heavy tokens seen; listed while nhl <= kHeavyCap
-        for (int d0 = 0; d0 < D; d0 += kWave) {
+        for (int d0 = SPLIT ? w * kWave : 0; d0 < D; d0 += (SPLIT ? kCwsWaves : 1) * kWave) {
           const int nc = D - d0 < kWave ? D - d0 : kWave;
           const bool have = lane < nc;
           const uint32_t mcode = have ? codes_s[d0 + lane] : 0u;
@@ -382,6 +395,27 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void c
           }
           wave_sync_lds();
         }
+        if constexpr (SPLIT) {
+          // the two smallest of two sorted pairs (m1 <= m2, o1 <= o2) are
+          // min(m1, o1) and med3(m1, o1, min(m2, o2))
+          mm[w][lane] = make_uint4(m1[0], m2[0], m1[1], m2[1]);
+          if (lane == 0) {
+            hn[w] = nhl;
+            ha[w] = any_heavy ? 1 : 0;
+          }
+          __syncthreads();
+          if (lead) {
+            for (int ww = 1; ww < kCwsWaves; ++ww) {
+              const uint4 o = mm[ww][lane];
+              m2[0] = med3(m1[0], o.x, m2[0] < o.y ? m2[0] : o.y);
+              m1[0] = o.x < m1[0] ? o.x : m1[0];
+              m2[1] = med3(m1[1], o.z, m2[1] < o.w ? m2[1] : o.w);
+              m1[1] = o.z < m1[1] ? o.z : m1[1];
+              any_heavy |= ha[ww] != 0;
+            }
+          }
+        }
+        if (lead) {
         // winner of pass A, unless its key is shared (then: exact re-scan)
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
@@ -433,9 +467,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void c
         if (any_heavy) {
           // the list built in pass A when it holds every heavy token; else the
           // heavy tokens of one chunk at a time
-          const bool listed = nhl <= kHeavyCap;
-          for (int d0 = 0; d0 < (listed ? 1 : D); d0 += kWave) {
-            int cnt = nhl;
+          bool listed = nhl <= kHeavyCap;
+          if constexpr (SPLIT)
+            for (int ww = 0; ww < kCwsWaves; ++ww) listed = listed && hn[ww] <= kHeavyCap;
+          // listed: one list (SPLIT: one per wave); else chunks of 64 tokens
+          const int nit = listed ? (SPLIT ? kCwsWaves : 1) : D;
+          for (int d0 = 0; d0 < nit; d0 += listed ? 1 : kWave) {
+            const int li = SPLIT && listed ? d0 : w;  // the list read
+            int cnt = SPLIT && listed ? hn[d0] : nhl;
             if (!listed) {
               const int nc = D - d0 < kWave ? D - d0 : kWave;
               const bool have = lane < nc;
@@ -452,7 +491,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void c
               wave_sync_lds();
             }
             for (int i = 0; i < cnt; ++i) {
-              const uint4 e = hl[w][i];
+              const uint4 e = hl[li][i];
               const uint32_t k = e.x;
               const double ls = __builtin_bit_cast(double, ((uint64_t)e.w << 32) | e.z);
               const int64_t row = (int64_t)k * H;
@@ -468,7 +507,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void c
             wave_sync_lds();
           }
         }
-      } else {
+        }  // lead
+      } else if (lead) {
         // more distinct tokens than 16-bit positions: plain exact scan
         for (int d = 0; d < D; ++d) {
 #pragma unroll
@@ -483,15 +523,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void c
       const double tmax = 281474976710655.0;  // 2^48 - 1
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
-        if (h ? v1 : v0) {
+        if (lead && (h ? v1 : v0)) {
           const uint64_t tq = (uint64_t)(b[h].t < tmax ? b[h].t : tmax);
           const uint64_t v = (tq << 16) | (uint64_t)b[h].k;
           out[h ? j1 : j0] = v;
           if constexpr (KEYS) held[h ? j1 : j0] = v;
         }
       }
+      if constexpr (SPLIT) __syncthreads();  // klist, hl and mm are reused next
     }
-    band_step(s);
+    if (lead) band_step(s);
   }
 }
 
@@ -533,14 +574,20 @@ ssh_status cws_launch(const uint32_t* codes, const uint32_t* counts, const int64
   CwsDev t{tab->r, tab->lnc, tab->beta, tab->a1, tab->lnS, tab->k16, tab->H, H2, tab->n};
   const unsigned grid = grid_for(N, kCwsWaves, 1 << 16);
   const bool fused = keys != nullptr && tab->H <= kBandLds;
-  if (fused) {
-    const int G = std::max(1, std::min(kWave / L, kBandLds / tab->H));
-    cws_kernel<true><<<grid, 256, 0, stream>>>(codes, counts, hist_off, n_distinct, N, t, hv, err,
-                                               BandOut{keys, K, L, seed, G});
-  } else {
-    cws_kernel<false><<<grid, 256, 0, stream>>>(codes, counts, hist_off, n_distinct, N, t, hv, err,
-                                                BandOut{nullptr, 0, 0, 0, 1});
-  }
+  // small batches (one series per wave would leave most of the GPU idle): a
+  // workgroup per series
+  const bool split = N < kSplitN;
+  const unsigned sgrid = grid_for(N, 1, 1 << 16);
+  const BandOut bo = fused ? BandOut{keys, K, L, seed, std::max(1, std::min(kWave / L, kBandLds / tab->H))}
+                           : BandOut{nullptr, 0, 0, 0, 1};
+  if (fused && split)
+    cws_kernel<true, true><<<sgrid, 256, 0, stream>>>(codes, counts, hist_off, n_distinct, N, t, hv, err, bo);
+  else if (fused)
+    cws_kernel<true, false><<<grid, 256, 0, stream>>>(codes, counts, hist_off, n_distinct, N, t, hv, err, bo);
+  else if (split)
+    cws_kernel<false, true><<<sgrid, 256, 0, stream>>>(codes, counts, hist_off, n_distinct, N, t, hv, err, bo);
+  else
+    cws_kernel<false, false><<<grid, 256, 0, stream>>>(codes, counts, hist_off, n_distinct, N, t, hv, err, bo);
   ssh_status st = check_launch("ssh_cws");
   if (st != SSH_OK || keys == nullptr || fused) return st;
   return band_keys_launch(hv, N, K, L, seed, keys, stream);
