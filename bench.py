@@ -42,11 +42,11 @@ VALU_LANE_OPS = FP32_VALU_TFLOPS * 1e12 / 4
 # kernel's source file still has the digest it was measured with.
 MEASURED_TRAFFIC = {
     # kernel: (source file, sha256 of it, FETCH_SIZE KiB, WRITE_SIZE KiB,
-    #          fetch scale, write scale); the 1 GiB copy read 524306.9 KiB on
+    #          fetch scale, write scale); the 1 GiB copy read 524307.3 KiB on
     #          FETCH_SIZE and 1048576 KiB on WRITE_SIZE
     "cws_kernel": ("paper_1610_07328_amd/csrc/cws.hip",
-                   "93ded3941c67d2e7eb0f095d6b8acc03550018db0801e84fa9437130d442dc7f",
-                   3570903.125, 903889.4375, 1048576.0 / 524306.9375, 1.0),
+                   "d82e1cadef07a1f436b9d60c3c44b8b84dbc605a29da5ea2e54e9dd832f8229e",
+                   3573179.0625, 903997.625, 1048576.0 / 524307.3125, 1.0),
 }
 
 
