@@ -108,10 +108,14 @@ __global__ __launch_bounds__(kShWaves * kWave) void shingle_kernel(
       const uint32_t* run = bm + (wd >> LW) * BS;
       uint32_t r = reinterpret_cast<const uint16_t*>(run + WPL)[j / GS];
       if constexpr (GS > 1) {
+        // the words of the group before word j, read unconditionally (they
+        // are in the lane's run) and counted when they precede j
         const int j0 = j - j % GS;
 #pragma unroll
-        for (int i = 0; i < GS - 1; ++i)
-          if (j0 + i < j) r += __builtin_popcount(run[j0 + i]);
+        for (int i = 0; i < GS - 1; ++i) {
+          const uint32_t c = __builtin_popcount(run[j0 + i]);
+          r += j0 + i < j ? c : 0u;
+        }
       }
       return r;
     } else {
