@@ -30,6 +30,11 @@
 //     their ln S (beyond that, pass B relists them one chunk at a time); every
 //     lane evaluates each of them exactly for its two hashes and compares by
 //     (ln a, k) with the pass-A winner, whose ln a is then evaluated exactly.
+// Batches of fewer than kSplitN series give each series a whole workgroup:
+// its four waves run pass A over alternate blocks of tokens and merge their
+// two smallest composites per hash, and the first wave finishes the series.
+// With band keys requested, the kernel also folds each series' hash values
+// into its L band keys (Algorithm 1) from a copy it keeps in LDS.
 #include <algorithm>
 #include <cmath>
 

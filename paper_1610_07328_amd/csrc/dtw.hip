@@ -24,7 +24,12 @@
 // slot that holds the first offset past the band (offset r + 1) and 0 for every
 // other slot, which keeps that slot at +inf without a select (all cell values
 // are >= 0, so adding 0 is exact).  In the steady state, blocks of rows whose
-// x indices are provably inside the series on every lane load x unchecked.
+// x indices are provably inside the series on every lane load x unchecked,
+// and each block's q and x values are loaded one block ahead.
+//
+// The kernel computes either every (query, column) pair or the pairs a slot
+// list names; the LB_Keogh-pruned re-rank at the end of this file uses two
+// such lists (the best-bound candidates, then the survivors).
 #include <cmath>
 
 #include "common.hpp"

@@ -7,15 +7,18 @@
 // matrix cores: with windows laid out in rows of 16, window 16 a + b is
 // sum_k F[b][k] X[k][a], F[b][k] = r[k - delta b] (the filter on a band),
 // X[k][a] = x[16 delta a + k], computed by 16x16x16 fp16 MFMAs (fp16 x fp16
-// products exact in fp32, fp32 accumulation).  The same product of the 0/1
-// band with bf16(x^2) gives each window's sum of squares.  The item's samples
-// are staged once in LDS and loaded for the next item while one is computed.
+// products exact in fp32, fp32 accumulation).  A second product gives each
+// window's margin term: |F| with the sign-cleared staged samples (sum of
+// |r^| |x^|, the L1 margin) or, for a filter with an fp16-subnormal entry, the
+// 0/1 band with bf16(x^2) (the sum of squares).  The item's samples are staged
+// once in LDS and loaded for the next item while one is computed.
 // Any other (W, delta) takes the generic path: one window per lane with
 // v_dot2_f32_f16 over fp16 sample pairs.
 //
 // Exactness: the reference bit is the sign of the float64 sum of the exact
 // float32 products in ascending filter index.  The fast sum s16 differs
-// from that float64 sum by at most
+// from that float64 sum by at most c1a A + c0a with the L1 margin (see
+// make_filter_args), else by at most
 //     c1 ||r|| ||w|| + c2 sqrt(W) (||r|| + ||w||)
 // (fp16 rounding of both operands, fp32 accumulation with up to W + 2
 // roundings counted at 2^-23 each in any order, fp16 underflow/flush at 2^-14

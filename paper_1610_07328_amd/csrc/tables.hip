@@ -11,7 +11,9 @@
 // (digit, tile) counts, and a stable scatter.  The scatter ranks elements
 // inside a wavefront with a ballot-based match of equal digits, keeps one
 // running count per (wave, digit) in LDS, reorders the tile in LDS and writes
-// each digit's run contiguously.
+// each digit's run contiguously.  The histogram and scatter take their tiles
+// in XCD-contiguous order, so the neighbouring partial lines that consecutive
+// tiles write meet in one L2.
 #include "band.hpp"
 
 namespace ssh {
