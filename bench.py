@@ -42,11 +42,11 @@ VALU_LANE_OPS = FP32_VALU_TFLOPS * 1e12 / 4
 # kernel's source file still has the digest it was measured with.
 MEASURED_TRAFFIC = {
     # kernel: (source file, sha256 of it, FETCH_SIZE KiB, WRITE_SIZE KiB,
-    #          fetch scale, write scale); the 1 GiB copy read 524307.3 KiB on
+    #          fetch scale, write scale); the 1 GiB copy read 524306.6 KiB on
     #          FETCH_SIZE and 1048576 KiB on WRITE_SIZE
     "cws_kernel": ("paper_1610_07328_amd/csrc/cws.hip",
-                   "d82e1cadef07a1f436b9d60c3c44b8b84dbc605a29da5ea2e54e9dd832f8229e",
-                   3573179.0625, 903997.625, 1048576.0 / 524307.3125, 1.0),
+                   "ccb9483ee387c2dfa4db072c851ec8119f7e73577ec1befb94fc91647033061b",
+                   3571453.9375, 903875.46875, 1048576.0 / 524306.5625, 1.0),
 }
 
 
