@@ -324,6 +324,27 @@ def main():
                 torch.equal(out_lb[1].view(torch.int32), out_full[1].view(torch.int32)))
     dtw_full["lb_pruned"] = {"ms": t_lb * 1e3, "speedup": t_full / t_lb, "same_results": same}
 
+    # weighted MinHash by integer replication over the same index histograms
+    # (outside the step: an alternative to the CWS stage, integer arithmetic only)
+    hv_int = torch.empty((N, p.H), dtype=torch.uint64, device=dev)
+
+    def wmh_index():
+        ssh.wmh_int(db.codes, db.counts, db.hoff, db.ndist, p.H, p.key_seed, out=hv_int)
+
+    wmh_index()
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(3):
+        wmh_index()
+    e1.record()
+    e1.synchronize()
+    t_wmh = e0.elapsed_time(e1) / 3 / 1e3
+    pairs = int(torch.clamp(db.nbits[:N].to(torch.int64) - p.n + 1, min=0).sum().item())
+    wmh_int_index = {"ms": t_wmh * 1e3, "series_per_s": N / t_wmh,
+                     "pair_hash_evals_per_s": pairs * p.H / t_wmh,
+                     "cws_stage_ms": per_stage["cws"]}
+    del hv_int
+
     # single-query latency with the index resident
     lat = []
     if args.latency_samples > 0:
@@ -376,6 +397,7 @@ def main():
                           "pruned_frac": float(1.0 - rsz.mean() / N)},
         "sketch_fp64_repaired_windows": repaired,
         "mean_distinct_shingles": sum_d / N,
+        "wmh_int_index": wmh_int_index,
         "roofline": roof,
     }
     if not args.no_cpu_baseline:

@@ -11,6 +11,8 @@
  *                  (Section 4.3; Section 2, eqs. WJaccardDef / CollProb)
  *   ssh_band_keys  one key per hash table from K hash values     (Algorithm 1)
  *   ssh_cws_band_keys  the two above in one pass
+ *   ssh_wmh_int    weighted MinHash by integer replication, integer only
+ *                  (Section 2, eq. CollProb; Section 4, one-pass hashing)
  *   ssh_table_build  the L hash tables                           (Algorithm 1)
  *   ssh_probe      retrieved set R of each query, ranked         (Algorithm 2)
  *   dtw_rerank     top-k of R by banded DTW distance             (Section 2.1,
@@ -169,6 +171,26 @@ ssh_status ssh_cws_prepare(const ssh_cws_tables* tab, void* stream);
 ssh_status ssh_cws(const uint32_t* codes, const uint32_t* counts, const int64_t* hist_off,
                    const int32_t* n_distinct, int64_t N, const ssh_cws_tables* tab, uint64_t* hv,
                    void* stream);
+
+/* Weighted MinHash by integer replication (Section 2, eqs. WJaccardDef and
+ * CollProb; the tokens hashed with a running minimum, Section 4, Discussions
+ * and Practical Issues).  A token of
+ * integer weight n_c stands for the n_c pairs (c, j), j = 1..n_c, and hash k
+ * keeps the pair of smallest
+ *     v_k(c, j) = mix(s_k ^ (c << 32 | j)),  s_k = mix(seed + (k + 1) * 0x9E3779B97F4A7C15),
+ * mix the SplitMix64 output function (as in ssh_band_keys).  Equal v_k resolve
+ * to the pair met first in input order (tokens as stored, then j ascending).
+ * The value stored is hv = c << 32 | j.  Two sets agree on hv with probability
+ * equal to their generalized Jaccard similarity, as for ssh_cws, with integer
+ * arithmetic only; the work is sum of counts x H per series.
+ *   codes, counts, hist_off, n_distinct  as for ssh_cws (any token order)
+ *   H            hashes per series, 1..65536
+ *   hv           uint64 [N * H] output, series-major; SSH_HV_EMPTY for a
+ *                series whose counts sum to zero
+ * Returns SSH_EINVAL for N < 0, H out of range or a null pointer (N > 0). */
+ssh_status ssh_wmh_int(const uint32_t* codes, const uint32_t* counts, const int64_t* hist_off,
+                       const int32_t* n_distinct, int64_t N, int32_t H, uint64_t seed, uint64_t* hv,
+                       void* stream);
 
 /* Band keys (Algorithm 1, one key per hash table).  Table l is keyed by the K
  * hash values hv[s*H + l*K .. + K) (H = K*L) folded with the SplitMix64 output

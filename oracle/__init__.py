@@ -28,6 +28,8 @@ from .ssh_oracle import (  # noqa: F401
     hv_encode,
     mix64,
     band_keys,
+    wmh_int,
+    wmh_int_batch,
     table_sort_bits,
     build_tables,
     probe,

@@ -8,6 +8,9 @@ Each function follows one passage of the paper (Luo & Shrivastava, "SSH
 * cws      -- Section 4.3 / Section 2 (Weighted Minwise Hashing, eqs.
               WJaccardDef and CollProb), realised with Ioffe's improved
               consistent weighted sampling, the method the paper cites;
+* wmh_int  -- Section 2 (eq. CollProb) by integer replication of the
+              weights, hashed with a running minimum as in Section 4
+              (Discussions and Practical Issues);
 * band_keys, build_tables -- Algorithm 1 (Pre-Processing), d hash tables;
 * probe    -- Algorithm 2 (Query Process), the retrieved set R;
 * dtw, rerank -- Section 2.1 (DTW) and the last step of Algorithm 2.
@@ -182,6 +185,45 @@ def mix64(z):
         z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
         z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
         return z ^ (z >> np.uint64(31))
+
+
+def wmh_int(codes, counts, H: int, seed: int) -> np.ndarray:
+    """Weighted MinHash of one weighted set by integer replication -> hv [H].
+
+    Section 2, eq. CollProb: a hash whose collision probability is the
+    generalized Jaccard similarity.  A token c of integer weight n stands for
+    the n distinct elements (c, 1) .. (c, n), so the weighted set becomes a
+    plain set and one min-hash over it is such a hash; Section 4 (Discussions
+    and Practical Issues) hashes the tokens with a running minimum.  Element
+    (c, j) is the integer c * 2^32 + j; hash k ranks it by
+    mix(s_k XOR element), s_k = mix(seed + (k+1) * gamma), and keeps the
+    element of smallest rank (the first one in input order on equal ranks).
+    A set whose weights sum to zero gets EMPTY.
+    """
+    codes = np.asarray(codes, dtype=np.uint64)
+    counts = np.asarray(counts, dtype=np.int64)
+    total = int(counts.sum())
+    if total == 0:
+        return np.full(H, EMPTY, dtype=np.uint64)
+    # the replicated elements in input order: token by token, j ascending
+    starts = np.cumsum(counts) - counts
+    j = np.arange(total, dtype=np.int64) - np.repeat(starts, counts) + 1
+    elem = (np.repeat(codes, counts) << np.uint64(32)) | j.astype(np.uint64)
+    k = np.arange(H, dtype=object)
+    s = mix64(np.array([(seed + (kk + 1) * GOLDEN_GAMMA) & U64 for kk in k], dtype=np.uint64))
+    rank = mix64(s[:, None] ^ elem[None, :])
+    return elem[np.argmin(rank, axis=1)]  # argmin: first of equal minima
+
+
+def wmh_int_batch(codes, counts, hist_off, n_distinct, H: int, seed: int) -> np.ndarray:
+    """wmh_int of every series of a ragged batch (layout of ssh_shingle) -> [N, H]."""
+    N = len(hist_off) - 1
+    out = np.empty((N, H), dtype=np.uint64)
+    for i in range(N):
+        a = int(hist_off[i])
+        d = int(n_distinct[i])
+        out[i] = wmh_int(codes[a:a + d], counts[a:a + d], H, seed)
+    return out
 
 
 def band_keys(hv, K: int, L: int, seed: int) -> np.ndarray:

@@ -57,6 +57,10 @@ ssh_status rerank_launch(const float* q, const int64_t* q_off, int nq, const flo
                          int64_t db_len, int k, int64_t* out_id, float* out_dist, void* ws,
                          size_t ws_bytes, hipStream_t stream);
 
+ssh_status wmh_int_launch(const uint32_t* codes, const uint32_t* counts, const int64_t* hist_off,
+                          const int32_t* n_distinct, int64_t N, int H, uint64_t seed, uint64_t* hv,
+                          hipStream_t stream);
+
 int take_sketch_err();
 int take_shingle_err();
 int take_cws_err();
@@ -202,6 +206,16 @@ ssh_status ssh_cws_band_keys(const uint32_t* codes, const uint32_t* counts,
               "ssh_cws_band_keys: null pointer");
   return cws_launch(codes, counts, hist_off, n_distinct, N, tab, hv, keys, K, L, seed,
                     as_stream(stream));
+}
+
+ssh_status ssh_wmh_int(const uint32_t* codes, const uint32_t* counts, const int64_t* hist_off,
+                       const int32_t* n_distinct, int64_t N, int32_t H, uint64_t seed, uint64_t* hv,
+                       void* stream) {
+  SSH_REQUIRE(N >= 0, "ssh_wmh_int: N < 0");
+  SSH_REQUIRE(H >= 1 && H <= 65536, "ssh_wmh_int: H out of [1, 65536]");
+  if (N == 0) return SSH_OK;
+  SSH_REQUIRE(codes && counts && hist_off && n_distinct && hv, "ssh_wmh_int: null pointer");
+  return wmh_int_launch(codes, counts, hist_off, n_distinct, N, H, seed, hv, as_stream(stream));
 }
 
 ssh_status ssh_band_keys(const uint64_t* hv, int64_t N, int32_t K, int32_t L, uint64_t seed,

@@ -1,0 +1,86 @@
+// Weighted MinHash by integer replication (Section 2, eqs. WJaccardDef and
+// CollProb; the one-pass minimum of Section 4, Discussions and Practical Issues).
+//
+// With integer weights, a weighted set {(c, n_c)} is the plain set of pairs
+// (c, j), j = 1..n_c, and a min-hash over those pairs collides between two
+// series with probability sum_c min(n_c, m_c) / sum_c max(n_c, m_c), the
+// generalized Jaccard similarity.  Hash k ranks a pair by
+//     v_k(c, j) = mix(s_k ^ (c << 32 | j)),  s_k = mix(seed + (k + 1) gamma),
+// mix the SplitMix64 output function, gamma = 0x9E3779B97F4A7C15, and the
+// hash value is the pair (c << 32 | j) of smallest v_k; equal v_k resolve to
+// the pair met first in input order (token order, then j ascending).  No
+// floating point is involved, so the result is exact by construction.
+//
+// One wavefront per series.  Lane L holds the running minima of hashes L and
+// L + 64 (G = 2 groups for H <= 128; larger H loops over groups of 128 and
+// re-reads the tokens from cache).  Tokens are loaded 64 at a time, one per
+// lane, and broadcast with readlane, so the pair loop is wave-uniform and
+// every active lane does one 64-bit mix per pair and hash.
+#include "band.hpp"
+#include "common.hpp"
+
+namespace ssh {
+
+constexpr int kWmhWaves = 4;
+
+__global__ __launch_bounds__(kWave * kWmhWaves) void wmh_int_kernel(
+    const uint32_t* __restrict__ codes, const uint32_t* __restrict__ counts,
+    const int64_t* __restrict__ hist_off, const int32_t* __restrict__ n_distinct, int64_t N,
+    int H, uint64_t seed, uint64_t* __restrict__ hv) {
+  const int lane = lane_id();
+  const int64_t wave0 = (int64_t)blockIdx.x * kWmhWaves + threadIdx.x / kWave;
+  const int64_t nwaves = (int64_t)gridDim.x * kWmhWaves;
+  for (int64_t s = wave0; s < N; s += nwaves) {
+    const int64_t off = hist_off[s];
+    const int d = n_distinct[s];
+    for (int k0 = 0; k0 < H; k0 += 2 * kWave) {
+      const int ka = k0 + lane, kb = k0 + kWave + lane;
+      const uint64_t sa = mix64(seed + (uint64_t)(ka + 1) * 0x9E3779B97F4A7C15ull);
+      const uint64_t sb = mix64(seed + (uint64_t)(kb + 1) * 0x9E3779B97F4A7C15ull);
+      uint64_t va = ~0ull, vb = ~0ull, ia = SSH_HV_EMPTY, ib = SSH_HV_EMPTY;
+      bool have = false;  // wave-uniform: some pair has been seen
+      for (int t0 = 0; t0 < d; t0 += kWave) {
+        const int nt = d - t0 < kWave ? d - t0 : kWave;
+        const uint32_t myc = lane < nt ? codes[off + t0 + lane] : 0u;
+        const uint32_t myn = lane < nt ? counts[off + t0 + lane] : 0u;
+        for (int t = 0; t < nt; ++t) {
+          const uint32_t c = __builtin_amdgcn_readlane(myc, t);
+          const uint32_t n = __builtin_amdgcn_readlane(myn, t);
+          uint32_t j = 1;
+          if (!have && n > 0) {
+            // the first pair seeds the minima, so a pair whose v is all ones
+            // still wins when nothing smaller follows
+            const uint64_t key = (uint64_t)c << 32 | 1u;
+            va = mix64(sa ^ key);
+            vb = mix64(sb ^ key);
+            ia = ib = key;
+            have = true;
+            j = 2;
+          }
+          for (; j - 1u < n; ++j) {  // j = .. n, and ends for n = 2^32 - 1
+            const uint64_t key = (uint64_t)c << 32 | j;
+            const uint64_t wa = mix64(sa ^ key);
+            const uint64_t wb = mix64(sb ^ key);
+            if (wa < va) { va = wa; ia = key; }
+            if (wb < vb) { vb = wb; ib = key; }
+          }
+        }
+      }
+      if (ka < H) hv[s * H + ka] = ia;
+      if (kb < H) hv[s * H + kb] = ib;
+    }
+  }
+}
+
+ssh_status wmh_int_launch(const uint32_t* codes, const uint32_t* counts, const int64_t* hist_off,
+                          const int32_t* n_distinct, int64_t N, int H, uint64_t seed, uint64_t* hv,
+                          hipStream_t stream) {
+  if (N == 0) return SSH_OK;
+  const int64_t want = (N + kWmhWaves - 1) / kWmhWaves;
+  const int blocks = (int)(want < (1 << 20) ? want : (1 << 20));
+  wmh_int_kernel<<<blocks, kWave * kWmhWaves, 0, stream>>>(codes, counts, hist_off, n_distinct, N, H,
+                                                           seed, hv);
+  return check_launch("ssh_wmh_int");
+}
+
+}  // namespace ssh

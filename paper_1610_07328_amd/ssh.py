@@ -58,6 +58,7 @@ SIGNATURES = {
     "ssh_band_keys": (_i32, [_vp, _i64, _i32, _i32, _u64, _vp, _vp]),
     "ssh_cws_band_keys": (_i32, [_vp, _vp, _vp, _vp, _i64, ctypes.POINTER(_CwsTablesC), _i32,
                                  _i32, _u64, _vp, _vp, _vp]),
+    "ssh_wmh_int": (_i32, [_vp, _vp, _vp, _vp, _i64, _i32, _u64, _vp, _vp]),
     "ssh_table_workspace_bytes": (_sz, [_i64, _i32]),
     "ssh_table_build": (_i32, [_vp, _i64, _i32, _vp, _vp, _vp, _sz, _vp]),
     "ssh_probe_workspace_bytes": (_sz, [_i32, _i32, _i32]),
@@ -255,6 +256,20 @@ def cws_band_keys(codes, counts, hist_off, n_distinct, tables: CwsTables, K: int
         ctypes.byref(tables._c), K, L, seed & ((1 << 64) - 1), _dev(hv, torch.uint64, "hv"),
         _dev(keys, torch.uint64, "keys"), _stream()), "ssh_cws_band_keys")
     return hv.view(-1)[: N * tables.H].view(N, tables.H), keys.view(-1)[: N * L].view(N, L)
+
+
+def wmh_int(codes, counts, hist_off, n_distinct, H: int, seed: int, out=None):
+    """Weighted MinHash by integer replication; returns hv [N, H] (uint64)."""
+    N = hist_off.numel() - 1
+    hv = out if out is not None else torch.empty((max(N, 1), H), dtype=torch.uint64,
+                                                 device=codes.device)
+    if hv.numel() < N * H:
+        raise SSHError("wmh_int: output buffer too small")
+    _check(lib().ssh_wmh_int(
+        _dev(codes, torch.uint32, "codes"), _dev(counts, torch.uint32, "counts"),
+        _dev(hist_off, torch.int64, "hist_off"), _dev(n_distinct, torch.int32, "n_distinct"), N,
+        H, seed & ((1 << 64) - 1), _dev(hv, torch.uint64, "hv"), _stream()), "ssh_wmh_int")
+    return hv.view(-1)[: N * H].view(N, H)
 
 
 def table_workspace_bytes(N: int, L: int) -> int:

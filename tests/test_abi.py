@@ -34,7 +34,7 @@ def _declared_functions():
 def test_header_declares_the_pipeline():
     names = _declared_functions()
     for want in ["ssh_sketch", "ssh_shingle", "ssh_cws", "ssh_band_keys", "ssh_cws_band_keys", "dtw_rerank",
-                 "ssh_table_build", "ssh_probe", "ssh_plan", "ssh_cws_prepare"]:
+                 "ssh_table_build", "ssh_probe", "ssh_plan", "ssh_cws_prepare", "ssh_wmh_int"]:
         assert want in names
 
 
@@ -121,6 +121,13 @@ def test_validation_rejects_without_device_work(ssh):
                                None, None) == EINVAL
     assert L.ssh_cws_band_keys(None, None, None, None, 0, ctypes.byref(t), 3, 4, 7, None,
                                None, None) == 0
+    # integer-replication MinHash: H range, null pointers, empty batch
+    assert L.ssh_wmh_int(dummy, dummy, dummy, dummy, 4, 0, 1, dummy, None) == EINVAL
+    assert L.ssh_wmh_int(dummy, dummy, dummy, dummy, 4, 65537, 1, dummy, None) == EINVAL
+    assert L.ssh_wmh_int(dummy, dummy, dummy, dummy, -1, 8, 1, dummy, None) == EINVAL
+    assert L.ssh_wmh_int(dummy, None, dummy, dummy, 4, 8, 1, dummy, None) == EINVAL
+    assert b"null pointer" in L.ssh_last_error()
+    assert L.ssh_wmh_int(None, None, None, None, 0, 8, 1, None, None) == 0
     assert L.ssh_status_str(EUNSUP) == b"SSH_EUNSUPPORTED"
 
 

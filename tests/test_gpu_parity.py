@@ -247,6 +247,61 @@ def test_cws_random_sets_exact(ssh):
         _cws_case(ssh, n, H, sets, seed=n)
 
 
+def _wmh_case(ssh, sets, H, seed):
+    codes = np.concatenate([c for c, _ in sets] + [np.zeros(0, np.uint32)]).astype(np.uint32)
+    counts = np.concatenate([k for _, k in sets] + [np.zeros(0, np.uint32)]).astype(np.uint32)
+    ho = np.zeros(len(sets) + 1, np.int64)
+    np.cumsum([len(c) for c, _ in sets], out=ho[1:])
+    nd = np.array([len(c) for c, _ in sets], np.int32)
+    hv = to_np(ssh.wmh_int(to_dev(codes), to_dev(counts), to_dev(ho), to_dev(nd), H, seed))
+    want = oracle.wmh_int_batch(codes, counts, ho, nd, H, seed)
+    assert hv.shape == want.shape
+    bad = np.argwhere(hv != want)
+    assert bad.size == 0, (H, seed, bad[:5])
+
+
+@pytest.mark.parametrize("H", [1, 64, 100, 130, 300])
+def test_wmh_int_random_sets_exact(ssh, H):
+    """Ragged batch: empty sets, zero counts, unsorted tokens, more than 64
+    tokens per set, and hash groups past 128."""
+    _announce(f"wmh_int random sets H={H}")
+    rng = np.random.default_rng(40 + H)
+    sets = [(np.zeros(0, np.uint32), np.zeros(0, np.uint32)),
+            (np.array([5], np.uint32), np.array([0], np.uint32))]
+    for i in range(150):
+        D = int(rng.integers(1, 200))
+        c = rng.choice(1 << 15, size=D, replace=False).astype(np.uint32)
+        if i % 3:
+            c = np.sort(c)
+        k = rng.integers(0 if i % 5 == 0 else 1, 12, size=D).astype(np.uint32)
+        sets.append((c, k))
+    sets.append((np.array([7, 9], np.uint32), np.array([3000, 1], np.uint32)))
+    _wmh_case(ssh, sets, H, seed=H * 1000003)
+
+
+def test_wmh_int_after_sketch_and_shingle_with_band_keys(ssh):
+    """Random walks through the device sketch and shingle kernels, then the
+    integer MinHash and band keys; the oracle runs its own chain from the same
+    series.  The integer hash values feed the same tables as the CWS ones."""
+    _announce("wmh_int chained after sketch and shingle, band keys")
+    W, delta, n, K, L = 80, 3, 15, 10, 10
+    lens = [1024] * 60 + [0, 90, 300, 777]
+    X = datagen.random_walks(len(lens), 1024, seed=44)
+    series = [X[i, :m] for i, m in enumerate(lens)]
+    x, off = ragged(series)
+    r = datagen.filter_r(W, seed=44)
+    p = ssh.plan(off, W, delta, n)
+    bits, nb, _ = ssh.sketch(to_dev(x), to_dev(off), r, W, delta, to_dev(p.bit_word_off))
+    codes, counts, nd = ssh.shingle(bits, to_dev(p.bit_word_off), nb, n, to_dev(p.hist_off))
+    hv = ssh.wmh_int(codes, counts, to_dev(p.hist_off), nd, K * L, 3)
+    keys = to_np(ssh.band_keys(hv, K, L, 11))
+    hv = to_np(hv)
+    sets = [oracle.shingle(oracle.sketch_series(xs, r, W, delta), n) for xs in series]
+    want = np.stack([oracle.wmh_int(c, k, K * L, 3) for c, k in sets])
+    assert np.array_equal(hv, want)
+    assert np.array_equal(keys, oracle.band_keys(want, K, L, 11))
+
+
 def test_cws_equal_keys_resolved_exactly(ssh):
     """Draws whose weight-1 ln a values all fall into one 16-bit key bucket."""
     _announce("cws equal keys")

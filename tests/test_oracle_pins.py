@@ -454,3 +454,93 @@ def test_two_smallest_of_two_sorted_pairs():
         srt = sorted([m1, m2, o1, o2])
         assert min(m1, o1) == srt[0]
         assert sorted([m1, o1, min(m2, o2)])[1] == srt[1], (m1, m2, o1, o2)
+
+
+# ----------------------------------------------------------------------------
+# weighted MinHash by integer replication (Section 2, eq. CollProb)
+# ----------------------------------------------------------------------------
+def _wmh_sparse(x):
+    sup = np.flatnonzero(x)
+    return sup.astype(np.uint32), x[sup].astype(np.uint32)
+
+
+def test_wmh_int_collision_rate_matches_weighted_jaccard():
+    # counts change on shared codes, so the weighted similarity differs from
+    # the plain set one: ignoring the weights would fail here
+    rng = np.random.default_rng(21)
+    H = 10000
+    seen = []
+    for trial in range(6):
+        x = np.zeros(48, np.int64)
+        sup = rng.choice(48, size=30, replace=False)
+        x[sup] = rng.integers(1, 13, size=30)
+        y = x.copy()
+        move = rng.random(48) < trial / 5.0
+        y[move] = rng.integers(0, 13, size=int(move.sum()))
+        if y.sum() == 0:
+            continue
+        J = _wjaccard(x, y)
+        hx = oracle.wmh_int(*_wmh_sparse(x), H, seed=77)
+        hy = oracle.wmh_int(*_wmh_sparse(y), H, seed=77)
+        p = float(np.mean(hx == hy))
+        assert abs(p - J) <= 0.02, (trial, J, p)
+        seen.append(J)
+    assert min(seen) < 0.4 and max(seen) == 1.0
+
+
+def test_wmh_int_elements_valid_and_order_free():
+    rng = np.random.default_rng(22)
+    H = 64
+    for _ in range(20):
+        D = int(rng.integers(1, 40))
+        c = rng.choice(1 << 15, size=D, replace=False).astype(np.uint32)
+        n = rng.integers(1, 30, size=D).astype(np.uint32)
+        hv = oracle.wmh_int(c, n, H, seed=5)
+        code = (hv >> np.uint64(32)).astype(np.int64)
+        j = (hv & np.uint64(0xFFFFFFFF)).astype(np.int64)
+        weight = dict(zip(c.tolist(), n.tolist()))
+        for cc, jj in zip(code.tolist(), j.tolist()):
+            assert cc in weight and 1 <= jj <= weight[cc]
+        perm = rng.permutation(D)
+        assert np.array_equal(oracle.wmh_int(c[perm], n[perm], H, seed=5), hv)
+        # a zero-weight token adds no element
+        c0 = np.append(c, np.uint32(1 << 15))
+        n0 = np.append(n, np.uint32(0))
+        assert np.array_equal(oracle.wmh_int(c0, n0, H, seed=5), hv)
+        # unit weights: plain min-hash over the codes, every element (c, 1)
+        assert np.all(oracle.wmh_int(c, np.ones(D, np.uint32), H, seed=5)
+                      & np.uint64(0xFFFFFFFF) == 1)
+
+
+def test_wmh_int_sub_multiset_keeps_shared_minimum():
+    # A inside B: where B's minimum element belongs to A, it is A's minimum too
+    rng = np.random.default_rng(23)
+    H = 256
+    agree = 0
+    for _ in range(10):
+        D = int(rng.integers(5, 30))
+        c = rng.choice(1 << 12, size=D, replace=False).astype(np.uint32)
+        nA = rng.integers(1, 10, size=D).astype(np.uint32)
+        nB = nA + rng.integers(0, 5, size=D).astype(np.uint32)
+        extra = np.setdiff1d(rng.choice(1 << 12, size=10, replace=False), c).astype(np.uint32)
+        cB = np.concatenate([c, extra])
+        nB = np.concatenate([nB, np.full(len(extra), 3, np.uint32)])
+        hA = oracle.wmh_int(c, nA, H, seed=9)
+        hB = oracle.wmh_int(cB, nB, H, seed=9)
+        wA = dict(zip(c.tolist(), nA.tolist()))
+        for a, b in zip(hA.tolist(), hB.tolist()):
+            cb, jb = b >> 32, b & 0xFFFFFFFF
+            if cb in wA and jb <= wA[cb]:
+                assert a == b
+                agree += 1
+    assert agree > 0
+
+
+def test_wmh_int_empty_and_seed():
+    assert np.all(oracle.wmh_int(np.zeros(0, np.uint32), np.zeros(0, np.uint32), 7, 1)
+                  == np.uint64(oracle.EMPTY))
+    assert np.all(oracle.wmh_int(np.array([3], np.uint32), np.array([0], np.uint32), 7, 1)
+                  == np.uint64(oracle.EMPTY))
+    c = np.arange(50, dtype=np.uint32)
+    n = np.full(50, 4, np.uint32)
+    assert not np.array_equal(oracle.wmh_int(c, n, 64, 1), oracle.wmh_int(c, n, 64, 2))
