@@ -22,6 +22,35 @@
 namespace ssh {
 
 constexpr int kWmhWaves = 4;
+constexpr uint64_t kMixC1 = 0xBF58476D1CE4E5B9ull;  // SplitMix64 output multipliers
+constexpr uint64_t kMixC2 = 0x94D049BB133111EBull;
+
+// mix(s ^ (c << 32 | j)) for one token c, the high word of the argument
+// (s_hi ^ c) fixed: the first round's shift of the high word and its share
+// of the first product's high word are taken once per token.
+struct TokMix {
+  uint32_t zhi;  // s_hi ^ c
+  uint32_t kc;   // low word of (zhi ^ zhi >> 30) * C1_lo
+  uint32_t slo;  // s_lo
+};
+
+__device__ __forceinline__ TokMix tok_mix(uint64_t s, uint32_t c) {
+  TokMix t;
+  t.zhi = (uint32_t)(s >> 32) ^ c;
+  t.kc = (t.zhi ^ (t.zhi >> 30)) * (uint32_t)kMixC1;
+  t.slo = (uint32_t)s;
+  return t;
+}
+
+__device__ __forceinline__ uint64_t elem_mix(const TokMix& t, uint32_t j) {
+  const uint32_t zlo = t.slo ^ j;
+  const uint32_t tlo = zlo ^ ((zlo >> 30) | (t.zhi << 2));  // low word of z ^ z >> 30
+  const uint64_t p = (uint64_t)tlo * (uint32_t)kMixC1;
+  const uint32_t phi = (uint32_t)(p >> 32) + tlo * (uint32_t)(kMixC1 >> 32) + t.kc;
+  uint64_t z = (uint64_t)phi << 32 | (uint32_t)p;
+  z = (z ^ (z >> 27)) * kMixC2;
+  return z ^ (z >> 31);
+}
 
 __global__ __launch_bounds__(kWave * kWmhWaves) void wmh_int_kernel(
     const uint32_t* __restrict__ codes, const uint32_t* __restrict__ counts,
@@ -57,12 +86,12 @@ __global__ __launch_bounds__(kWave * kWmhWaves) void wmh_int_kernel(
             have = true;
             j = 2;
           }
+          const TokMix ta = tok_mix(sa, c), tb = tok_mix(sb, c);
           for (; j - 1u < n; ++j) {  // j = .. n, and ends for n = 2^32 - 1
-            const uint64_t key = (uint64_t)c << 32 | j;
-            const uint64_t wa = mix64(sa ^ key);
-            const uint64_t wb = mix64(sb ^ key);
-            if (wa < va) { va = wa; ia = key; }
-            if (wb < vb) { vb = wb; ib = key; }
+            const uint64_t wa = elem_mix(ta, j);
+            const uint64_t wb = elem_mix(tb, j);
+            if (wa < va) { va = wa; ia = (uint64_t)c << 32 | j; }
+            if (wb < vb) { vb = wb; ib = (uint64_t)c << 32 | j; }
           }
         }
       }
