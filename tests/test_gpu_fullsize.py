@@ -77,6 +77,19 @@ def _check_sampled_hash(hb: HashBatch, x, off, r, draws, p: Params, sample):
         assert np.array_equal(keys[i], okeys), f"series {s}: keys differ"
 
 
+def _check_sampled_wmh(ssh, hb: HashBatch, x, off, r, p: Params, sample):
+    """Integer-replication MinHash of the whole batch (the benchmark's launch),
+    sampled series against the oracle's own sketch, shingle and MinHash."""
+    hv = torch.empty((hb.N, p.H), dtype=torch.uint64, device=hb.codes.device)
+    ssh.wmh_int(hb.codes, hb.counts, hb.hoff, hb.ndist, p.H, p.key_seed, out=hv)
+    got = _rows(hv, sample)
+    del hv
+    for i, s in enumerate(sample):
+        xs = x[off[s]:off[s + 1]]
+        oc, ok = oracle.shingle(oracle.sketch_series(xs, r, p.W, p.delta), p.n)
+        assert np.array_equal(got[i], oracle.wmh_int(oc, ok, p.H, p.key_seed)), s
+
+
 def _check_tables(ix: Index, N: int, L: int):
     """Each table: a permutation of the ids, keys in place, stable by the top
     table_sort_bits(N) bits."""
@@ -188,6 +201,7 @@ def test_index_build_workload_sampled(ssh):
     rng = np.random.default_rng(1)
     sample = np.sort(np.concatenate([rng.choice(N, 44, replace=False), [0, 1, N - 2, N - 1]]))
     _check_sampled_hash(db, x, off, r, draws, p, sample)
+    _check_sampled_wmh(ssh, db, x, off, r, p, sample)
     _check_tables(ix, N, p.L)
     qsel = _query_sample(qb, rng, 16)
     _check_sampled_hash(qh, qx, qoff, r, draws, p, qsel)
