@@ -75,19 +75,19 @@ __global__ __launch_bounds__(kWave * kWmhWaves) void wmh_int_kernel(
         for (int t = 0; t < nt; ++t) {
           const uint32_t c = __builtin_amdgcn_readlane(myc, t);
           const uint32_t n = __builtin_amdgcn_readlane(myn, t);
-          uint32_t j = 1;
           if (!have && n > 0) {
             // the first pair seeds the minima, so a pair whose v is all ones
-            // still wins when nothing smaller follows
+            // still wins when nothing smaller follows (the loop below meets
+            // it again with an equal v, which changes nothing)
             const uint64_t key = (uint64_t)c << 32 | 1u;
             va = mix64(sa ^ key);
             vb = mix64(sb ^ key);
             ia = ib = key;
             have = true;
-            j = 2;
           }
           const TokMix ta = tok_mix(sa, c), tb = tok_mix(sb, c);
-          for (; j - 1u < n; ++j) {  // j = .. n, and ends for n = 2^32 - 1
+          // j = 1 .. n, wave-uniform; the test also ends the loop for n = 2^32 - 1
+          for (uint32_t j = 1; j - 1u < n; ++j) {
             const uint64_t wa = elem_mix(ta, j);
             const uint64_t wb = elem_mix(tb, j);
             if (wa < va) { va = wa; ia = (uint64_t)c << 32 | j; }
