@@ -12,8 +12,8 @@
 // floating point is involved, so the result is exact by construction.
 //
 // One wavefront per series.  Lane L holds the running minima of hashes L and
-// L + 64 (G = 2 groups for H <= 128; larger H loops over groups of 128 and
-// re-reads the tokens from cache).  Tokens are loaded 64 at a time, one per
+// L + 64 of a group of 128 (a last group of at most 64 hashes takes one per
+// lane); H > 128 loops over groups and re-reads the tokens from cache.  Tokens are loaded 64 at a time, one per
 // lane, and broadcast with readlane, so the pair loop is wave-uniform and
 // every active lane does one 64-bit mix per pair and hash.
 #include "band.hpp"
@@ -52,51 +52,70 @@ __device__ __forceinline__ uint64_t elem_mix(const TokMix& t, uint32_t j) {
   return z ^ (z >> 31);
 }
 
+// Hashes k0 + lane and, with TWO, k0 + 64 + lane of one series: the running
+// minimum over its elements in input order, stored to row[k] for k < H.
+template <bool TWO>
+__device__ __forceinline__ void wmh_group(const uint32_t* __restrict__ codes,
+                                          const uint32_t* __restrict__ counts, int64_t off, int d,
+                                          uint64_t seed, int k0, int H, uint64_t* __restrict__ row) {
+  const int lane = lane_id();
+  const int ka = k0 + lane, kb = k0 + kWave + lane;
+  const uint64_t sa = mix64(seed + (uint64_t)(ka + 1) * 0x9E3779B97F4A7C15ull);
+  const uint64_t sb = TWO ? mix64(seed + (uint64_t)(kb + 1) * 0x9E3779B97F4A7C15ull) : 0;
+  uint64_t va = ~0ull, vb = ~0ull, ia = SSH_HV_EMPTY, ib = SSH_HV_EMPTY;
+  bool have = false;  // wave-uniform: some element has been seen
+  for (int t0 = 0; t0 < d; t0 += kWave) {
+    const int nt = d - t0 < kWave ? d - t0 : kWave;
+    const uint32_t myc = lane < nt ? codes[off + t0 + lane] : 0u;
+    const uint32_t myn = lane < nt ? counts[off + t0 + lane] : 0u;
+    for (int t = 0; t < nt; ++t) {
+      const uint32_t c = __builtin_amdgcn_readlane(myc, t);
+      const uint32_t n = __builtin_amdgcn_readlane(myn, t);
+      if (!have && n > 0) {
+        // the first element seeds the minima, so an element whose rank is
+        // all ones still wins when nothing smaller follows (the loop below
+        // meets it again with an equal rank, which changes nothing)
+        const uint64_t key = (uint64_t)c << 32 | 1u;
+        va = mix64(sa ^ key);
+        ia = key;
+        if (TWO) {
+          vb = mix64(sb ^ key);
+          ib = key;
+        }
+        have = true;
+      }
+      const TokMix ta = tok_mix(sa, c), tb = tok_mix(sb, c);
+      // j = 1 .. n, wave-uniform; the test also ends the loop for n = 2^32 - 1
+      for (uint32_t j = 1; j - 1u < n; ++j) {
+        const uint64_t wa = elem_mix(ta, j);
+        if (wa < va) { va = wa; ia = (uint64_t)c << 32 | j; }
+        if (TWO) {
+          const uint64_t wb = elem_mix(tb, j);
+          if (wb < vb) { vb = wb; ib = (uint64_t)c << 32 | j; }
+        }
+      }
+    }
+  }
+  if (ka < H) row[ka] = ia;
+  if (TWO && kb < H) row[kb] = ib;
+}
+
+// One wave per series; hashes in groups of 128 (two per lane), the last group
+// of at most 64 with one per lane.
 __global__ __launch_bounds__(kWave * kWmhWaves) void wmh_int_kernel(
     const uint32_t* __restrict__ codes, const uint32_t* __restrict__ counts,
     const int64_t* __restrict__ hist_off, const int32_t* __restrict__ n_distinct, int64_t N,
     int H, uint64_t seed, uint64_t* __restrict__ hv) {
-  const int lane = lane_id();
   const int64_t wave0 = (int64_t)blockIdx.x * kWmhWaves + threadIdx.x / kWave;
   const int64_t nwaves = (int64_t)gridDim.x * kWmhWaves;
   for (int64_t s = wave0; s < N; s += nwaves) {
     const int64_t off = hist_off[s];
     const int d = n_distinct[s];
     for (int k0 = 0; k0 < H; k0 += 2 * kWave) {
-      const int ka = k0 + lane, kb = k0 + kWave + lane;
-      const uint64_t sa = mix64(seed + (uint64_t)(ka + 1) * 0x9E3779B97F4A7C15ull);
-      const uint64_t sb = mix64(seed + (uint64_t)(kb + 1) * 0x9E3779B97F4A7C15ull);
-      uint64_t va = ~0ull, vb = ~0ull, ia = SSH_HV_EMPTY, ib = SSH_HV_EMPTY;
-      bool have = false;  // wave-uniform: some pair has been seen
-      for (int t0 = 0; t0 < d; t0 += kWave) {
-        const int nt = d - t0 < kWave ? d - t0 : kWave;
-        const uint32_t myc = lane < nt ? codes[off + t0 + lane] : 0u;
-        const uint32_t myn = lane < nt ? counts[off + t0 + lane] : 0u;
-        for (int t = 0; t < nt; ++t) {
-          const uint32_t c = __builtin_amdgcn_readlane(myc, t);
-          const uint32_t n = __builtin_amdgcn_readlane(myn, t);
-          if (!have && n > 0) {
-            // the first pair seeds the minima, so a pair whose v is all ones
-            // still wins when nothing smaller follows (the loop below meets
-            // it again with an equal v, which changes nothing)
-            const uint64_t key = (uint64_t)c << 32 | 1u;
-            va = mix64(sa ^ key);
-            vb = mix64(sb ^ key);
-            ia = ib = key;
-            have = true;
-          }
-          const TokMix ta = tok_mix(sa, c), tb = tok_mix(sb, c);
-          // j = 1 .. n, wave-uniform; the test also ends the loop for n = 2^32 - 1
-          for (uint32_t j = 1; j - 1u < n; ++j) {
-            const uint64_t wa = elem_mix(ta, j);
-            const uint64_t wb = elem_mix(tb, j);
-            if (wa < va) { va = wa; ia = (uint64_t)c << 32 | j; }
-            if (wb < vb) { vb = wb; ib = (uint64_t)c << 32 | j; }
-          }
-        }
-      }
-      if (ka < H) hv[s * H + ka] = ia;
-      if (kb < H) hv[s * H + kb] = ib;
+      if (H - k0 > kWave)
+        wmh_group<true>(codes, counts, off, d, seed, k0, H, hv + s * H);
+      else
+        wmh_group<false>(codes, counts, off, d, seed, k0, H, hv + s * H);
     }
   }
 }
