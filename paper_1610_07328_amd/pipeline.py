@@ -22,6 +22,7 @@ class Params:
     K: int
     L: int
     key_seed: int = 0x5EED
+    wmh_seed: int = 0x1D5EED  # seed of the integer-replication MinHash
     band_frac: float = 0.05
     C: int = 50
     k: int = 10
@@ -77,10 +78,26 @@ class HashBatch:
         ssh.cws_band_keys(self.codes, self.counts, self.hoff, self.ndist, tables, self.p.K,
                           self.p.L, self.p.key_seed, out=(self.hv, self.keys))
 
-    def run(self, r: np.ndarray, tables: ssh.CwsTables):
+    def wmh_int_band_keys(self):
+        """Integer-replication MinHash, then band keys: the hash values and keys
+        feed the same tables, probe and re-rank as the CWS ones."""
+        ssh.wmh_int(self.codes, self.counts, self.hoff, self.ndist, self.p.H, self.p.wmh_seed,
+                    out=self.hv)
+        self.band_keys()
+
+    def run(self, r: np.ndarray, tables: ssh.CwsTables | None = None, method: str = "cws"):
+        """Sketch, shingle and hash the batch; method "cws" (needs tables) or
+        "wmh_int" (integer-replication MinHash)."""
+        if method not in ("cws", "wmh_int"):
+            raise ValueError(f"unknown hash method {method!r}")
+        if method == "cws" and tables is None:
+            raise ValueError("method 'cws' needs CWS tables")
         self.sketch(r)
         self.shingle()
-        self.cws_band_keys(tables)
+        if method == "cws":
+            self.cws_band_keys(tables)
+        else:
+            self.wmh_int_band_keys()
         return self.hv[: self.N], self.keys[: self.N]
 
 

@@ -555,6 +555,48 @@ def test_c1_probe_exact(ssh, c1):
         assert cand[P["nq"] + t, 0] == t
 
 
+def test_c1_wmh_int_pipeline_probe_exact(ssh, c1):
+    """The small configuration hashed with the integer MinHash through the
+    pipeline (sketch, shingle, MinHash, band keys, tables, probe), against the
+    oracle's own chain; H = 20 runs the one-hash-per-lane group."""
+    _announce("C1 integer MinHash pipeline and probe")
+    from paper_1610_07328_amd.pipeline import HashBatch, Index, Params, QueryBatch
+    X, r, Q, _ = c1
+    P = C1
+    p = Params(W=P["W"], delta=P["delta"], n=P["n"], K=P["K"], L=P["L"], C=P["C"])
+    x, off = datagen.csr(X)
+    qx, qoff = datagen.csr(Q)
+    db = HashBatch(to_dev(x), off, p)
+    qh = HashBatch(to_dev(qx), qoff, p)
+    db.run(r, method="wmh_int")
+    qh.run(r, method="wmh_int")
+    ix = Index(db)
+    ix.build()
+    qb = QueryBatch(qh, ix)
+    qb.probe()
+    torch.cuda.synchronize()
+
+    def chain(S):
+        B = oracle.sketch_batch(S, r, P["W"], P["delta"])
+        hv = np.stack([oracle.wmh_int(*oracle.shingle(b, P["n"]), p.H, p.wmh_seed) for b in B])
+        return hv, oracle.band_keys(hv, P["K"], P["L"], p.key_seed)
+
+    ohv, okeys = chain(X)
+    oq_hv, oq_keys = chain(Q)
+    assert np.array_equal(to_np(db.hv[: db.N]), ohv)
+    assert np.array_equal(to_np(db.keys[: db.N]), okeys)
+    assert np.array_equal(to_np(qh.hv[: qh.N]), oq_hv)
+    cand, ncand, rs = to_np(qb.cand), to_np(qb.ncand), to_np(qb.rsize)
+    for i in range(Q.shape[0]):
+        oc, orr = oracle.probe(okeys, ohv, oq_keys[i], oq_hv[i], P["C"])
+        assert rs[i] == orr and ncand[i] == len(oc), i
+        assert np.array_equal(cand[i, : ncand[i]], oc), i
+    for t in range(3):  # exact copies find themselves first
+        assert cand[P["nq"] + t, 0] == t
+    with pytest.raises(ValueError):
+        db.run(r, method="minhash")
+
+
 @pytest.mark.parametrize("C", [1, 7, 100, 600, 4096])
 def test_probe_large_retrieved_sets_with_ties(ssh, C):
     """|R| far above C, a tie level larger than a part's in-LDS tie buffer, and
