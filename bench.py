@@ -329,7 +329,7 @@ def main():
     hv_int = torch.empty((N, p.H), dtype=torch.uint64, device=dev)
 
     def wmh_index():
-        ssh.wmh_int(db.codes, db.counts, db.hoff, db.ndist, p.H, p.key_seed, out=hv_int)
+        ssh.wmh_int(db.codes, db.counts, db.hoff, db.ndist, p.H, p.wmh_seed, out=hv_int)
 
     wmh_index()
     torch.cuda.synchronize()

@@ -161,7 +161,8 @@ ssh_status ssh_cws_prepare(const ssh_cws_tables* tab, void* stream);
  *     t = floor(ln S_k / r + beta),  ln y = r (t - beta),  ln a = ln c - ln y - r
  * each step one correctly rounded float64 operation in this order, ln S_k
  * correctly rounded.  The sample is k* = argmin_k ln a (ties to the smaller k)
- * with its t*, stored as hv = min(t*, 2^48 - 1) << 16 | k*.  The probability
+ * with its t*, stored as hv = min(t*, 2^47 - 1) << 16 | k* (at most 2^63 - 1,
+ * so never SSH_HV_EMPTY, whatever k* is).  The probability
  * that two sets agree on hv equals their weighted Jaccard similarity
  * (eq. CollProb).
  *   codes, counts, hist_off, n_distinct  as produced by ssh_shingle

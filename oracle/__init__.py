@@ -30,7 +30,6 @@ from .ssh_oracle import (  # noqa: F401
     band_keys,
     wmh_int,
     wmh_int_batch,
-    table_sort_bits,
     build_tables,
     probe,
     band_radius,

@@ -30,7 +30,7 @@ from . import _dtw_c
 U64 = (1 << 64) - 1
 EMPTY = U64            # hash value of a series with no shingle
 KEY_EMPTY = U64        # band key of a series with no shingle
-HV_T_MAX = (1 << 48) - 1
+HV_T_MAX = (1 << 47) - 1  # keeps every hash value below EMPTY, even with k* = 2^16 - 1
 GOLDEN_GAMMA = 0x9E3779B97F4A7C15
 
 
@@ -135,7 +135,11 @@ def ln_table(s_max: int) -> np.ndarray:
 
 
 def hv_encode(kstar: np.ndarray, tstar: np.ndarray) -> np.ndarray:
-    """Pack a sample (k*, t*) into one uint64: min(t*, 2^48 - 1) << 16 | k*."""
+    """Pack a sample (k*, t*) into one uint64: min(t*, 2^47 - 1) << 16 | k*.
+
+    The cap keeps the value at most 2^63 - 1, so a sample never reads as the
+    EMPTY value (2^64 - 1) of a series without shingles, whatever k* is.
+    """
     t = np.minimum(np.asarray(tstar, dtype=np.float64), float(HV_T_MAX)).astype(np.uint64)
     return (t << np.uint64(16)) | np.asarray(kstar, dtype=np.uint64)
 
@@ -250,29 +254,26 @@ def band_keys(hv, K: int, L: int, seed: int) -> np.ndarray:
     return keys
 
 
-def table_sort_bits(N: int) -> int:
-    """Top bits of a key the tables are ordered by: 24 for N <= 2^20, else 32."""
-    return 24 if N <= (1 << 20) else 32
-
-
 def build_tables(keys):
-    """Per table l: every (key, id) pair, ordered by the top B bits of the key
-    (B = table_sort_bits(N)).
+    """The L hash tables of Algorithm 1, each a map from key to bucket.
 
-    The tables only have to let a bucket (the ids of one full key) be found;
-    the order is the library's layout contract.  The order among equal top
-    bits is ascending id.  Returns (tab_keys [L, N] uint64, tab_ids [L, N] uint32).
+    Algorithm 1 inserts every series into every table under its key for that
+    table.  Series are inserted in id order, so a bucket is the ascending list
+    of the ids that share one full key (series without shingles sit in the
+    KEY_EMPTY bucket, which no query key equals).  How a table is laid out in
+    memory is not part of the method.  Returns a list of L dicts
+    {key (int): int64 array of ids, ascending}.
     """
     keys = np.asarray(keys, dtype=np.uint64)
     N, L = keys.shape
-    sh = np.uint64(64 - table_sort_bits(N))
-    tk = np.empty((L, N), np.uint64)
-    ti = np.empty((L, N), np.uint32)
+    tables = []
     for l in range(L):
-        order = np.argsort(keys[:, l] >> sh, kind="stable")
-        tk[l] = keys[order, l]
-        ti[l] = order.astype(np.uint32)
-    return tk, ti
+        col = keys[:, l].tolist()
+        buckets = {}
+        for i in range(N):
+            buckets.setdefault(col[i], []).append(i)
+        tables.append({k: np.asarray(v, dtype=np.int64) for k, v in buckets.items()})
+    return tables
 
 
 # ----------------------------------------------------------------------------

@@ -6,7 +6,8 @@
 //     t    = floor(ln S / r + beta)
 //     ln y = r (t - beta)
 //     ln a = ln c - ln y - r
-// k* = argmin_k ln a (ties to the smaller k), hv = min(t*, 2^48-1) << 16 | k*.
+// k* = argmin_k ln a (ties to the smaller k), hv = min(t*, 2^47-1) << 16 | k*
+// (at most 2^63 - 1, so no hash value equals the empty-series value 2^64 - 1).
 // Every step is one correctly rounded float64 operation, in this order; the
 // library is compiled without floating-point contraction so no step fuses.
 // ln S comes from a table of correctly rounded logarithms prepared once on
@@ -525,7 +526,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void c
           }
         }
       }
-      const double tmax = 281474976710655.0;  // 2^48 - 1
+      const double tmax = 140737488355327.0;  // 2^47 - 1: hv stays below SSH_HV_EMPTY
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         if (lead && (h ? v1 : v0)) {

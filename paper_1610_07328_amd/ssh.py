@@ -232,12 +232,17 @@ def cws(codes, counts, hist_off, n_distinct, tables: CwsTables, out=None):
 
 
 def band_keys(hv: torch.Tensor, K: int, L: int, seed: int, out=None):
+    """Band keys of hash-value rows hv [N, K*L]; returns keys [N, L] (uint64)."""
+    if hv.dim() != 2 or hv.shape[1] != K * L:
+        raise SSHError(f"band_keys: hv must be [N, K*L] = [N, {K * L}], got {tuple(hv.shape)}")
     N = hv.shape[0]
     keys = out if out is not None else torch.empty((max(N, 1), L), dtype=torch.uint64,
                                                    device=hv.device)
+    if keys.numel() < N * L:
+        raise SSHError(f"band_keys: keys holds {keys.numel()} values, needs N*L = {N * L}")
     _check(lib().ssh_band_keys(_dev(hv, torch.uint64, "hv"), N, K, L, seed & ((1 << 64) - 1),
                                _dev(keys, torch.uint64, "keys"), _stream()), "ssh_band_keys")
-    return keys[:N]
+    return keys.view(-1)[: N * L].view(N, L)
 
 
 def cws_band_keys(codes, counts, hist_off, n_distinct, tables: CwsTables, K: int, L: int,

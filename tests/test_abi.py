@@ -138,3 +138,14 @@ def test_workspace_sizes(ssh):
     # the partial rankings of every part of every query, and the runs
     assert ssh.probe_workspace_bytes(1000, 10, 50) >= 1000 * 8 * 50 * 8 + 1000 * 21 * 8
     assert ssh.probe_workspace_bytes(1, 10, 4096) >= 4096 * 8
+
+
+def test_band_keys_binding_checks_shapes(ssh):
+    """band_keys refuses hash values that are not [N, K*L] and a short output
+    before any device call (the C call takes no H)."""
+    import torch
+    hv = torch.zeros((4, 12), dtype=torch.uint64)
+    with pytest.raises(ssh.SSHError, match="K\\*L"):
+        ssh.band_keys(hv, 5, 2, 1)
+    with pytest.raises(ssh.SSHError, match="N\\*L"):
+        ssh.band_keys(hv, 4, 3, 1, out=torch.zeros(11, dtype=torch.uint64))

@@ -81,29 +81,30 @@ def _check_sampled_wmh(ssh, hb: HashBatch, x, off, r, p: Params, sample):
     """Integer-replication MinHash of the whole batch (the benchmark's launch),
     sampled series against the oracle's own sketch, shingle and MinHash."""
     hv = torch.empty((hb.N, p.H), dtype=torch.uint64, device=hb.codes.device)
-    ssh.wmh_int(hb.codes, hb.counts, hb.hoff, hb.ndist, p.H, p.key_seed, out=hv)
+    ssh.wmh_int(hb.codes, hb.counts, hb.hoff, hb.ndist, p.H, p.wmh_seed, out=hv)
     got = _rows(hv, sample)
     del hv
     for i, s in enumerate(sample):
         xs = x[off[s]:off[s + 1]]
         oc, ok = oracle.shingle(oracle.sketch_series(xs, r, p.W, p.delta), p.n)
-        assert np.array_equal(got[i], oracle.wmh_int(oc, ok, p.H, p.key_seed)), s
+        assert np.array_equal(got[i], oracle.wmh_int(oc, ok, p.H, p.wmh_seed)), s
 
 
 def _check_tables(ix: Index, N: int, L: int):
-    """Each table: a permutation of the ids, keys in place, stable by the top
-    table_sort_bits(N) bits."""
+    """Algorithm 1's tables at full size, by properties that fix every bucket:
+    each table holds every id once with its own key, and the entries of one
+    key, read in storage order, have ascending ids (the bucket).  The device's
+    keys are those checked against the oracle on the sampled series."""
     keys = ix.db.keys[:N].view(torch.int64)
-    B = oracle.table_sort_bits(N)
     for l in range(L):
         tk = ix.tab_keys[l, :N].view(torch.int64)
         ti = ix.tab_ids[l, :N].view(torch.int32).to(torch.int64)  # ids < 2^31
-        hi = (tk >> (64 - B)) & ((1 << B) - 1)
-        assert bool((hi[1:] >= hi[:-1]).all()), l
-        eq = hi[1:] == hi[:-1]
-        assert bool((ti[1:][eq] > ti[:-1][eq]).all()), l
         assert torch.equal(torch.sort(ti).values, torch.arange(N, device=ti.device)), l
         assert torch.equal(keys[ti, l], tk), l
+        sk, perm = torch.sort(tk, stable=True)  # groups equal keys, storage order kept
+        sid = ti[perm]
+        same = sk[1:] == sk[:-1]
+        assert bool((sid[1:][same] > sid[:-1][same]).all()), l
 
 
 def _check_probe(qb: QueryBatch, qsel, C: int, H: int):

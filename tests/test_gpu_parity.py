@@ -13,6 +13,7 @@ import torch
 import oracle
 from paper_1610_07328_amd import datagen
 from tests._gpu_helpers import DTW_RTOL, compare_rerank, ragged, to_dev, to_np, unpack_bits
+from tests._tables import assert_tables_match
 
 pytestmark = pytest.mark.gpu
 
@@ -328,6 +329,124 @@ def test_cws_equal_keys_resolved_exactly(ssh):
         assert np.array_equal(hv[s], oracle.cws(c, k, r, lnc, beta, lnS)[2]), s
 
 
+def _tied_draws(n, H, a, b, seed, r0=50.0):
+    """Tokens a and b get identical draw rows with r in [r0, r0 + 1) and
+    beta < 0.8, so t = 0 for every weight w with ln w / r0 < 0.2 and their
+    ln a (= ln c + r beta - r) is bit-identical whatever the weights; their
+    ln c is low enough that the tie is the minimum."""
+    rng = np.random.default_rng(seed)
+    D = 1 << n
+    r = rng.gamma(2.0, 1.0, (D, H))
+    lnc = np.log(rng.gamma(2.0, 1.0, (D, H)))
+    beta = rng.random((D, H))
+    r[a] = r[b] = r0 + rng.random(H)
+    beta[a] = beta[b] = 0.8 * rng.random(H)
+    lnc[a] = lnc[b] = -60.0 + rng.random(H)
+    return r, lnc, beta
+
+
+def _cws_sets_exact(ssh, n, draws, sets, expect_k=None):
+    tabs = ssh.CwsTables(*draws, n)
+    codes = np.concatenate([c for c, _ in sets]).astype(np.uint32)
+    counts = np.concatenate([k for _, k in sets]).astype(np.uint32)
+    ho = np.zeros(len(sets) + 1, np.int64)
+    np.cumsum([len(c) for c, _ in sets], out=ho[1:])
+    nd = np.array([len(c) for c, _ in sets], np.int32)
+    hv = to_np(ssh.cws(to_dev(codes), to_dev(counts), to_dev(ho), to_dev(nd), tabs))
+    torch.cuda.synchronize()
+    ssh.check_device_errors()
+    lnS = oracle.ln_table(max(2, int(counts.max())))
+    checked = {}
+    for s, (c, k) in enumerate(sets):
+        key = (c.tobytes(), k.tobytes())
+        if key not in checked:
+            kk, _, want = oracle.cws(c, k, *draws, lnS)
+            if expect_k is not None:
+                assert np.all(kk == expect_k), s  # the tie is the minimum: the smaller token
+            checked[key] = want
+        assert np.array_equal(hv[s], checked[key]), s
+
+
+@pytest.mark.parametrize("split", [True, False])
+def test_cws_exact_ties_go_to_the_smaller_token(ssh, split):
+    """Two tokens with bit-identical ln a at the minimum, the smaller one wins:
+    both keyed (pass A: equal keys, exact re-scan), keyed against heavy in
+    either order (pass B's (ln a, k) comparison), and the two run codes at
+    counts up to 4096 (keyed by their run rows).  split: fewer than 4,096
+    series (a workgroup per series), else one wave per series."""
+    _announce(f"cws exact ties split={split}")
+    n, H, a, b = 6, 130, 9, 41
+    rng = np.random.default_rng(31)
+    weights = [(1, 1), (2, 2), (7, 3), (1, 10), (10, 1), (20, 100), (8, 8), (1, 7), (7, 8)]
+    base = []
+    for wa, wb in weights:
+        others = rng.choice([c for c in range(1 << n) if c not in (a, b)], size=12, replace=False)
+        c = np.array(sorted([a, b, *others.tolist()]), np.uint32)
+        k = rng.integers(1, 12, size=len(c)).astype(np.uint32)
+        k[c == a], k[c == b] = wa, wb
+        base.append((c, k))
+    reps = 1 if split else 4200 // len(base) + 1
+    _cws_sets_exact(ssh, n, _tied_draws(n, H, a, b, seed=32), base * reps, expect_k=a)
+    # the run codes 0 and 2^n - 1, keyed up to 4096 (r ~ 100 keeps t = 0 there)
+    z, o = 0, (1 << n) - 1
+    runs = []
+    for wa, wb in [(300, 4096), (4096, 300), (4000, 4000), (1, 4096)]:
+        c = np.array([z, 5, 17, o], np.uint32)
+        runs.append((c, np.array([wa, 2, 1, wb], np.uint32)))
+    _cws_sets_exact(ssh, n, _tied_draws(n, H, z, o, seed=33, r0=100.0),
+                    runs * (1 if split else 4200 // len(runs) + 1), expect_k=z)
+
+
+def test_cws_exact_ties_with_many_distinct_tokens(ssh):
+    """n = 16: a set of all 65,536 codes takes the plain exact scan (more
+    tokens than 16-bit positions), one of 65,535 the keyed passes; a tied
+    pair at the minimum goes to the smaller token in both."""
+    _announce("cws exact ties, 65,535 and 65,536 distinct tokens")
+    n, H, a, b = 16, 4, 1000, 60000
+    draws = _tied_draws(n, H, a, b, seed=34)
+    allc = np.arange(1 << n, dtype=np.uint32)
+    rng = np.random.default_rng(35)
+    w = rng.integers(1, 9, size=1 << n).astype(np.uint32)
+    w[a], w[b] = 1, 10
+    drop = np.ones(1 << n, bool)
+    drop[777] = False
+    sets = [(allc, w), (allc[drop], w[drop])]
+    _cws_sets_exact(ssh, n, draws, sets, expect_k=a)
+
+
+def test_cws_saturated_t_is_not_the_empty_value(ssh):
+    """n = 16, token 2^16 - 1 wins with a tiny r: t saturates at 2^47 - 1 and
+    the hash value and band keys stay distinct from the empty values."""
+    _announce("cws saturated t")
+    n, H = 16, 3
+    D = 1 << n
+    r = np.full((D, H), 1.0)
+    lnc = np.zeros((D, H))
+    beta = np.full((D, H), 0.5)
+    k = D - 1
+    r[k] = 1e-15
+    lnc[k] = -100.0
+    tabs = ssh.CwsTables(r, lnc, beta, n)
+    sets = [(np.array([5, k], np.uint32), np.array([1, 2], np.uint32)),
+            (np.array([k], np.uint32), np.array([3], np.uint32))]
+    codes = np.concatenate([c for c, _ in sets])
+    counts = np.concatenate([c for _, c in sets])
+    ho = np.array([0, 2, 3], np.int64)
+    nd = np.array([2, 1], np.int32)
+    hv, keys = ssh.cws_band_keys(to_dev(codes), to_dev(counts), to_dev(ho), to_dev(nd), tabs,
+                                 1, H, 3)
+    torch.cuda.synchronize()
+    ssh.check_device_errors()
+    hv, keys = to_np(hv), to_np(keys)
+    lnS = oracle.ln_table(4)
+    for s, (c, kk) in enumerate(sets):
+        want = oracle.cws(c, kk, r, lnc, beta, lnS)[2]
+        assert np.array_equal(hv[s], want)
+        assert np.all(want == np.uint64(((1 << 47) - 1) << 16 | k))
+        assert np.array_equal(keys[s], oracle.band_keys(want[None, :], 1, H, 3)[0])
+        assert not np.any(keys[s] == np.uint64(oracle.KEY_EMPTY))
+
+
 def test_cws_counts_beyond_table(ssh):
     _announce("cws counts beyond the ln table")
     rng = np.random.default_rng(4)
@@ -505,8 +624,8 @@ def test_c1_hash_values_and_keys_exact(ssh, c1):
                                           (3000, 65, 40), (1 << 20, 2, 300),
                                           ((1 << 20) + 1, 2, 300)])
 def test_table_build_exact(ssh, N, L, distinct):
-    """Tables sorted on the top 24 bits (three passes, N <= 2^20) or 32 bits (four),
-    table-major or, for L > 64, straight from the series-major keys."""
+    """Every bucket of Algorithm 1 read back from the device tables (three radix
+    passes for N <= 2^20, four above; L > 64 straight from the series-major keys)."""
     _announce(f"table build N={N} L={L}")
     rng = np.random.default_rng(N)
     if distinct is None:
@@ -518,9 +637,7 @@ def test_table_build_exact(ssh, N, L, distinct):
     keys[3] = np.uint64(oracle.KEY_EMPTY)
     tk, ti = ssh.table_build(to_dev(keys))
     torch.cuda.synchronize()
-    otk, oti = oracle.build_tables(keys)
-    assert np.array_equal(to_np(tk), otk)
-    assert np.array_equal(to_np(ti), oti)
+    assert_tables_match(to_np(tk), to_np(ti), keys, oracle.build_tables(keys))
     if N > 1 << 20:  # the probe's search over the 32-bit order, against the brute-force oracle
         hv = rng.integers(0, 4, size=(N, 6), dtype=np.int64).astype(np.uint64)
         qs = [0, 1, 5, N - 1]

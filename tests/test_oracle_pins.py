@@ -281,6 +281,73 @@ def test_cws_log_form_matches_product_form(draws):
     assert disagree <= total * 1e-3
 
 
+def _tied_draws(n, H, a, b, seed):
+    """Draws in which tokens a and b have identical rows, r in [50, 51) and
+    beta < 0.9, so that t = floor(ln S / r + beta) = 0 for every weight up to
+    100 and ln a = ln c + r beta - r is the same for both whatever their
+    weights; their ln c is so low that the tied value is the minimum."""
+    rng = np.random.default_rng(seed)
+    D = 1 << n
+    r = rng.gamma(2.0, 1.0, (D, H))
+    lnc = np.log(rng.gamma(2.0, 1.0, (D, H)))
+    beta = rng.random((D, H))
+    r[a] = r[b] = 50.0 + rng.random(H)
+    beta[a] = beta[b] = 0.9 * rng.random(H)
+    lnc[a] = lnc[b] = -60.0 + rng.random(H)
+    return r, lnc, beta
+
+
+def test_cws_exact_tie_goes_to_the_smaller_token():
+    """Reading: equal ln a resolves to the smaller token (first minimum in
+    ascending token order), whatever the two weights."""
+    n, H, a, b = 6, 48, 9, 41
+    r, lnc, beta = _tied_draws(n, H, a, b, seed=21)
+    lnS = oracle.ln_table(100)
+    for wa, wb in [(1, 1), (1, 10), (10, 1), (37, 100), (2, 2)]:
+        codes = np.array([3, a, 20, b, 50], np.uint32)
+        counts = np.array([4, wa, 1, wb, 7], np.uint32)
+        k, t, hv = oracle.cws(codes, counts, r, lnc, beta, lnS)
+        # it is a real tie: both tokens give bit-identical ln a
+        for w, c in ((wa, a), (wb, b)):
+            tt = np.floor(lnS[w] / r[c] + beta[c])
+            assert np.all(tt == 0)
+        la_a = (lnc[a] - r[a] * (0 - beta[a])) - r[a]
+        la_b = (lnc[b] - r[b] * (0 - beta[b])) - r[b]
+        assert np.array_equal(la_a, la_b)
+        assert np.all(k == a), (wa, wb)
+        assert np.all(t == 0)
+        assert np.array_equal(hv, oracle.hv_encode(np.full(H, a), np.zeros(H)))
+    # without the tied partner the winner is still a (the tie is at the minimum)
+    k1, _, _ = oracle.cws(np.array([3, a, 50], np.uint32), np.array([4, 1, 7], np.uint32),
+                          r, lnc, beta, lnS)
+    k2, _, _ = oracle.cws(np.array([3, b, 50], np.uint32), np.array([4, 1, 7], np.uint32),
+                          r, lnc, beta, lnS)
+    assert np.all(k1 == a) and np.all(k2 == b)
+
+
+def test_cws_saturated_t_is_not_the_empty_value():
+    """With n = 16 the token 2^16 - 1 fills the low 16 bits of hv.  A tiny r
+    makes t = floor(ln S / r + beta) exceed 2^47; the stored t saturates at
+    2^47 - 1, so hv stays below the EMPTY value and the band keys are real."""
+    n, H = 16, 3
+    D = 1 << n
+    r = np.full((D, H), 1.0)
+    lnc = np.zeros((D, H))
+    beta = np.full((D, H), 0.5)
+    k = D - 1
+    r[k] = 1e-15          # ln 2 / 1e-15 = 6.9e14 > 2^47 = 1.4e14
+    lnc[k] = -100.0       # the winner
+    lnS = oracle.ln_table(4)
+    codes = np.array([5, k], np.uint32)
+    counts = np.array([1, 2], np.uint32)
+    kk, t, hv = oracle.cws(codes, counts, r, lnc, beta, lnS)
+    assert np.all(kk == k) and np.all(t > 2.0 ** 47)
+    assert np.all(hv == np.uint64(((1 << 47) - 1) << 16 | k))
+    assert np.all(hv < np.uint64(oracle.EMPTY))
+    keys = oracle.band_keys(hv[None, :], 1, H, seed=3)
+    assert not np.any(keys == np.uint64(oracle.KEY_EMPTY))
+
+
 def test_cws_empty_set(draws):
     k, t, hv = _cws(draws, np.zeros(64, np.int64))
     assert np.all(hv == np.uint64(oracle.EMPTY))
@@ -326,16 +393,52 @@ def _tiny_index(seed=12, N=60, L=3, H=6):
     return keys, hv
 
 
-def test_tables_are_stable_order_by_top_bits():
+def test_tables_hold_every_series_in_its_bucket():
+    """Algorithm 1: every series is inserted into every table under its key."""
     keys, _ = _tiny_index()
-    tk, ti = oracle.build_tables(keys)
+    tabs = oracle.build_tables(keys)
     N, L = keys.shape
-    assert oracle.table_sort_bits(N) == 24 and oracle.table_sort_bits(1 << 20) == 24
-    assert oracle.table_sort_bits((1 << 20) + 1) == 32
+    assert len(tabs) == L
     for l in range(L):
-        want = sorted(range(N), key=lambda i: (int(keys[i, l]) >> 40, i))
-        assert ti[l].tolist() == want
-        assert tk[l].tolist() == [int(keys[i, l]) for i in want]
+        seen = np.concatenate(list(tabs[l].values()))
+        assert np.array_equal(np.sort(seen), np.arange(N))          # each id once
+        assert set(tabs[l]) == set(keys[:, l].tolist())             # one bucket per key
+        for k, ids in tabs[l].items():
+            assert np.array_equal(ids, np.nonzero(keys[:, l] == np.uint64(k))[0])
+    # the union of a query's buckets is the brute-force retrieved set
+    for qi in (0, 11, 59):
+        R = set()
+        for l in range(L):
+            R.update(tabs[l].get(int(keys[qi, l]), np.zeros(0, np.int64)).tolist())
+        assert len(R) == oracle.probe(keys, _tiny_index()[1], keys[qi], _tiny_index()[1][qi], 60)[1]
+
+
+def test_layout_buckets_helper():
+    """The test helper that reads buckets from a (tab_keys, tab_ids) layout
+    accepts any layout whose per-key storage order is ascending and rejects one
+    that is not."""
+    from tests._tables import assert_tables_match
+    keys, _ = _tiny_index()
+    tabs = oracle.build_tables(keys)
+    N, L = keys.shape
+    rng = np.random.default_rng(5)
+    tk = np.empty((L, N), np.uint64)
+    ti = np.empty((L, N), np.uint32)
+    for l in range(L):
+        # any grouping of the buckets, ids ascending within each: here buckets
+        # in a random order, concatenated
+        ks = list(tabs[l])
+        rng.shuffle(ks)
+        ids = np.concatenate([tabs[l][k] for k in ks])
+        ti[l] = ids
+        tk[l] = keys[ids, l]
+    assert_tables_match(tk, ti, keys, tabs)
+    bad = ti.copy()
+    big = max(tabs[0].values(), key=len)
+    pos = np.nonzero(np.isin(bad[0], big))[0]
+    bad[0, pos[0]], bad[0, pos[1]] = bad[0, pos[1]], bad[0, pos[0]]  # two ids of one bucket
+    with pytest.raises(AssertionError):
+        assert_tables_match(tk, bad, keys, tabs)
 
 
 def test_probe_brute_force():
