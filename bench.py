@@ -205,7 +205,7 @@ def main():
         mark(5)
         qry.probe()
         mark(6)
-        qry.rerank(m, m)
+        qry.rerank()
         mark(7)
 
     for _ in range(args.warmup):
@@ -285,7 +285,7 @@ def main():
                 torch.empty((nq, p.k), dtype=torch.float32, device=dev))
 
     def full_rerank():
-        ssh.dtw_rerank(qb.x, qb.x_off, db.x, db.x_off, cand_full, ncand_full, p.band_frac, m, m,
+        ssh.dtw_rerank(qb.x, qb.x_off, db.x, db.x_off, cand_full, ncand_full, p.band_frac,
                        p.k, ws=ws_full, out=out_full)
 
     full_rerank()
@@ -304,12 +304,12 @@ def main():
                 "alu_frac": full_cells * 3 / t_full / VALU_LANE_OPS}
 
     # the same batch through the LB_Keogh-pruned re-rank (same results, less work)
-    ws_lb = torch.empty(max(ssh.rerank_lb_workspace_bytes(nq, p.C, m), 1), dtype=torch.uint8,
+    ws_lb = torch.empty(max(ssh.rerank_lb_workspace_bytes(nq, p.C, qb.x.numel()), 1), dtype=torch.uint8,
                         device=dev)
     out_lb = (torch.empty_like(out_full[0]), torch.empty_like(out_full[1]))
 
     def full_rerank_lb():
-        ssh.dtw_rerank(qb.x, qb.x_off, db.x, db.x_off, cand_full, ncand_full, p.band_frac, m, m,
+        ssh.dtw_rerank(qb.x, qb.x_off, db.x, db.x_off, cand_full, ncand_full, p.band_frac,
                        p.k, ws=ws_lb, out=out_lb, prune=True)
 
     full_rerank_lb()
@@ -360,7 +360,7 @@ def main():
             e0.record()
             hb.run(r, tables)
             qq.probe()
-            qq.rerank(m, m)
+            qq.rerank()
             e1.record()
             e1.synchronize()
             lat.append(e0.elapsed_time(e1))

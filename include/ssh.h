@@ -64,7 +64,7 @@ typedef int32_t ssh_status;
 #define SSH_CWS_RUN_CAP 4096     /* counts keyed for the codes 0 and 2^n-1  */
 #define SSH_MAX_C 4096           /* largest candidate cap of ssh_probe      */
 #define SSH_MAX_K 1024           /* largest k of dtw_rerank                 */
-#define SSH_MAX_BAND 255         /* largest Sakoe-Chiba radius of dtw_rerank */
+#define SSH_MAX_BAND 255         /* largest Sakoe-Chiba radius of a dtw_rerank pair */
 
 /* [host] Name of a status code, and the detail of the last error raised on the
  * calling thread ("" if none).  Both strings are owned by the library. */
@@ -253,49 +253,62 @@ ssh_status ssh_probe(const uint64_t* tab_keys, const uint32_t* tab_ids, int64_t 
                      int64_t* cand, int32_t* ncand, int64_t* r_size, void* ws, size_t ws_bytes,
                      void* stream);
 
-/* [host] Workspace bytes needed by dtw_rerank. */
+/* [host] Workspace bytes needed by dtw_rerank for nq queries of C candidates. */
 size_t ssh_rerank_workspace_bytes(int32_t nq, int32_t C);
 
 /* DTW re-rank (Section 2.1; last step of Algorithm 2).  For each query q and
  * each of its ncand[q] candidates X = cand[q*C + c], the banded DTW distance:
  * cost (q_i - x_j)^2, steps (1,0), (0,1), (1,1) from (0,0) to (lq-1, lx-1),
- * Sakoe-Chiba band |i - j| <= floor(band_frac * max(lq, lx)), distance = sqrt
- * of the least total cost (+inf when |lq - lx| exceeds the band).  Accumulated
- * in float32.  The k nearest by (distance, id) are returned.
- *   q, q_off     float32 query values and int64 [nq+1] offsets
- *   db, db_off   float32 series values and int64 [N+1] offsets; N series
- *   cand, ncand  from ssh_probe (C columns)
- *   band_frac    in [0, 1]; the radius must not exceed SSH_MAX_BAND
- *   q_len, db_len  [host] the common query length and candidate length of the
- *                batch (every query and every series must have them)
- *   k            1..SSH_MAX_K, k <= C
+ * Sakoe-Chiba band |i - j| <= r with r = floor(band_frac * max(lq, lx)) taken
+ * per pair from that pair's own lengths, distance = sqrt of the least total
+ * cost (+inf when |lq - lx| > r or a length is 0).  Accumulated in float32.
+ * Queries and candidates may all have different lengths.  The k nearest by
+ * (distance, id) are returned.
+ *   q, q_off     float32 query values and int64 [nq+1] offsets (ragged)
+ *   db, db_off   float32 series values and int64 [N+1] offsets (ragged); N series
+ *   cand, ncand  from ssh_probe (C columns); ids must lie in [0, N)
+ *   band_frac    in [0, 1]; a pair whose radius exceeds SSH_MAX_BAND gets +inf
+ *                and raises a device flag (ssh_check_device_errors)
+ *   k            1..SSH_MAX_K, k <= C; nq * C must stay below 2^31
  *   out_id       int64 [nq * k] output, -1 padding
  *   out_dist     float32 [nq * k] output, +inf padding
- *   ws, ws_bytes at least ssh_rerank_workspace_bytes(nq, C) */
+ *   ws, ws_bytes at least ssh_rerank_workspace_bytes(nq, C); on return (after
+ *                the stream is synchronised) its first nq * C float32 values
+ *                are every pair's distance, [q][c], +inf past ncand[q]
+ * An invalid candidate id raises a device flag and gets +inf. */
 ssh_status dtw_rerank(const float* q, const int64_t* q_off, int32_t nq, const float* db,
                       const int64_t* db_off, int64_t N, const int64_t* cand, const int32_t* ncand,
-                      int32_t C, float band_frac, int64_t q_len, int64_t db_len, int32_t k,
-                      int64_t* out_id, float* out_dist, void* ws, size_t ws_bytes, void* stream);
+                      int32_t C, float band_frac, int32_t k, int64_t* out_id, float* out_dist,
+                      void* ws, size_t ws_bytes, void* stream);
 
-/* [host] Workspace bytes needed by dtw_rerank_lb (db_len: the candidate length). */
-size_t ssh_rerank_lb_workspace_bytes(int32_t nq, int32_t C, int64_t db_len);
+/* [host] Workspace bytes needed by dtw_rerank_lb; q_values = q_off[nq], the
+ * number of query values of the batch. */
+size_t ssh_rerank_lb_workspace_bytes(int32_t nq, int32_t C, int64_t q_values);
 
-/* dtw_rerank with lower-bound pruning (Section 2.1: DTW is costly, so cheap
- * lower bounds discard candidates first).  Same arguments and the same
- * outputs, bit for bit, as dtw_rerank; only the work differs.  Each candidate
- * gets its LB_Keogh bound (squared distance of x_j to the envelope of the
- * query values it may be aligned with); each query's k candidates of smallest
- * bound are computed first, and a candidate whose bound exceeds the largest of
- * their squared distances, times a factor covering every float32 rounding
- * (about 1 + (q_len + 2 db_len) 2^-23), is not computed: its distance is above
- * the k-th best.  Pays off when many candidates are far from the query; the
- * two dependent DTW passes make it slower on small batches.
- *   ws, ws_bytes at least ssh_rerank_lb_workspace_bytes(nq, C, db_len) */
+/* dtw_rerank with lower-bound pruning and early abandoning (Section 2.1: DTW
+ * is costly, so cheap lower bounds discard candidates first).  Same arguments
+ * and the same outputs, bit for bit, as dtw_rerank; only the work differs.
+ * Each candidate gets a bound on its squared distance: LB_Kim (first and last
+ * cells, which every warping path visits) and, when the candidate is not
+ * longer than the query, LB_Keogh (squared distance of x_j to the envelope of
+ * the query values it may be aligned with).  Each query's k candidates of
+ * smallest bound are computed first; tau, the largest of their distances,
+ * bounds the k-th best.  A candidate whose bound exceeds tau^2 times a factor
+ * covering every float32 rounding (about 1 + (lq + 2 lx) 2^-23) is not
+ * computed, and the DTW of the others stops as soon as every cell of a row
+ * front exceeds that cut: either way its distance is above the k-th best.
+ * Pays off when many candidates are far from the query; the two dependent DTW
+ * passes make it slower on small batches.
+ *   ws, ws_bytes at least ssh_rerank_lb_workspace_bytes(nq, C, q_off[nq]); a
+ *                smaller workspace that still holds the fixed part leaves the
+ *                queries past its envelope capacity with LB_Kim alone and
+ *                raises a device flag.  The distances of skipped or abandoned
+ *                candidates in the workspace are +inf. */
 ssh_status dtw_rerank_lb(const float* q, const int64_t* q_off, int32_t nq, const float* db,
                          const int64_t* db_off, int64_t N, const int64_t* cand,
-                         const int32_t* ncand, int32_t C, float band_frac, int64_t q_len,
-                         int64_t db_len, int32_t k, int64_t* out_id, float* out_dist, void* ws,
-                         size_t ws_bytes, void* stream);
+                         const int32_t* ncand, int32_t C, float band_frac, int32_t k,
+                         int64_t* out_id, float* out_dist, void* ws, size_t ws_bytes,
+                         void* stream);
 
 /* Same contract as ssh_sketch, always through the kernel that handles any W
  * and delta (ssh_sketch picks a register-blocked kernel for the filter shapes
@@ -307,9 +320,9 @@ ssh_status ssh_sketch_generic(const float* x, const int64_t* x_off, int64_t N, c
 
 /* [host] Synchronise the device and collect the error flags that kernels raise
  * for inconsistent device-side arguments since the last call (offsets whose
- * capacity is too small, candidate ids outside [0, N), lengths that differ from
- * dtw_rerank's q_len / db_len, CWS draws outside their ranges).  The flags are
- * cleared.  Returns SSH_OK when none was raised, else SSH_EINVAL with the
+ * capacity is too small, candidate ids outside [0, N), a DTW band radius above
+ * SSH_MAX_BAND, an undersized pruned re-rank workspace, CWS draws outside their
+ * ranges).  The flags are cleared.  Returns SSH_OK when none was raised, else SSH_EINVAL with the
  * detail in ssh_last_error(). */
 ssh_status ssh_check_device_errors(void);
 

@@ -45,17 +45,15 @@ ssh_status probe_launch(const uint64_t* tab_keys, const uint32_t* tab_ids, int64
                         hipStream_t stream);
 size_t probe_workspace_bytes(int nq, int L, int C);
 size_t rerank_workspace_bytes(int nq, int C);
-size_t rerank_lb_workspace_bytes(int nq, int C, int64_t lx);
+size_t rerank_lb_workspace_bytes(int nq, int C, int64_t q_values);
 ssh_status rerank_lb_launch(const float* q, const int64_t* q_off, int nq, const float* db,
                             const int64_t* db_off, int64_t Ndb, const int64_t* cand,
-                            const int32_t* ncand, int C, float band_frac, int64_t q_len,
-                            int64_t db_len, int k, int64_t* out_id, float* out_dist, void* ws,
-                            size_t ws_bytes, hipStream_t stream);
+                            const int32_t* ncand, int C, float band_frac, int k, int64_t* out_id,
+                            float* out_dist, void* ws, size_t ws_bytes, hipStream_t stream);
 ssh_status rerank_launch(const float* q, const int64_t* q_off, int nq, const float* db,
                          const int64_t* db_off, int64_t Ndb, const int64_t* cand,
-                         const int32_t* ncand, int C, float band_frac, int64_t q_len,
-                         int64_t db_len, int k, int64_t* out_id, float* out_dist, void* ws,
-                         size_t ws_bytes, hipStream_t stream);
+                         const int32_t* ncand, int C, float band_frac, int k, int64_t* out_id,
+                         float* out_dist, void* ws, size_t ws_bytes, hipStream_t stream);
 
 ssh_status wmh_int_launch(const uint32_t* codes, const uint32_t* counts, const int64_t* hist_off,
                           const int32_t* n_distinct, int64_t N, int H, uint64_t seed, uint64_t* hv,
@@ -268,42 +266,38 @@ size_t ssh_rerank_workspace_bytes(int32_t nq, int32_t C) {
 
 ssh_status dtw_rerank(const float* q, const int64_t* q_off, int32_t nq, const float* db,
                       const int64_t* db_off, int64_t N, const int64_t* cand, const int32_t* ncand,
-                      int32_t C, float band_frac, int64_t q_len, int64_t db_len, int32_t k,
-                      int64_t* out_id, float* out_dist, void* ws, size_t ws_bytes, void* stream) {
+                      int32_t C, float band_frac, int32_t k, int64_t* out_id, float* out_dist,
+                      void* ws, size_t ws_bytes, void* stream) {
   SSH_REQUIRE(nq >= 0 && N >= 0, "dtw_rerank: nq or N < 0");
   SSH_REQUIRE(C >= 1 && C <= SSH_MAX_C, "dtw_rerank: C out of [1, SSH_MAX_C]");
   SSH_REQUIRE(k >= 1 && k <= SSH_MAX_K && k <= C, "dtw_rerank: k out of [1, min(C, SSH_MAX_K)]");
   SSH_REQUIRE(band_frac >= 0.0f && band_frac <= 1.0f, "dtw_rerank: band_frac out of [0, 1]");
-  SSH_REQUIRE(q_len >= 1 && q_len <= (1 << 30) && db_len >= 1 && db_len <= (1 << 30),
-              "dtw_rerank: lengths out of range");
   if (nq == 0) return SSH_OK;
   SSH_REQUIRE(q && q_off && cand && ncand && out_id && out_dist && ws, "dtw_rerank: null pointer");
   SSH_REQUIRE(N == 0 || (db && db_off), "dtw_rerank: null series pointer");
-  return rerank_launch(q, q_off, nq, db, db_off, N, cand, ncand, C, band_frac, q_len, db_len, k,
-                       out_id, out_dist, ws, ws_bytes, as_stream(stream));
+  return rerank_launch(q, q_off, nq, db, db_off, N, cand, ncand, C, band_frac, k, out_id, out_dist,
+                       ws, ws_bytes, as_stream(stream));
 }
 
-size_t ssh_rerank_lb_workspace_bytes(int32_t nq, int32_t C, int64_t db_len) {
-  if (nq < 0 || C < 1 || db_len < 1) return 0;
-  return rerank_lb_workspace_bytes(nq, C, db_len);
+size_t ssh_rerank_lb_workspace_bytes(int32_t nq, int32_t C, int64_t q_values) {
+  if (nq < 0 || C < 1 || q_values < 0) return 0;
+  return rerank_lb_workspace_bytes(nq, C, q_values);
 }
 
 ssh_status dtw_rerank_lb(const float* q, const int64_t* q_off, int32_t nq, const float* db,
                          const int64_t* db_off, int64_t N, const int64_t* cand,
-                         const int32_t* ncand, int32_t C, float band_frac, int64_t q_len,
-                         int64_t db_len, int32_t k, int64_t* out_id, float* out_dist, void* ws,
-                         size_t ws_bytes, void* stream) {
+                         const int32_t* ncand, int32_t C, float band_frac, int32_t k,
+                         int64_t* out_id, float* out_dist, void* ws, size_t ws_bytes,
+                         void* stream) {
   SSH_REQUIRE(nq >= 0 && N >= 0, "dtw_rerank_lb: nq or N < 0");
   SSH_REQUIRE(C >= 1 && C <= SSH_MAX_C, "dtw_rerank_lb: C out of [1, SSH_MAX_C]");
   SSH_REQUIRE(k >= 1 && k <= SSH_MAX_K && k <= C, "dtw_rerank_lb: k out of [1, min(C, SSH_MAX_K)]");
   SSH_REQUIRE(band_frac >= 0.0f && band_frac <= 1.0f, "dtw_rerank_lb: band_frac out of [0, 1]");
-  SSH_REQUIRE(q_len >= 1 && q_len <= (1 << 30) && db_len >= 1 && db_len <= (1 << 30),
-              "dtw_rerank_lb: lengths out of range");
   if (nq == 0) return SSH_OK;
   SSH_REQUIRE(q && q_off && cand && ncand && out_id && out_dist && ws, "dtw_rerank_lb: null pointer");
   SSH_REQUIRE(N == 0 || (db && db_off), "dtw_rerank_lb: null series pointer");
-  return rerank_lb_launch(q, q_off, nq, db, db_off, N, cand, ncand, C, band_frac, q_len, db_len, k,
-                          out_id, out_dist, ws, ws_bytes, as_stream(stream));
+  return rerank_lb_launch(q, q_off, nq, db, db_off, N, cand, ncand, C, band_frac, k, out_id,
+                          out_dist, ws, ws_bytes, as_stream(stream));
 }
 
 ssh_status ssh_check_device_errors(void) {
@@ -315,7 +309,10 @@ ssh_status ssh_check_device_errors(void) {
   if (b) msg += "ssh_shingle: hist_off or bit_word_off capacity too small; ";
   if (c & 2) msg += "ssh_cws_prepare: a draw is outside its range (0 < r < 1e5, beta in [0,1), finite ln c); ";
   if (c & 4) msg += "ssh_cws: internal error, a minimum pointed past the token list; ";
-  if (d) msg += "dtw_rerank: candidate id outside [0, N) or a length differs from q_len/db_len; ";
+  if (d & 1) msg += "dtw_rerank: candidate id outside [0, N); ";
+  if (d & 2) msg += "dtw_rerank: a pair's band radius is above SSH_MAX_BAND (its distance is +inf); ";
+  if (d & 4) msg += "dtw_rerank: a series or query length is negative or above 2^30; ";
+  if (d & 8) msg += "dtw_rerank_lb: workspace holds fewer query values than q_off[nq] (bounds fell back to LB_Kim); ";
   if (!msg.empty()) return fail(SSH_EINVAL, msg);
   return SSH_OK;
 }

@@ -142,7 +142,7 @@ class QueryBatch:
         ssh.probe(ix.tab_keys[:, :N], ix.tab_ids[:, :N], db.keys[:N], db.hv[:N], q.keys[: q.N],
                   q.hv[: q.N], q.p.C, out=(self.cand, self.ncand, self.rsize), ws=self.pws)
 
-    def rerank(self, q_len: int, db_len: int):
+    def rerank(self):
         db, q = self.index.db, self.qh
         ssh.dtw_rerank(q.x, q.x_off, db.x, db.x_off, self.cand[: q.N], self.ncand[: q.N],
-                       q.p.band_frac, q_len, db_len, q.p.k, ws=self.ws, out=(self.ids, self.dist))
+                       q.p.band_frac, q.p.k, ws=self.ws, out=(self.ids, self.dist))

@@ -65,11 +65,11 @@ SIGNATURES = {
     "ssh_probe": (_i32, [_vp, _vp, _i64, _i32, _vp, _vp, _i32, _vp, _vp, _i32, _i32, _vp, _vp,
                          _vp, _vp, _sz, _vp]),
     "ssh_rerank_workspace_bytes": (_sz, [_i32, _i32]),
-    "dtw_rerank": (_i32, [_vp, _vp, _i32, _vp, _vp, _i64, _vp, _vp, _i32, _f32, _i64, _i64,
-                          _i32, _vp, _vp, _vp, _sz, _vp]),
+    "dtw_rerank": (_i32, [_vp, _vp, _i32, _vp, _vp, _i64, _vp, _vp, _i32, _f32, _i32, _vp,
+                          _vp, _vp, _sz, _vp]),
     "ssh_rerank_lb_workspace_bytes": (_sz, [_i32, _i32, _i64]),
-    "dtw_rerank_lb": (_i32, [_vp, _vp, _i32, _vp, _vp, _i64, _vp, _vp, _i32, _f32, _i64, _i64,
-                             _i32, _vp, _vp, _vp, _sz, _vp]),
+    "dtw_rerank_lb": (_i32, [_vp, _vp, _i32, _vp, _vp, _i64, _vp, _vp, _i32, _f32, _i32, _vp,
+                             _vp, _vp, _sz, _vp]),
     "ssh_check_device_errors": (_i32, []),
 }
 
@@ -334,14 +334,19 @@ def rerank_workspace_bytes(nq: int, C: int) -> int:
     return int(lib().ssh_rerank_workspace_bytes(nq, C))
 
 
-def rerank_lb_workspace_bytes(nq: int, C: int, db_len: int) -> int:
-    return int(lib().ssh_rerank_lb_workspace_bytes(nq, C, db_len))
+def rerank_lb_workspace_bytes(nq: int, C: int, q_values: int) -> int:
+    """Workspace of the pruned re-rank; q_values = q_off[nq] (query values of the batch)."""
+    return int(lib().ssh_rerank_lb_workspace_bytes(nq, C, q_values))
 
 
-def dtw_rerank(q, q_off, db, db_off, cand, ncand, band_frac: float, q_len: int, db_len: int,
-               k: int, ws: torch.Tensor | None = None, out=None, prune: bool = False):
-    """Returns (ids int64 [nq, k], dist float32 [nq, k]).  With prune, the same
-    results through dtw_rerank_lb (LB_Keogh bounds skip far candidates)."""
+def dtw_rerank(q, q_off, db, db_off, cand, ncand, band_frac: float, k: int,
+               ws: torch.Tensor | None = None, out=None, prune: bool = False):
+    """Returns (ids int64 [nq, k], dist float32 [nq, k]).  Queries and series
+    may have any lengths (CSR offsets); each pair's band radius is
+    floor(band_frac * max(lq, lx)).  With prune, the same results through
+    dtw_rerank_lb (lower bounds and early abandoning skip far candidates).
+    A caller-supplied ws keeps every pair's distance in its first nq*C float32
+    values (see pair_distances)."""
     nq, C = cand.shape
     N = db_off.numel() - 1
     dev = q.device
@@ -351,13 +356,19 @@ def dtw_rerank(q, q_off, db, db_off, cand, ncand, band_frac: float, q_len: int, 
     else:
         oid, od = out
     if ws is None:
-        nws = rerank_lb_workspace_bytes(nq, C, db_len) if prune else rerank_workspace_bytes(nq, C)
+        nws = rerank_lb_workspace_bytes(nq, C, q.numel()) if prune else \
+            rerank_workspace_bytes(nq, C)
         ws = torch.empty(max(nws, 1), dtype=torch.uint8, device=dev)
     fn = lib().dtw_rerank_lb if prune else lib().dtw_rerank
     _check(fn(_dev(q, torch.float32, "q"), _dev(q_off, torch.int64, "q_off"), nq,
               _dev(db, torch.float32, "db"), _dev(db_off, torch.int64, "db_off"), N,
               _dev(cand, torch.int64, "cand"), _dev(ncand, torch.int32, "ncand"), C,
-              float(band_frac), q_len, db_len, k, _dev(oid, torch.int64, "out_id"),
+              float(band_frac), k, _dev(oid, torch.int64, "out_id"),
               _dev(od, torch.float32, "out_dist"), _dev(ws, torch.uint8, "ws"), ws.numel(),
               _stream()), "dtw_rerank_lb" if prune else "dtw_rerank")
     return oid[:nq], od[:nq]
+
+
+def pair_distances(ws: torch.Tensor, nq: int, C: int) -> torch.Tensor:
+    """View of the [nq, C] float32 pair distances a re-rank left in its workspace."""
+    return ws[: nq * C * 4].view(torch.float32).view(nq, C)

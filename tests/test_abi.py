@@ -90,16 +90,22 @@ def test_validation_rejects_without_device_work(ssh):
     # too small a probe workspace
     assert L.ssh_probe(dummy, dummy, 10, 2, dummy, dummy, 4, dummy, dummy, 3, 50, dummy, dummy,
                        dummy, dummy, 8, None) == EINVAL
-    assert L.dtw_rerank(dummy, dummy, 1, dummy, dummy, 10, dummy, dummy, 8, 0.1, 100, 100, 9,
+    assert L.dtw_rerank(dummy, dummy, 1, dummy, dummy, 10, dummy, dummy, 8, 0.1, 9,
                         dummy, dummy, dummy, 1 << 20, None) == EINVAL
-    assert L.dtw_rerank(dummy, dummy, 1, dummy, dummy, 10, dummy, dummy, 8, 1.5, 100, 100, 4,
+    assert L.dtw_rerank(dummy, dummy, 1, dummy, dummy, 10, dummy, dummy, 8, 1.5, 4,
                         dummy, dummy, dummy, 1 << 20, None) == EINVAL
+    assert L.dtw_rerank(dummy, dummy, 2, dummy, dummy, 10, dummy, dummy, 8, 0.1, 4,
+                        dummy, dummy, dummy, 16, None) == EINVAL
+    assert b"workspace" in L.ssh_last_error()
+    # nq * C must stay below 2^31 (int32 pair indices)
+    assert L.dtw_rerank(dummy, dummy, 1 << 20, dummy, dummy, 10, dummy, dummy, 4096, 0.1, 4,
+                        dummy, dummy, dummy, 1 << 20, None) == EUNSUP
     # the pruned re-rank validates the same way, and its workspace must be large enough
-    assert L.dtw_rerank_lb(dummy, dummy, 1, dummy, dummy, 10, dummy, dummy, 8, 0.1, 100, 100, 9,
+    assert L.dtw_rerank_lb(dummy, dummy, 1, dummy, dummy, 10, dummy, dummy, 8, 0.1, 9,
                            dummy, dummy, dummy, 1 << 20, None) == EINVAL
-    assert L.dtw_rerank_lb(dummy, dummy, 1, dummy, dummy, 10, dummy, dummy, 8, 1.5, 100, 100, 4,
+    assert L.dtw_rerank_lb(dummy, dummy, 1, dummy, dummy, 10, dummy, dummy, 8, 1.5, 4,
                            dummy, dummy, dummy, 1 << 20, None) == EINVAL
-    assert L.dtw_rerank_lb(dummy, dummy, 2, dummy, dummy, 10, dummy, dummy, 8, 0.1, 100, 100, 4,
+    assert L.dtw_rerank_lb(dummy, dummy, 2, dummy, dummy, 10, dummy, dummy, 8, 0.1, 4,
                            dummy, dummy, dummy, 16, None) == EINVAL
     assert b"workspace" in L.ssh_last_error()
     # a filter value that fp16 staging cannot represent is refused
@@ -133,8 +139,11 @@ def test_validation_rejects_without_device_work(ssh):
 
 def test_workspace_sizes(ssh):
     assert ssh.table_workspace_bytes(1_000_000, 10) >= 1_000_000 * 10 * 12
-    assert ssh.rerank_workspace_bytes(50, 50) >= 50 * 50 * 4
-    assert ssh.rerank_lb_workspace_bytes(50, 50, 1024) >= 50 * 50 * 13 + 2 * 50 * 1024 * 4
+    # distances, class bytes and class lists of every pair
+    assert ssh.rerank_workspace_bytes(50, 50) >= 50 * 50 * 9
+    # distances, bounds, marks, lists, planning, and two envelopes of the query values
+    assert ssh.rerank_lb_workspace_bytes(50, 50, 50 * 1024) >= 50 * 50 * 18 + 2 * 50 * 1024 * 4
+    assert ssh.rerank_lb_workspace_bytes(50, 50, 50 * 1024) > ssh.rerank_lb_workspace_bytes(50, 50, 0)
     # the partial rankings of every part of every query, and the runs
     assert ssh.probe_workspace_bytes(1000, 10, 50) >= 1000 * 8 * 50 * 8 + 1000 * 21 * 8
     assert ssh.probe_workspace_bytes(1, 10, 4096) >= 4096 * 8

@@ -150,8 +150,7 @@ def _check_rerank(ssh, qh: HashBatch, db: HashBatch, Qx, Qoff, x, off, p: Params
     qx = np.concatenate(qs).astype(np.float32)
     ids, dist = ssh.dtw_rerank(torch.as_tensor(qx).cuda(), torch.as_tensor(qoff).cuda(), db.x,
                                db.x_off, torch.as_tensor(cand).cuda(),
-                               torch.as_tensor(ncand).cuda(), p.band_frac, len(qs[0]),
-                               int(off[1] - off[0]), p.k)
+                               torch.as_tensor(ncand).cuda(), p.band_frac, p.k)
     torch.cuda.synchronize()
     ssh.check_device_errors()
     oids, odist, all_d = oracle.rerank(qx, qoff, x, off, cand, ncand, p.band_frac, p.k)
@@ -175,7 +174,7 @@ def _run_index_and_queries(ssh, X, Q, p: Params, seed: int):
     ix.build()
     qh.run(r, tables)
     qb.probe()
-    qb.rerank(Q.shape[1], X.shape[1])
+    qb.rerank()
     torch.cuda.synchronize()
     ssh.check_device_errors()
     return x, off, qx, qoff, r, draws, db, qh, ix, qb
