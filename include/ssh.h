@@ -65,6 +65,7 @@ typedef int32_t ssh_status;
 #define SSH_MAX_C 4096           /* largest candidate cap of ssh_probe      */
 #define SSH_MAX_K 1024           /* largest k of dtw_rerank                 */
 #define SSH_MAX_BAND 255         /* largest Sakoe-Chiba radius of a dtw_rerank pair */
+#define SSH_NOALLOC_SCRATCH_BYTES (32u << 20) /* static scratch of dtw_rerank_noalloc, per device */
 
 /* [host] Name of a status code, and the detail of the last error raised on the
  * calling thread ("" if none).  Both strings are owned by the library. */
@@ -280,6 +281,26 @@ ssh_status dtw_rerank(const float* q, const int64_t* q_off, int32_t nq, const fl
                       const int64_t* db_off, int64_t N, const int64_t* cand, const int32_t* ncand,
                       int32_t C, float band_frac, int32_t k, int64_t* out_id, float* out_dist,
                       void* ws, size_t ws_bytes, void* stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): dtw_rerank
+ * with the same arguments and results, minus the workspace.  Its workspace is
+ * a static array of SSH_NOALLOC_SCRATCH_BYTES (32 MiB) that every device the
+ * library runs on holds until the process ends; the call itself allocates and
+ * frees nothing.
+ *   Limit: ssh_rerank_workspace_bytes(nq, C) must not exceed the array (about
+ *   3.5 million pairs nq * C); a larger call returns SSH_ECAPACITY and enqueues
+ *   nothing.
+ *   Concurrency: every call on one device shares that device's array, so calls
+ *   that overlap on one GPU (other threads, or other streams whose work is not
+ *   ordered after this call's) race and give undefined results.  Calls on one
+ *   stream are ordered and safe.  The array's contents after a call are the
+ *   pair distances as for dtw_rerank's workspace (read by no other entry
+ *   point); nothing in it needs to start at zero. */
+ssh_status dtw_rerank_noalloc(const float* q, const int64_t* q_off, int32_t nq, const float* db,
+                              const int64_t* db_off, int64_t N, const int64_t* cand,
+                              const int32_t* ncand, int32_t C, float band_frac, int32_t k,
+                              int64_t* out_id, float* out_dist, void* stream);
 
 /* [host] Workspace bytes needed by dtw_rerank_lb; q_values = q_off[nq], the
  * number of query values of the batch. */

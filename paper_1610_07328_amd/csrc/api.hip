@@ -54,6 +54,10 @@ ssh_status rerank_launch(const float* q, const int64_t* q_off, int nq, const flo
                          const int64_t* db_off, int64_t Ndb, const int64_t* cand,
                          const int32_t* ncand, int C, float band_frac, int k, int64_t* out_id,
                          float* out_dist, void* ws, size_t ws_bytes, hipStream_t stream);
+ssh_status rerank_noalloc_launch(const float* q, const int64_t* q_off, int nq, const float* db,
+                                 const int64_t* db_off, int64_t Ndb, const int64_t* cand,
+                                 const int32_t* ncand, int C, float band_frac, int k,
+                                 int64_t* out_id, float* out_dist, hipStream_t stream);
 
 ssh_status wmh_int_launch(const uint32_t* codes, const uint32_t* counts, const int64_t* hist_off,
                           const int32_t* n_distinct, int64_t N, int H, uint64_t seed, uint64_t* hv,
@@ -277,6 +281,22 @@ ssh_status dtw_rerank(const float* q, const int64_t* q_off, int32_t nq, const fl
   SSH_REQUIRE(N == 0 || (db && db_off), "dtw_rerank: null series pointer");
   return rerank_launch(q, q_off, nq, db, db_off, N, cand, ncand, C, band_frac, k, out_id, out_dist,
                        ws, ws_bytes, as_stream(stream));
+}
+
+ssh_status dtw_rerank_noalloc(const float* q, const int64_t* q_off, int32_t nq, const float* db,
+                              const int64_t* db_off, int64_t N, const int64_t* cand,
+                              const int32_t* ncand, int32_t C, float band_frac, int32_t k,
+                              int64_t* out_id, float* out_dist, void* stream) {
+  SSH_REQUIRE(nq >= 0 && N >= 0, "dtw_rerank_noalloc: nq or N < 0");
+  SSH_REQUIRE(C >= 1 && C <= SSH_MAX_C, "dtw_rerank_noalloc: C out of [1, SSH_MAX_C]");
+  SSH_REQUIRE(k >= 1 && k <= SSH_MAX_K && k <= C,
+              "dtw_rerank_noalloc: k out of [1, min(C, SSH_MAX_K)]");
+  SSH_REQUIRE(band_frac >= 0.0f && band_frac <= 1.0f, "dtw_rerank_noalloc: band_frac out of [0, 1]");
+  if (nq == 0) return SSH_OK;
+  SSH_REQUIRE(q && q_off && cand && ncand && out_id && out_dist, "dtw_rerank_noalloc: null pointer");
+  SSH_REQUIRE(N == 0 || (db && db_off), "dtw_rerank_noalloc: null series pointer");
+  return rerank_noalloc_launch(q, q_off, nq, db, db_off, N, cand, ncand, C, band_frac, k, out_id,
+                               out_dist, as_stream(stream));
 }
 
 size_t ssh_rerank_lb_workspace_bytes(int32_t nq, int32_t C, int64_t q_values) {

@@ -45,6 +45,7 @@
 // their minimum bounds the final total from below.  A wavefront whose four
 // pairs all have that minimum above their cut stops and reports +inf.
 #include <cmath>
+#include <mutex>
 
 #include "common.hpp"
 
@@ -1069,6 +1070,55 @@ ssh_status rerank_lb_launch(const float* q, const int64_t* q_off, int nq, const 
   }
   topk_kernel<<<nq, 256, 0, stream>>>(dist, cand, ncand, C, k, out_id, out_dist);
   return check_launch("dtw_rerank_lb");
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free re-rank: the workspace of dtw_rerank in a static array
+// ---------------------------------------------------------------------------
+// One copy per device, held until the process ends.  Host code never passes
+// the array's name to a kernel (on the host it is only a stand-in for the
+// symbol): the device address is resolved once per device with
+// hipGetSymbolAddress and every launch takes that address.
+constexpr size_t kNoAllocScratch = SSH_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) uint8_t scratch[kNoAllocScratch];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices];
+
+static ssh_status scratch_address(void** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(SSH_EDEVICE, "dtw_rerank_noalloc: no current device");
+  if (dev < 0 || dev >= kMaxDevices)
+    return fail(SSH_EUNSUPPORTED, "dtw_rerank_noalloc: device index above 63");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[dev] == nullptr) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || p == nullptr)
+      return fail(SSH_EDEVICE, std::string("dtw_rerank_noalloc: cannot resolve the scratch array: ") +
+                                   hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return SSH_OK;
+}
+
+ssh_status rerank_noalloc_launch(const float* q, const int64_t* q_off, int nq, const float* db,
+                                 const int64_t* db_off, int64_t Ndb, const int64_t* cand,
+                                 const int32_t* ncand, int C, float band_frac, int k,
+                                 int64_t* out_id, float* out_dist, hipStream_t stream) {
+  if (nq == 0) return SSH_OK;
+  const size_t need = rerank_workspace_bytes(nq, C);
+  if ((int64_t)nq * C > INT32_MAX || need > kNoAllocScratch)
+    return fail(SSH_ECAPACITY, "dtw_rerank_noalloc: nq * C = " + std::to_string((int64_t)nq * C) +
+                                   " pairs need " + std::to_string(need) +
+                                   " bytes of scratch, above SSH_NOALLOC_SCRATCH_BYTES");
+  void* ws = nullptr;
+  const ssh_status st = scratch_address(&ws);
+  if (st != SSH_OK) return st;
+  return rerank_launch(q, q_off, nq, db, db_off, Ndb, cand, ncand, C, band_frac, k, out_id,
+                       out_dist, ws, kNoAllocScratch, stream);
 }
 
 }  // namespace ssh

@@ -67,6 +67,8 @@ SIGNATURES = {
     "ssh_rerank_workspace_bytes": (_sz, [_i32, _i32]),
     "dtw_rerank": (_i32, [_vp, _vp, _i32, _vp, _vp, _i64, _vp, _vp, _i32, _f32, _i32, _vp,
                           _vp, _vp, _sz, _vp]),
+    "dtw_rerank_noalloc": (_i32, [_vp, _vp, _i32, _vp, _vp, _i64, _vp, _vp, _i32, _f32, _i32,
+                                  _vp, _vp, _vp]),
     "ssh_rerank_lb_workspace_bytes": (_sz, [_i32, _i32, _i64]),
     "dtw_rerank_lb": (_i32, [_vp, _vp, _i32, _vp, _vp, _i64, _vp, _vp, _i32, _f32, _i32, _vp,
                              _vp, _vp, _sz, _vp]),
@@ -366,6 +368,26 @@ def dtw_rerank(q, q_off, db, db_off, cand, ncand, band_frac: float, k: int,
               float(band_frac), k, _dev(oid, torch.int64, "out_id"),
               _dev(od, torch.float32, "out_dist"), _dev(ws, torch.uint8, "ws"), ws.numel(),
               _stream()), "dtw_rerank_lb" if prune else "dtw_rerank")
+    return oid[:nq], od[:nq]
+
+
+NOALLOC_SCRATCH_BYTES = 32 << 20
+
+
+def dtw_rerank_noalloc(q, q_off, db, db_off, cand, ncand, band_frac: float, k: int, out):
+    """dtw_rerank through the allocation-free entry point: the library takes
+    its workspace from a static per-device array, and the caller passes the
+    outputs (ids int64 [nq, k], dist float32 [nq, k]).  Calls that overlap on
+    one device race for that array."""
+    nq, C = cand.shape
+    N = db_off.numel() - 1
+    oid, od = out
+    _check(lib().dtw_rerank_noalloc(
+        _dev(q, torch.float32, "q"), _dev(q_off, torch.int64, "q_off"), nq,
+        _dev(db, torch.float32, "db"), _dev(db_off, torch.int64, "db_off"), N,
+        _dev(cand, torch.int64, "cand"), _dev(ncand, torch.int32, "ncand"), C, float(band_frac),
+        k, _dev(oid, torch.int64, "out_id"), _dev(od, torch.float32, "out_dist"), _stream()),
+        "dtw_rerank_noalloc")
     return oid[:nq], od[:nq]
 
 

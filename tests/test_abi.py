@@ -100,6 +100,12 @@ def test_validation_rejects_without_device_work(ssh):
     # nq * C must stay below 2^31 (int32 pair indices)
     assert L.dtw_rerank(dummy, dummy, 1 << 20, dummy, dummy, 10, dummy, dummy, 4096, 0.1, 4,
                         dummy, dummy, dummy, 1 << 20, None) == EUNSUP
+    # the allocation-free re-rank refuses a batch beyond its static scratch, before any device work
+    assert L.dtw_rerank_noalloc(dummy, dummy, 1 << 16, dummy, dummy, 10, dummy, dummy, 4096, 0.1,
+                                4, dummy, dummy, None) == -4  # SSH_ECAPACITY
+    assert b"SSH_NOALLOC_SCRATCH_BYTES" in L.ssh_last_error()
+    assert L.dtw_rerank_noalloc(dummy, dummy, 1, dummy, dummy, 10, dummy, dummy, 8, 0.1, 9,
+                                dummy, dummy, None) == EINVAL
     # the pruned re-rank validates the same way, and its workspace must be large enough
     assert L.dtw_rerank_lb(dummy, dummy, 1, dummy, dummy, 10, dummy, dummy, 8, 0.1, 9,
                            dummy, dummy, dummy, 1 << 20, None) == EINVAL
