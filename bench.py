@@ -1,23 +1,32 @@
 """Benchmark of the SSH hot path on one MI355X.
 
-Workload (batched index build): 1,000,000 z-normalised random-walk series of
-length 1024 (fp32, resident in HBM), filter W = 80, step delta = 3, shingle
-n = 15, 100 weighted-MinHash hashes (K = 10 per band, L = 10 tables).  One
-step is one pass of the whole hot path: sketch, shingle, CWS and band keys of
-the database, the hash-table build, then a batch of 1,000 queries (perturbed
-database series, N(0, 0.1^2) noise, z-normalised) through sketch, shingle,
-CWS, band keys, probe (top C = 50 candidates) and banded DTW re-rank (5 %
+Headline workload (the largest single-GPU configuration): 10,000,000
+z-normalised random-walk series of length 2048 (fp32, 81.92 GB resident in
+HBM), filter W = 128, step delta = 4, shingle n = 15, 200 weighted-MinHash
+hashes (K = 10 per band, L = 20 tables).  One step is one pass of the whole
+hot path: sketch, shingle, CWS and band keys of the database, the hash-table
+build, then a batch of 4,096 queries (perturbed copies of series among the
+first 100,000, N(0, 0.1^2) noise, z-normalised) through sketch, shingle, CWS,
+band keys, probe (top C = 200 candidates) and banded DTW re-rank (10 %
 Sakoe-Chiba band, top k = 10).
 
+`--workload index` puts the batched index-build configuration on the line
+instead: 1,000,000 series of length 1024, W = 80, delta = 3, n = 15, 100
+hashes (K = L = 10), 1,000 queries, C = 50, 5 % band.  The default run
+reports that configuration's figures as extra keys.
+
 Prints one JSON line: series hashed per second (value), DTW cells per
-second, per-stage times, the roofline of the dominant kernel and the CPU
+second, per-stage times, the roofline of the dominant kernel, single-query
+latency, recall@10 against exhaustive DTW on sampled queries, and the CPU
 oracle timed on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
 import argparse
+import concurrent.futures as cf
 import json
 import math
+import multiprocessing as mp
 import os
 import sys
 import time
@@ -35,18 +44,37 @@ FP32_VALU_TFLOPS = 157.3
 # 2.4 GHz (157.3 TFLOP/s counts an FMA as 2 and packed fp32 as 2 lanes)
 VALU_LANE_OPS = FP32_VALU_TFLOPS * 1e12 / 4
 
-# HBM traffic of one launch of a kernel on this workload, from two rocprofv3
+METRIC = "series hashed/s + DTW cells/s (vs roofline); p50/p99 top-10 query latency"
+
+WORKLOADS = {
+    "large": dict(
+        workload="large configuration: 10,000,000 random-walk series x 2048 fp32 (81.92 GB in "
+                 "HBM), W=128 delta=4 n=15, 200 CWS hashes (K=10, L=20); 4,096 queries, C=200, "
+                 "DTW band 10%, top-10",
+        N=10_000_000, m=2048, W=128, delta=4, n=15, K=10, L=20, nq=4096, C=200, band=0.10,
+        k=10, recall_queries=8),
+    "index": dict(
+        workload="batched index build: 1,000,000 random-walk series x 1024 fp32, W=80 delta=3 "
+                 "n=15, 100 CWS hashes (K=10, L=10); 1,000 queries, C=50, DTW band 5%, top-10",
+        N=1_000_000, m=1024, W=80, delta=3, n=15, K=10, L=10, nq=1000, C=50, band=0.05, k=10,
+        recall_queries=100),
+}
+
+# series per upload chunk: generated on the host, copied, then dropped
+UPLOAD_ROWS = 1 << 18
+
+# HBM traffic of one launch of a kernel on a workload, from two rocprofv3
 # counter runs of this script (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch),
 # each scaled by the ratio of known bytes to the same counter's reading for a
 # plain device copy (--copy-calibration).  A figure is reported only while the
 # kernel's source file still has the digest it was measured with.
 MEASURED_TRAFFIC = {
-    # kernel: (source file, sha256 of it, FETCH_SIZE KiB, WRITE_SIZE KiB,
-    #          fetch scale, write scale); the 1 GiB copy read 524306.6 KiB on
-    #          FETCH_SIZE and 1048576 KiB on WRITE_SIZE
-    "cws_kernel": ("paper_1610_07328_amd/csrc/cws.hip",
-                   "ccb9483ee387c2dfa4db072c851ec8119f7e73577ec1befb94fc91647033061b",
-                   3571453.9375, 903875.46875, 1048576.0 / 524306.5625, 1.0),
+    # (kernel, workload): (source file, sha256 of it, FETCH_SIZE KiB, WRITE_SIZE KiB,
+    #                      fetch scale, write scale); the 1 GiB copy read 524306.6 KiB
+    #                      on FETCH_SIZE and 1048576 KiB on WRITE_SIZE
+    ("cws_kernel", "index"): ("paper_1610_07328_amd/csrc/cws.hip",
+                              "ccb9483ee387c2dfa4db072c851ec8119f7e73577ec1befb94fc91647033061b",
+                              3571453.9375, 903875.46875, 1048576.0 / 524306.5625, 1.0),
 }
 
 
@@ -60,10 +88,10 @@ def band_cells(lq: int, lx: int, r: int) -> int:
     return total
 
 
-def measured_traffic(kernel: str):
+def measured_traffic(kernel: str, workload: str):
     """HBM bytes per launch of `kernel` from the recorded counters, or None."""
     import hashlib
-    rec = MEASURED_TRAFFIC.get(kernel)
+    rec = MEASURED_TRAFFIC.get((kernel, workload))
     if rec is None:
         return None
     src, digest, fetch_kib, write_kib, fs, ws = rec
@@ -92,12 +120,14 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--n-series", type=int, default=1_000_000)
-    ap.add_argument("--length", type=int, default=1024)
-    ap.add_argument("--nq", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="large")
+    ap.add_argument("--n-series", type=int, default=0, help="override the workload's series count")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the other workload's figures")
     ap.add_argument("--latency-samples", type=int, default=200)
-    ap.add_argument("--cpu-sample", type=int, default=80000)
+    ap.add_argument("--recall-queries", type=int, default=-1)
+    ap.add_argument("--cpu-sample", type=int, default=100_000)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run one device copy of BYTES bytes (counter calibration)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -105,77 +135,149 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(X, r, draws, p, Q, sample: int):
-    """The CPU oracle on the first `sample` series (and 16 queries) of the workload."""
-    import oracle
-    from oracle import _dtw_c
+def log(msg: str):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
-    Xs = X[:sample]
-    t0 = time.perf_counter()
-    B = oracle.sketch_batch(Xs, r, p.W, p.delta)
-    sets = [oracle.shingle(b, p.n) for b in B]
-    smax = max(2, max(int(c.max()) for _, c in sets if len(c)))
+
+# --------------------------------------------------------------------------
+# CPU baseline: the oracle, unchanged, over the host's cores
+# --------------------------------------------------------------------------
+_W = {}
+
+
+def _cpu_init(cfg, seed):
+    from paper_1610_07328_amd import datagen
+    _W["cfg"] = cfg
+    _W["r"] = datagen.filter_r(cfg["W"], seed=seed)
+    _W["draws"] = datagen.cws_draws(cfg["n"], cfg["K"] * cfg["L"], seed=seed)
+
+
+def _cpu_hash(X):
+    """Sketch, shingle, CWS and band keys of rows X with the oracle; returns the
+    number of series hashed."""
+    import oracle
+    cfg, r, draws = _W["cfg"], _W["r"], _W["draws"]
+    B = oracle.sketch_batch(X, r, cfg["W"], cfg["delta"])
+    sets = [oracle.shingle(b, cfg["n"]) for b in B]
+    smax = max([2] + [int(c.max()) for _, c in sets if len(c)])
     lnS = oracle.ln_table(smax)
     hv = np.stack([oracle.cws(c, k, *draws, lnS)[2] for c, k in sets])
-    oracle.band_keys(hv, p.K, p.L, p.key_seed)
-    t_hash = time.perf_counter() - t0
-    # DTW: 16 queries x C candidates in the same band
+    oracle.band_keys(hv, cfg["K"], cfg["L"], 0x5EED)
+    return X.shape[0]
+
+
+def cpu_baseline(cfg, seed: int, sample: int, Q):
+    """The CPU oracle on the first `sample` series of the workload, split over the
+    host's cores (at most 16, the host share of one GPU), and its DTW on 64
+    queries x C random candidates of the same shape."""
+    from oracle import _dtw_c
     from paper_1610_07328_amd import datagen
-    nqs = 16
+
+    cores = min(16, len(os.sched_getaffinity(0)))
+    X = datagen.random_walk_rows(0, sample, cfg["m"], seed=seed)
+    parts = np.array_split(X, cores * 4)
+    ctx = mp.get_context("spawn")
+    with cf.ProcessPoolExecutor(cores, mp_context=ctx, initializer=_cpu_init,
+                                initargs=(cfg, seed)) as ex:
+        list(ex.map(_cpu_hash, [X[:cores]] * cores))  # workers started and warm
+        t0 = time.perf_counter()
+        done = sum(ex.map(_cpu_hash, parts))
+        t_hash = time.perf_counter() - t0
+    nqs = 64
     q, qoff = datagen.csr(Q[:nqs])
-    db, dboff = datagen.csr(Xs)
+    db, dboff = datagen.csr(X)
     rng = np.random.default_rng(0)
-    cand = rng.integers(0, sample, size=(nqs, p.C)).astype(np.int64)
-    ncand = np.full(nqs, p.C, np.int32)
+    cand = rng.integers(0, sample, size=(nqs, cfg["C"])).astype(np.int64)
+    ncand = np.full(nqs, cfg["C"], np.int32)
     t1 = time.perf_counter()
-    oracle.rerank(q, qoff, db, dboff, cand, ncand, p.band_frac, p.k)
+    _dtw_c.dtw_pairs(q, qoff, db, dboff, cand, ncand, cfg["band"])
     t_dtw = time.perf_counter() - t1
-    rr = int(math.floor(float(np.float32(p.band_frac)) * X.shape[1]))
-    cells = nqs * p.C * band_cells(X.shape[1], X.shape[1], rr)
+    rr = int(math.floor(float(np.float32(cfg["band"])) * cfg["m"]))
+    cells = nqs * cfg["C"] * band_cells(cfg["m"], cfg["m"], rr)
+    try:
+        cpu = [ln.split(":", 1)[1].strip() for ln in open("/proc/cpuinfo")
+               if ln.startswith("model name")][0]
+    except (OSError, IndexError):
+        cpu = "unknown"
     return {
-        "value": sample / t_hash,
+        "value": done / t_hash,
         "unit": "series hashed/s",
-        "cores": 1,
+        "cores": cores,
         "kind": "oracle",
-        "sample": f"first {sample} series of the workload through sketch, shingle, CWS and "
-                  f"band keys (numpy float64, one thread); DTW re-rank of {nqs} queries x "
-                  f"{p.C} candidates in C with OpenMP",
+        "sample": f"first {done} series of the workload through the oracle's sketch, shingle, "
+                  f"CWS and band keys (numpy float64), split over {cores} worker processes; DTW "
+                  f"of {nqs} queries x {cfg['C']} candidates in the oracle's C with OpenMP",
+        "cpu_model": cpu,
+        "host_cpus": os.cpu_count(),
+        "hash_seconds": t_hash,
         "dtw_cells_per_s": cells / t_dtw,
         "dtw_cores": _dtw_c.num_threads(),
-        "seconds": t_hash + t_dtw,
     }
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
-              f"(the index would shard by series across GPUs; only one GPU is measured).", file=sys.stderr)
-        sys.exit(2)
-    if args.copy_calibration > 0:
-        copy_calibration(args.copy_calibration)
-        return
+# --------------------------------------------------------------------------
+# GPU runs
+# --------------------------------------------------------------------------
+def upload_walks(N: int, m: int, seed: int, dev):
+    """The workload's random walks, generated on the host in chunks of
+    UPLOAD_ROWS series and copied into one device array (the host never holds
+    more than two chunks)."""
+    import torch
 
+    from paper_1610_07328_amd import datagen
+    x = torch.empty(N * m, dtype=torch.float32, device=dev)
+    chunks = [(lo, min(N, lo + UPLOAD_ROWS)) for lo in range(0, N, UPLOAD_ROWS)]
+    with cf.ThreadPoolExecutor(1) as ex:
+        nxt = ex.submit(datagen.random_walk_rows, *chunks[0], m, seed)
+        for i, (lo, hi) in enumerate(chunks):
+            rows = nxt.result()
+            if i + 1 < len(chunks):
+                nxt = ex.submit(datagen.random_walk_rows, *chunks[i + 1], m, seed)
+            x[lo * m:hi * m].copy_(torch.from_numpy(rows.reshape(-1)))
+            del rows
+    return x
+
+
+def event_ms(fn, reps: int) -> float:
+    import torch
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    fn()
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    e1.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def run_workload(name: str, args, main: bool):
     import torch
 
     from paper_1610_07328_amd import datagen, ssh
-    from paper_1610_07328_amd.pipeline import HashBatch, Index, Params, QueryBatch
+    from paper_1610_07328_amd.pipeline import (HashBatch, Index, Params, QueryBatch,
+                                               exhaustive_topk)
 
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
-    torch.cuda.set_device(0)
-    p = Params(W=80, delta=3, n=15, K=10, L=10, band_frac=0.05, C=50, k=10)
-    N, m, nq = args.n_series, args.length, args.nq
-    t0 = time.perf_counter()
-    X = datagen.random_walks(N, m, seed=args.seed)
-    Q, _ = datagen.perturbed_queries(X[: min(N, 100_000)], nq, 0.1, seed=args.seed)
-    r = datagen.filter_r(p.W, seed=args.seed)
-    draws = datagen.cws_draws(p.n, p.H, seed=args.seed)
-    print(f"[bench] generated {N} x {m} series in {time.perf_counter() - t0:.1f}s", file=sys.stderr,
-          flush=True)
-
+    cfg = dict(WORKLOADS[name])
+    if main and args.n_series > 0:
+        cfg["N"] = args.n_series
+    N, m, nq = cfg["N"], cfg["m"], cfg["nq"]
+    p = Params(W=cfg["W"], delta=cfg["delta"], n=cfg["n"], K=cfg["K"], L=cfg["L"],
+               band_frac=cfg["band"], C=cfg["C"], k=cfg["k"])
+    steps = args.steps if main else 3
+    warmup = args.warmup if main else 1
     dev = torch.device("cuda:0")
-    x, off = datagen.csr(X)
-    xd = torch.as_tensor(x).to(dev)
+    seed = args.seed
+
+    t0 = time.perf_counter()
+    xd = upload_walks(N, m, seed, dev)
+    off = np.arange(N + 1, dtype=np.int64) * m
+    first = datagen.random_walk_rows(0, min(N, 100_000), m, seed=seed)
+    Q, src = datagen.perturbed_queries(first, nq, 0.1, seed=seed)
+    r = datagen.filter_r(p.W, seed=seed)
+    draws = datagen.cws_draws(p.n, p.H, seed=seed)
+    log(f"{name}: {N} x {m} series generated and resident in {time.perf_counter() - t0:.1f}s")
+
     q, qoff = datagen.csr(Q)
     qd = torch.as_tensor(q).to(dev)
     tables = ssh.CwsTables(*draws, p.n, device=dev)
@@ -208,40 +310,37 @@ def main():
         qry.rerank()
         mark(7)
 
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         step()
     torch.cuda.synchronize()
     ssh.check_device_errors()
-
     events = [[torch.cuda.Event(enable_timing=True) for _ in range(len(stages) + 1)]
-              for _ in range(args.steps)]
+              for _ in range(steps)]
     torch.cuda.synchronize()
     t_start = time.perf_counter()
-    for s in range(args.steps):
+    for s in range(steps):
         step(events[s])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
     ssh.check_device_errors()
+    log(f"{name}: {steps} steps in {wall:.2f}s")
 
-    per_stage = {name: 0.0 for name in stages}
+    per_stage = {k: 0.0 for k in stages}
     for ev in events:
-        for i, name in enumerate(stages):
-            per_stage[name] += ev[i].elapsed_time(ev[i + 1]) / args.steps  # ms
-    ms_per_step = wall * 1000.0 / args.steps
+        for i, k in enumerate(stages):
+            per_stage[k] += ev[i].elapsed_time(ev[i + 1]) / steps  # ms
 
-    # workload facts for the algorithmic byte counts
+    # workload facts for the algorithmic counts
     ncand = qry.ncand[:nq].cpu().numpy()
     rsz = qry.rsize[:nq].cpu().numpy().astype(np.float64)
     nd = db.ndist[:N].cpu().numpy().astype(np.int64)
-    repaired = int(db.repair.cpu().numpy()[0]) / (args.warmup + args.steps)
+    repaired = int(db.repair.cpu().numpy()[0]) / (warmup + steps)
     nb = int(db.plan.max_nbits)
     words = (nb + 63) // 64
-    S = nb - p.n + 1
     rr = int(math.floor(float(np.float32(p.band_frac)) * m))
     cells_per_pair = band_cells(m, m, rr)
-    cells = int(ncand.sum()) * cells_per_pair
+    step_cells = int(ncand.sum()) * cells_per_pair
     sum_d = int(nd.sum())
-
     bytes_stage = {
         "sketch": N * (4 * m + 8 * words + 4) + 16 * (N + 1),
         "shingle": N * (8 * words + 4 + 4) + 16 * (N + 1) + 8 * sum_d,
@@ -249,109 +348,52 @@ def main():
         # radix passes over the top 24 bits (N <= 2^20) or 32: keys and ids read twice, written once
         "table_build": (3 if N <= (1 << 20) else 4) * N * p.L * (8 + 12 + 12),
     }
-    stage_roofline = {}
-    for name, b in bytes_stage.items():
-        t = per_stage[name] / 1e3
-        stage_roofline[name] = {"GB/s": b / t / 1e9, "frac_hbm": b / t / 1e9 / HBM_PEAK_GBS}
-
-    # CWS float64 evaluations: one per (series, distinct token, hash)
+    stage_hbm = {k: {"GB/s": b / (per_stage[k] / 1e3) / 1e9,
+                     "frac_hbm": b / (per_stage[k] / 1e3) / 1e9 / HBM_PEAK_GBS}
+                 for k, b in bytes_stage.items()}
     cws_evals = sum_d * p.H
-    dominant = max(["sketch", "shingle", "cws", "table_build", "rerank"],
-                   key=lambda k: per_stage[k])
-    if dominant == "rerank":
-        # 3 VALU lane-ops per cell (subtract, 3-way min, FMA) against the lane-op peak
-        achieved = cells * 3 / (per_stage["rerank"] / 1e3) / 1e12
-        peak = VALU_LANE_OPS / 1e12
-        roof = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tops/s",
-                "frac": achieved / peak, "traffic": None, "kernel": "dtw_kernel"}
-    else:
-        kname = {"sketch": "sketch_mfma_kernel", "shingle": "shingle_kernel", "cws": "cws_kernel",
-                 "table_build": "rs_scatter_kernel"}[dominant]
-        achieved = bytes_stage[dominant] / (per_stage[dominant] / 1e3) / 1e9
-        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(kname),
-                "kernel": kname, "kernel_ms": per_stage[dominant],
-                "algorithmic_bytes": bytes_stage[dominant]}
-        if dominant == "cws":
-            roof["token_hash_evals_per_s"] = cws_evals / (per_stage["cws"] / 1e3)
 
-    # DTW kernel throughput on a full batch: every query re-ranks C seeded
-    # random candidates in the same band (outside the timed step)
-    g = np.random.default_rng(args.seed + 1)
+    # the re-rank kernels on a full batch: every query re-ranks C seeded random
+    # candidates of the same shape (plain, then pruned)
+    g = np.random.default_rng(seed + 1)
     cand_full = torch.as_tensor(g.integers(0, N, size=(nq, p.C)), device=dev)
     ncand_full = torch.full((nq,), p.C, dtype=torch.int32, device=dev)
-    ws_full = torch.empty(max(ssh.rerank_workspace_bytes(nq, p.C), 1), dtype=torch.uint8, device=dev)
+    ws_full = torch.empty(ssh.rerank_workspace_bytes(nq, p.C), dtype=torch.uint8, device=dev)
     out_full = (torch.empty((nq, p.k), dtype=torch.int64, device=dev),
                 torch.empty((nq, p.k), dtype=torch.float32, device=dev))
-
-    def full_rerank():
-        ssh.dtw_rerank(qb.x, qb.x_off, db.x, db.x_off, cand_full, ncand_full, p.band_frac,
-                       p.k, ws=ws_full, out=out_full)
-
-    full_rerank()
-    torch.cuda.synchronize()
-    reps = 5
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(reps):
-        full_rerank()
-    e1.record()
-    e1.synchronize()
-    t_full = e0.elapsed_time(e1) / reps / 1e3
-    full_cells = nq * p.C * cells_per_pair
-    dtw_full = {"cells_per_s": full_cells / t_full, "ms": t_full * 1e3,
-                "pairs": nq * p.C, "cells": full_cells,
-                "alu_frac": full_cells * 3 / t_full / VALU_LANE_OPS}
-
-    # the same batch through the LB_Keogh-pruned re-rank (same results, less work)
-    ws_lb = torch.empty(max(ssh.rerank_lb_workspace_bytes(nq, p.C, qb.x.numel()), 1), dtype=torch.uint8,
+    ws_lb = torch.empty(ssh.rerank_lb_workspace_bytes(nq, p.C, qb.x.numel()), dtype=torch.uint8,
                         device=dev)
     out_lb = (torch.empty_like(out_full[0]), torch.empty_like(out_full[1]))
 
-    def full_rerank_lb():
-        ssh.dtw_rerank(qb.x, qb.x_off, db.x, db.x_off, cand_full, ncand_full, p.band_frac,
-                       p.k, ws=ws_lb, out=out_lb, prune=True)
+    def full_rerank(prune):
+        ssh.dtw_rerank(qb.x, qb.x_off, db.x, db.x_off, cand_full, ncand_full, p.band_frac, p.k,
+                       ws=ws_lb if prune else ws_full, out=out_lb if prune else out_full,
+                       prune=prune)
 
-    full_rerank_lb()
-    torch.cuda.synchronize()
-    e0.record()
-    for _ in range(reps):
-        full_rerank_lb()
-    e1.record()
-    e1.synchronize()
-    t_lb = e0.elapsed_time(e1) / reps / 1e3
+    reps = 3 if main else 5
+    t_full = event_ms(lambda: full_rerank(False), reps) / 1e3
+    t_lb = event_ms(lambda: full_rerank(True), reps) / 1e3
     same = bool(torch.equal(out_lb[0], out_full[0]) and
                 torch.equal(out_lb[1].view(torch.int32), out_full[1].view(torch.int32)))
-    dtw_full["lb_pruned"] = {"ms": t_lb * 1e3, "speedup": t_full / t_lb, "same_results": same}
-
-    # weighted MinHash by integer replication over the same index histograms
-    # (outside the step: an alternative to the CWS stage, integer arithmetic only)
-    hv_int = torch.empty((N, p.H), dtype=torch.uint64, device=dev)
-
-    def wmh_index():
-        ssh.wmh_int(db.codes, db.counts, db.hoff, db.ndist, p.H, p.wmh_seed, out=hv_int)
-
-    wmh_index()
-    torch.cuda.synchronize()
-    e0.record()
-    for _ in range(3):
-        wmh_index()
-    e1.record()
-    e1.synchronize()
-    t_wmh = e0.elapsed_time(e1) / 3 / 1e3
-    pairs = int(torch.clamp(db.nbits[:N].to(torch.int64) - p.n + 1, min=0).sum().item())
-    wmh_int_index = {"ms": t_wmh * 1e3, "series_per_s": N / t_wmh,
-                     "pair_hash_evals_per_s": pairs * p.H / t_wmh,
-                     "cws_stage_ms": per_stage["cws"]}
-    del hv_int
+    full_cells = nq * p.C * cells_per_pair
+    dtw_full = {"cells_per_s": full_cells / t_full, "ms": t_full * 1e3, "pairs": nq * p.C,
+                "cells": full_cells, "alu_frac": full_cells * 3 / t_full / VALU_LANE_OPS,
+                "lb_pruned": {"ms": t_lb * 1e3, "speedup": t_full / t_lb, "same_results": same}}
+    # the pruned re-rank on the step's own candidate lists
+    ws_lbs = torch.empty(ssh.rerank_lb_workspace_bytes(nq, p.C, qb.x.numel()), dtype=torch.uint8,
+                         device=dev)
+    t_step_plain = event_ms(qry.rerank, 5)
+    t_step_lb = event_ms(lambda: ssh.dtw_rerank(qb.x, qb.x_off, db.x, db.x_off, qry.cand[:nq],
+                                                qry.ncand[:nq], p.band_frac, p.k, ws=ws_lbs,
+                                                prune=True), 5)
+    del ws_lb, ws_lbs
 
     # single-query latency with the index resident
     lat = []
     if args.latency_samples > 0:
-        Q1 = Q[: args.latency_samples]
         singles = []
-        for i in range(Q1.shape[0]):
-            qi, qio = datagen.csr(Q1[i: i + 1])
+        for i in range(min(args.latency_samples, nq)):
+            qi, qio = datagen.csr(Q[i: i + 1])
             hb = HashBatch(torch.as_tensor(qi).to(dev), qio, p)
             singles.append((hb, QueryBatch(hb, index)))
         torch.cuda.synchronize()
@@ -364,44 +406,133 @@ def main():
             e1.record()
             e1.synchronize()
             lat.append(e0.elapsed_time(e1))
+        del singles
     lat = np.array(lat) if lat else np.array([float("nan")])
 
+    # recall@10: the step's top-10 against exhaustive DTW over all N series, on a
+    # seeded random sample of the queries
+    nrec = cfg["recall_queries"] if args.recall_queries < 0 else args.recall_queries
+    recall = None
+    if nrec > 0:
+        t_r = time.perf_counter()
+        ids_step = qry.ids[:nq].cpu().numpy()
+        pick = np.sort(np.random.default_rng(seed + 2).choice(nq, min(nrec, nq), replace=False))
+        hits, tot, src_exact, answered = 0, 0, 0, 0
+        for i in pick:
+            ex_id, ex_d = exhaustive_topk(qb.x[qoff[i]:qoff[i + 1]], db.x, db.x_off, p.band_frac,
+                                          p.k)
+            want = set(ex_id.cpu().numpy().tolist()) - {-1}
+            got = set(ids_step[i].tolist()) - {-1}
+            hits += len(want & got)
+            tot += len(want)
+            src_exact += int(src[i] in want)
+            answered += int(ncand[i] > 0)
+        recall = {"recall_at_10": hits / max(tot, 1), "queries": int(len(pick)),
+                  "queries_with_candidates": answered,
+                  # the ground truth holds each sampled query's source series
+                  "exhaustive_top10_holds_source": src_exact / len(pick),
+                  "seconds": time.perf_counter() - t_r,
+                  # every query is a noisy copy of a database series: how often
+                  # that series is among the step's top 10, over all queries
+                  "source_in_top10": float(np.mean([src[i] in set(ids_step[i].tolist())
+                                                    for i in range(nq)]))}
+        log(f"{name}: recall@10 {recall['recall_at_10']:.3f} on {recall['queries']} queries")
+
+    # dominant stage and its roofline
+    dominant = max(["sketch", "shingle", "cws", "table_build", "rerank"], key=lambda k: per_stage[k])
+    if dominant == "rerank":
+        achieved = step_cells * 3 / (per_stage["rerank"] / 1e3) / 1e12
+        peak = VALU_LANE_OPS / 1e12
+        roof = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tops/s",
+                "frac": achieved / peak, "traffic": None, "kernel": "dtw_group_kernel"}
+    else:
+        kname = {"sketch": "sketch_mfma_kernel", "shingle": "shingle_kernel", "cws": "cws_kernel",
+                 "table_build": "rs_scatter_kernel"}[dominant]
+        achieved = bytes_stage[dominant] / (per_stage[dominant] / 1e3) / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(kname, name),
+                "kernel": kname, "kernel_ms": per_stage[dominant],
+                "algorithmic_bytes": bytes_stage[dominant]}
+        if dominant == "cws":
+            roof["token_hash_evals_per_s"] = cws_evals / (per_stage["cws"] / 1e3)
+            # the same kernel against the FP64 vector peak: about 6 lane operations
+            # per (token, hash) evaluation in its keyed form
+            roof["valu_lane_ops_per_eval"] = 6
+
+    res = {
+        "value": N * steps / wall,
+        "ms_per_step": wall * 1000.0 / steps,
+        "steps": steps,
+        "warmup": warmup,
+        "config": {"workload": cfg["workload"], "n_series": N, "length": m, "W": p.W,
+                   "delta": p.delta, "n": p.n, "K": p.K, "L": p.L, "queries": nq, "C": p.C,
+                   "band_frac": p.band_frac, "k": p.k},
+        "dtw_cells_per_s": step_cells / (per_stage["rerank"] / 1e3),
+        "dtw_step_pairs": int(ncand.sum()),
+        "dtw_full_batch": dtw_full,
+        "rerank_step_candidates": {"plain_ms": t_step_plain, "pruned_ms": t_step_lb,
+                                   "speedup": t_step_plain / t_step_lb},
+        "query_latency_ms": {"p50": float(np.percentile(lat, 50)),
+                             "p99": float(np.percentile(lat, 99)),
+                             "samples": int(lat.size), "batch": 1},
+        "recall": recall,
+        "stage_ms": per_stage,
+        "stage_hbm": stage_hbm,
+        "retrieved_set": {"mean": float(rsz.mean()), "p50": float(np.percentile(rsz, 50)),
+                          "p99": float(np.percentile(rsz, 99)), "max": float(rsz.max()),
+                          "pruned_frac": float(1.0 - rsz.mean() / N),
+                          "queries_with_candidates": int((ncand > 0).sum())},
+        "sketch_fp64_repaired_windows": repaired,
+        "mean_distinct_shingles": sum_d / N,
+        "roofline": roof,
+    }
+    # free the device state before anything else runs
+    del db, qb, index, qry, xd, tables, cand_full, ws_full
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    return res, cfg, Q
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
+              f"(the index would shard by series across GPUs; only one GPU is measured).",
+              file=sys.stderr)
+        sys.exit(2)
+    if args.copy_calibration > 0:
+        copy_calibration(args.copy_calibration)
+        return
+
+    import torch
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+
+    res, cfg, Q = run_workload(args.workload, args, main=True)
     out = {
-        "metric": "series hashed/s",
-        "value": N * args.steps / wall,
-        "unit": "series/s",
+        "metric": METRIC,
+        "value": res["value"],
+        "unit": "series hashed/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "steps": res["steps"],
+        "warmup": res["warmup"],
+        "ms_per_step": res["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f16 dot / f32 acc / f64 repair + f64 CWS + f32 DTW",
         "data": "synthetic",
-        "config": {"workload": "batched index build: 1,000,000 random-walk series x 1024 fp32, "
-                               "W=80 delta=3 n=15, 100 CWS hashes (K=10, L=10); 1,000 queries, "
-                               "C=50, DTW band 5%, top-10",
-                   "n_series": N, "length": m, "W": p.W, "delta": p.delta, "n": p.n,
-                   "K": p.K, "L": p.L, "queries": nq, "C": p.C, "band_frac": p.band_frac,
-                   "k": p.k},
-        "dtw_cells_per_s": cells / (per_stage["rerank"] / 1e3),
-        "dtw_full_batch": dtw_full,
-        "query_latency_ms": {"p50": float(np.percentile(lat, 50)),
-                             "p99": float(np.percentile(lat, 99)),
-                             "samples": int(lat.size), "batch": 1},
-        "stage_ms": per_stage,
-        "stage_hbm": stage_roofline,
-        "retrieved_set": {"mean": float(rsz.mean()), "p50": float(np.percentile(rsz, 50)),
-                          "p99": float(np.percentile(rsz, 99)), "max": float(rsz.max()),
-                          "pruned_frac": float(1.0 - rsz.mean() / N)},
-        "sketch_fp64_repaired_windows": repaired,
-        "mean_distinct_shingles": sum_d / N,
-        "wmh_int_index": wmh_int_index,
-        "roofline": roof,
+        "config": res["config"],
     }
+    out.update({k: v for k, v in res.items() if k not in out and k != "value"})
+    if not args.no_extra:
+        other = "index" if args.workload == "large" else "large"
+        extra, _, _ = run_workload(other, args, main=False)
+        out["other_workload"] = extra
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(X, r, draws, p, Q, min(args.cpu_sample, N))
+        log("cpu baseline")
+        out["cpu_baseline"] = cpu_baseline(cfg, args.seed, min(args.cpu_sample, cfg["N"]), Q)
     print(json.dumps(out), flush=True)
 
 

@@ -118,6 +118,33 @@ def random_walks(N: int, m: int, seed: int = 0, threads: int | None = None) -> n
     return _blocks(seed, N, m, _rw_block, threads)
 
 
+def random_walk_rows(lo: int, hi: int, m: int, seed: int = 0,
+                     threads: int | None = None) -> np.ndarray:
+    """Rows [lo, hi) of random_walks(N, m, seed) for any N >= hi, without drawing
+    the others: each block of SERIES_BLOCK series has its own stream, so only
+    the blocks that overlap [lo, hi) are drawn.  Lets a batch too large for host
+    memory be generated and uploaded piece by piece, and any sample of it be
+    drawn again on the host."""
+    b0, b1 = lo // SERIES_BLOCK, (hi + SERIES_BLOCK - 1) // SERIES_BLOCK
+    kids = _child(seed, _DATA).spawn(b1)
+    out = np.empty((hi - lo, m), dtype=np.float32)
+
+    def work(b):
+        a = b * SERIES_BLOCK
+        rows = _rw_block(kids[b], SERIES_BLOCK, m)
+        s0, s1 = max(a, lo), min(a + SERIES_BLOCK, hi)
+        out[s0 - lo:s1 - lo] = rows[s0 - a:s1 - a]
+
+    threads = threads or min(16, os.cpu_count() or 1)
+    if b1 - b0 == 1 or threads == 1:
+        for b in range(b0, b1):
+            work(b)
+    else:
+        with _fut.ThreadPoolExecutor(threads) as ex:
+            list(ex.map(work, range(b0, b1)))
+    return out
+
+
 def ecg_like(N: int, m: int, seed: int = 0, threads: int | None = None) -> np.ndarray:
     """[N, m] float32 z-normalised ECG-like series."""
     return _blocks(seed, N, m, _ecg_block, threads)

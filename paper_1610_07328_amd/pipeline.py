@@ -146,3 +146,38 @@ class QueryBatch:
         db, q = self.index.db, self.qh
         ssh.dtw_rerank(q.x, q.x_off, db.x, db.x_off, self.cand[: q.N], self.ncand[: q.N],
                        q.p.band_frac, q.p.k, ws=self.ws, out=(self.ids, self.dist))
+
+
+def exhaustive_topk(q: torch.Tensor, db_x: torch.Tensor, db_off: torch.Tensor, band_frac: float,
+                    k: int, chunk: int = ssh.MAX_C):
+    """Exact top-k of one query over every series of the database by banded DTW.
+
+    Ground truth for recall: a search that visits every series.  Only the
+    library's re-rank runs: the database is cut into rows of `chunk`
+    candidates (the query repeated once per row), each row keeps its k best by
+    (distance, id), and the survivors go through the same re-rank again until
+    one row remains.  A pair's distance does not depend on the batch it is
+    computed in, so the result is the global top-k by (distance, id).
+    Returns (ids int64 [k], dist float32 [k]) on the device.
+    """
+    dev = q.device
+    lq = q.numel()
+    N = db_off.numel() - 1
+    ids = torch.arange(N, dtype=torch.int64, device=dev)
+    while True:
+        n = ids.numel()
+        rows = max(1, (n + chunk - 1) // chunk)
+        C = min(chunk, max(n, k))
+        cand = torch.full((rows * C,), -1, dtype=torch.int64, device=dev)
+        cand[:n] = ids
+        cand = cand.view(rows, C)
+        ncand = torch.full((rows,), C, dtype=torch.int32, device=dev)
+        if n % C:
+            ncand[-1] = n % C
+        qx = q.repeat(rows)
+        qoff = torch.arange(rows + 1, dtype=torch.int64, device=dev) * lq
+        out_id, out_d = ssh.dtw_rerank(qx, qoff, db_x, db_off, cand, ncand, band_frac, k)
+        if rows == 1:
+            return out_id[0], out_d[0]
+        keep = out_id.reshape(-1)
+        ids = keep[keep >= 0]

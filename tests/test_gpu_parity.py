@@ -891,6 +891,29 @@ def test_rerank_many_pairs_multiblock_plan(ssh):
     print(f"[result] largest relative error: {worst:.3e}", flush=True)
 
 
+def test_exhaustive_topk_is_the_oracle_top_k(ssh):
+    """The exhaustive search (re-rank rounds over chunks of the whole database,
+    then over the survivors) against the oracle's top-10 over every series;
+    64-candidate chunks give three rounds over 2,000 series."""
+    _announce("exhaustive top-k over 2,000 series in 64-candidate chunks")
+    from paper_1610_07328_amd.pipeline import exhaustive_topk
+    N, m = 2000, 128
+    X = datagen.random_walks(N, m, seed=111)
+    Q, src = datagen.perturbed_queries(X, 3, 0.1, seed=111)
+    db, dboff = datagen.csr(X)
+    ddb, ddo = to_dev(db), to_dev(dboff)
+    allc = np.arange(N, dtype=np.int64)[None, :]
+    for i in range(3):
+        ids, dist = exhaustive_topk(to_dev(Q[i]), ddb, ddo, 0.05, 10, chunk=64)
+        torch.cuda.synchronize()
+        q, qoff = datagen.csr(Q[i:i + 1])
+        oids, odist, all_d = oracle.rerank(q, qoff, db, dboff, allc, np.array([N], np.int32),
+                                           0.05, 10)
+        compare_rerank(to_np(ids)[None, :], to_np(dist)[None, :], oids, odist, all_d, allc,
+                       np.array([N], np.int32))
+        assert to_np(ids)[0] == src[i]
+
+
 def test_rerank_uniform_equals_ragged_layout(ssh):
     """The same pairs computed in a uniform batch and inside a mixed-length
     batch give the same bits (a pair's result does not depend on the others)."""
