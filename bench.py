@@ -128,6 +128,9 @@ def parse():
     ap.add_argument("--latency-samples", type=int, default=200)
     ap.add_argument("--recall-queries", type=int, default=-1)
     ap.add_argument("--cpu-sample", type=int, default=100_000)
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving run")
+    ap.add_argument("--serving-only", action="store_true", help="only the serving run")
+    ap.add_argument("--serve-requests", type=int, default=6000)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run one device copy of BYTES bytes (counter calibration)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -493,6 +496,162 @@ def run_workload(name: str, args, main: bool):
     return res, cfg, Q
 
 
+SERVING = dict(
+    workload="serving: Poisson stream at 2,000 queries/s of lengths 128, 512, 1024 and 2048 "
+             "(noisy copies of stride-1 windows of one random-walk stream), against one "
+             "resident index of 1,000,000 z-normalised windows per length (4,000,000 series, "
+             "14.8 GB), W=80 delta=3 n=15, 100 CWS hashes (K=10, L=10), C=1024, DTW band 5%, "
+             "top-10; recall@10 on every 100th arrival against exhaustive DTW",
+    lengths=(128, 512, 1024, 2048), windows=1_000_000, rate=2000.0, C=1024, band=0.05,
+    arena=256 << 20, max_batch=64, slots=4)
+
+
+def run_serving(args):
+    """Continuous batching over the resident mixed-length index (paper_1610_07328_amd.serving),
+    then the plain form (one query at a time) on the same arrival trace."""
+    import torch
+
+    from paper_1610_07328_amd import datagen, ssh
+    from paper_1610_07328_amd.pipeline import HashBatch, Params, exhaustive_topk
+    from paper_1610_07328_amd.serving import (GpuExecutor, MixedIndex, Request, RingArena,
+                                              Scheduler, latency_summary)
+
+    cfg = SERVING
+    seed = args.seed
+    dev = torch.device("cuda:0")
+    p = Params(W=80, delta=3, n=15, K=10, L=10, band_frac=cfg["band"], C=cfg["C"], k=10)
+    lens, nwin = cfg["lengths"], cfg["windows"]
+    t0 = time.perf_counter()
+    stream = datagen.walk_stream(nwin + max(lens) - 1, seed=seed)
+    total = sum(lens) * nwin
+    x = torch.empty(total, dtype=torch.float32, device=dev)
+    base = 0
+    for ell in lens:
+        for lo in range(0, nwin, 1 << 17):
+            hi = min(nwin, lo + (1 << 17))
+            w = datagen.stream_windows(stream, ell, lo, hi)
+            x[base + lo * ell: base + hi * ell].copy_(torch.from_numpy(w.reshape(-1)))
+        base += ell * nwin
+    r = datagen.filter_r(p.W, seed=seed)
+    draws = datagen.cws_draws(p.n, p.H, seed=seed)
+    tables = ssh.CwsTables(*draws, p.n, device=dev)
+    t1 = time.perf_counter()
+    ix = MixedIndex(x, [(ell, nwin) for ell in lens], p, tables, r)
+    t_index = time.perf_counter() - t1
+    log(f"serving: {len(lens)} x {nwin} windows resident in {t1 - t0:.1f}s, index built in "
+        f"{t_index:.2f}s")
+    arr, cls, src, qv = datagen.stream_queries(stream, lens, nwin, args.serve_requests,
+                                               cfg["rate"], seed=seed)
+    reqs = [Request(i, float(arr[i]), int(cls[i]), qv[i]) for i in range(len(qv))]
+    ex = GpuExecutor(ix, cfg["arena"], slots=cfg["slots"], max_batch=cfg["max_batch"],
+                     max_len=max(lens))
+    # warm-up on the first 200 arrivals (kernel loading, first launches)
+    Scheduler(ex, RingArena(cfg["arena"]), cfg["max_batch"], cfg["slots"]).run(reqs[:200])
+    torch.cuda.synchronize()
+
+    def serve(max_batch, slots):
+        arena = RingArena(cfg["arena"])
+        res, st = Scheduler(ex, arena, max_batch, slots).run(reqs)
+        ssh.check_device_errors()
+        lat = latency_summary(reqs, res)
+        last = max(rr.completion for rr in res if not rr.refused)
+        return res, {"latency_ms": lat, "throughput_qps": lat["served"] / last,
+                     "batches": st.batches, "mean_batch": float(np.mean(st.batch_sizes)),
+                     "max_batch": int(max(st.batch_sizes)), "inflight_max": st.inflight_max,
+                     "arena_peak_bytes": st.arena_peak, "arena_bytes": arena.capacity,
+                     "refused": st.refused, "wall_s": st.wall}
+
+    res, batched = serve(cfg["max_batch"], cfg["slots"])
+    log(f"serving: p50 {batched['latency_ms']['p50']:.3f} ms, p99 "
+        f"{batched['latency_ms']['p99']:.3f} ms, {batched['batches']} batches")
+    res_plain, plain = serve(1, 1)
+    log(f"serving, plain form: p50 {plain['latency_ms']['p50']:.3f} ms, p99 "
+        f"{plain['latency_ms']['p99']:.3f} ms")
+    same = all(np.array_equal(a.ids, b.ids) and np.array_equal(a.dist.view(np.uint32),
+                                                                 b.dist.view(np.uint32))
+               for a, b in zip(res, res_plain))
+
+    # capacity: every request of a burst arrives at once
+    burst = [Request(q.rid, 0.0, q.cls, q.values) for q in reqs[:2000]]
+
+    def capacity(max_batch, slots):
+        res_b, st = Scheduler(ex, RingArena(cfg["arena"]), max_batch, slots).run(burst)
+        last = max(rr.completion for rr in res_b)
+        return {"requests": len(burst), "makespan_s": last, "throughput_qps": len(burst) / last,
+                "mean_batch": float(np.mean(st.batch_sizes))}
+
+    cap_batched = capacity(cfg["max_batch"], cfg["slots"])
+    cap_plain = capacity(1, 1)
+    log(f"serving capacity: {cap_batched['throughput_qps']:.0f} q/s batched, "
+        f"{cap_plain['throughput_qps']:.0f} q/s one at a time")
+
+    # recall@10 on every 100th arrival against exhaustive DTW over the class's windows
+    t_r = time.perf_counter()
+    offs_c = np.concatenate([[0], np.cumsum([ell * nwin for ell in lens])])
+    sample = [q for q in reqs if q.rid % 100 == 0]
+    truth = {}
+    src_in = 0
+    for j, q in enumerate(sample):
+        ell = lens[q.cls]
+        dbx = x[offs_c[q.cls]:offs_c[q.cls + 1]]
+        dbo = torch.arange(nwin + 1, dtype=torch.int64, device=dev) * ell
+        ex_id, ex_d = exhaustive_topk(torch.as_tensor(q.values).to(dev), dbx, dbo, p.band_frac,
+                                      p.k)
+        ex_id, ex_d = ex_id.cpu().numpy(), ex_d.cpu().numpy()
+        truth[q.rid] = set(ex_id.tolist()) - {-1}
+        src_in += int(src[q.rid] in truth[q.rid])
+    # how many of the 100 hash values each sampled query shares with its source
+    # window: the MinHash estimate of their weighted Jaccard similarity, which
+    # sets the chance that a table's K values all agree
+    qx = np.concatenate([q.values for q in sample])
+    qoff = np.concatenate([[0], np.cumsum([len(q.values) for q in sample])]).astype(np.int64)
+    hb = HashBatch(torch.as_tensor(qx).to(dev), qoff, p)
+    hb.run(r, tables)
+    agree = [float((hb.hv[j] == ix.hv[int(ix.base[q.cls] + src[q.rid])]).float().mean())
+             for j, q in enumerate(sample)]
+    del hb
+
+    def recall_of(answers):
+        hits = sum(len(truth[q.rid] & (set(answers[q.rid].tolist()) - {-1})) for q in sample)
+        return hits / max(sum(len(truth[q.rid]) for q in sample), 1)
+
+    recall = {"recall_at_10": recall_of({q.rid: res[q.rid].ids for q in sample}),
+              "queries": len(sample),
+              "exhaustive_top10_holds_source": src_in / max(len(sample), 1),
+              "hash_agreement_with_source": {"mean": float(np.mean(agree)),
+                                             "median": float(np.median(agree))}}
+    # the same sample through the paper's own table setting: 20 tables, each
+    # keyed by one weighted MinHash (K = 1, L = 20), on a second resident index
+    pp = Params(W=80, delta=3, n=15, K=1, L=20, band_frac=cfg["band"], C=cfg["C"], k=10)
+    draws20 = datagen.cws_draws(pp.n, pp.H, seed=seed)
+    tables20 = ssh.CwsTables(*draws20, pp.n, device=dev)
+    ix20 = MixedIndex(x, [(ell, nwin) for ell in lens], pp, tables20, r)
+    ex20 = GpuExecutor(ix20, cfg["arena"], slots=1, max_batch=len(sample), max_len=max(lens))
+    ex20.start(time.perf_counter())
+    h = ex20.launch(sample, 0, 0)
+    torch.cuda.synchronize()
+    ssh.check_device_errors()
+    ans20 = {rr.rid: rr.ids for rr in ex20.finish(h)}
+    recall["paper_tables_K1_L20"] = {"recall_at_10": recall_of(ans20), "queries": len(sample)}
+    recall["seconds"] = time.perf_counter() - t_r
+    log(f"serving: recall@10 {recall['recall_at_10']:.3f} (K=10, L=10), "
+        f"{recall['paper_tables_K1_L20']['recall_at_10']:.3f} (K=1, L=20) on {len(sample)} queries")
+    del ex20, ix20, tables20
+    out = {"config": {"workload": cfg["workload"], "lengths": list(lens), "windows": nwin,
+                      "rate_qps": cfg["rate"], "requests": len(reqs), "C": p.C,
+                      "band_frac": p.band_frac, "k": p.k, "max_batch": cfg["max_batch"],
+                      "slots": cfg["slots"], "arena_bytes": cfg["arena"]},
+           "continuous_batching": batched, "plain_one_at_a_time": plain,
+           "same_answers_batched_and_plain": bool(same),
+           "capacity_burst": {"continuous_batching": cap_batched, "plain_one_at_a_time": cap_plain},
+           "recall": recall,
+           "index_build_s": t_index}
+    del ex, ix, x, tables
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -508,6 +667,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.serving_only:
+        print(json.dumps({"serving": run_serving(args)}), flush=True)
+        return
 
     res, cfg, Q = run_workload(args.workload, args, main=True)
     out = {
@@ -530,6 +692,9 @@ def main():
         other = "index" if args.workload == "large" else "large"
         extra, _, _ = run_workload(other, args, main=False)
         out["other_workload"] = extra
+    if not args.no_serving:
+        out["serving"] = run_serving(args)
+        out["query_latency_ms_served"] = out["serving"]["continuous_batching"]["latency_ms"]
     if not args.no_cpu_baseline:
         log("cpu baseline")
         out["cpu_baseline"] = cpu_baseline(cfg, args.seed, min(args.cpu_sample, cfg["N"]), Q)

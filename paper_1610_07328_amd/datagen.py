@@ -205,6 +205,60 @@ def cws_draws(n: int, H: int, seed: int = 0):
     return r, np.log(c), beta
 
 
+def walk_stream(length: int, seed: int = 0) -> np.ndarray:
+    """One random-walk stream x_t = x_{t-1} + N(0, 1) of `length` samples
+    (float64, not normalised): the recording that subsequence search cuts into
+    windows (Experiments: every length-l window of a long series)."""
+    return np.cumsum(_rng(seed, _DATA).standard_normal(length))
+
+
+def stream_windows(stream: np.ndarray, ell: int, lo: int, hi: int,
+                   threads: int | None = None) -> np.ndarray:
+    """Windows stream[s : s + ell] for s in [lo, hi), each z-normalised in
+    float64 (population sigma) and stored as float32: [hi - lo, ell]."""
+    from numpy.lib.stride_tricks import sliding_window_view
+    win = sliding_window_view(stream, ell)
+    out = np.empty((hi - lo, ell), dtype=np.float32)
+    step = max(1, (1 << 22) // ell)
+
+    def work(a):
+        b = min(hi, a + step)
+        out[a - lo:b - lo] = znorm(win[a:b]).astype(np.float32)
+
+    starts = range(lo, hi, step)
+    threads = threads or min(16, os.cpu_count() or 1)
+    if len(starts) == 1 or threads == 1:
+        for a in starts:
+            work(a)
+    else:
+        with _fut.ThreadPoolExecutor(threads) as ex:
+            list(ex.map(work, starts))
+    return out
+
+
+def stream_queries(stream: np.ndarray, lengths, n_windows: int, count: int, rate: float,
+                   noise_std: float = 0.1, seed: int = 0):
+    """A Poisson query stream over the windows of `stream`.
+
+    Arrival gaps are exponential with mean 1/rate; each query's length is drawn
+    uniformly from `lengths` and its source window uniformly from the first
+    n_windows windows of that length; the query is znorm(window +
+    N(0, noise_std^2)), the window itself z-normalised first.  Returns
+    (arrivals [count] s, class index [count], source window [count], list of
+    float32 query arrays)."""
+    arrivals = poisson_arrivals(rate, count, seed)
+    g = _rng(seed, _LENGTHS)
+    cls = g.integers(0, len(lengths), size=count)
+    gq = _rng(seed, _QUERY)
+    src = gq.integers(0, n_windows, size=count)
+    out = []
+    for c, s in zip(cls, src):
+        ell = lengths[c]
+        w = znorm(stream[s:s + ell][None, :])[0]
+        out.append(znorm((w + gq.normal(0.0, noise_std, size=ell))[None, :])[0].astype(np.float32))
+    return arrivals, cls.astype(np.int64), src.astype(np.int64), out
+
+
 def poisson_arrivals(rate: float, count: int, seed: int = 0) -> np.ndarray:
     """Arrival times (s) of a Poisson stream with exponential gaps."""
     g = _rng(seed, _ARRIVAL)

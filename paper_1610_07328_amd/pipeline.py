@@ -35,7 +35,8 @@ class Params:
 class HashBatch:
     """Device buffers for sketch -> shingle -> CWS -> band keys of one ragged batch."""
 
-    def __init__(self, x: torch.Tensor, x_off_host: np.ndarray, p: Params):
+    def __init__(self, x: torch.Tensor, x_off_host: np.ndarray, p: Params, out=None):
+        """out: optional (hv [N, H], keys [N, L]) device views to hash into."""
         dev = x.device
         self.p = p
         self.N = len(x_off_host) - 1
@@ -55,8 +56,11 @@ class HashBatch:
         self.codes = torch.empty(cap, dtype=torch.uint32, device=dev)
         self.counts = torch.empty(cap, dtype=torch.uint32, device=dev)
         self.ndist = torch.empty(N1, dtype=torch.int32, device=dev)
-        self.hv = torch.empty((N1, p.H), dtype=torch.uint64, device=dev)
-        self.keys = torch.empty((N1, p.L), dtype=torch.uint64, device=dev)
+        if out is not None:
+            self.hv, self.keys = out
+        else:
+            self.hv = torch.empty((N1, p.H), dtype=torch.uint64, device=dev)
+            self.keys = torch.empty((N1, p.L), dtype=torch.uint64, device=dev)
 
     # individual stages (return nothing; results stay in the buffers)
     def sketch(self, r: np.ndarray):
@@ -70,13 +74,16 @@ class HashBatch:
     def cws(self, tables: ssh.CwsTables):
         ssh.cws(self.codes, self.counts, self.hoff, self.ndist, tables, out=self.hv)
 
-    def band_keys(self):
-        ssh.band_keys(self.hv[: self.N], self.p.K, self.p.L, self.p.key_seed, out=self.keys)
+    def band_keys(self, seed: int | None = None):
+        ssh.band_keys(self.hv[: self.N], self.p.K, self.p.L,
+                      self.p.key_seed if seed is None else seed, out=self.keys)
 
-    def cws_band_keys(self, tables: ssh.CwsTables):
-        """CWS and band keys in one kernel pass (same results as cws() then band_keys())."""
+    def cws_band_keys(self, tables: ssh.CwsTables, seed: int | None = None):
+        """CWS and band keys in one kernel pass (same results as cws() then band_keys());
+        seed overrides the band-key seed of the parameters."""
         ssh.cws_band_keys(self.codes, self.counts, self.hoff, self.ndist, tables, self.p.K,
-                          self.p.L, self.p.key_seed, out=(self.hv, self.keys))
+                          self.p.L, self.p.key_seed if seed is None else seed,
+                          out=(self.hv, self.keys))
 
     def wmh_int_band_keys(self):
         """Integer-replication MinHash, then band keys: the hash values and keys
