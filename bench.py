@@ -130,6 +130,8 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=100_000)
     ap.add_argument("--no-serving", action="store_true", help="skip the serving run")
     ap.add_argument("--serving-only", action="store_true", help="only the serving run")
+    ap.add_argument("--no-uneven", action="store_true", help="skip the uneven-batch run")
+    ap.add_argument("--uneven-only", action="store_true", help="only the uneven-batch run")
     ap.add_argument("--serve-requests", type=int, default=6000)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run one device copy of BYTES bytes (counter calibration)")
@@ -496,6 +498,104 @@ def run_workload(name: str, args, main: bool):
     return res, cfg, Q
 
 
+UNEVEN = dict(
+    workload="uneven batch: 200,000 series of lengths uniform in [256, 8192] (even ids random "
+             "walk, odd ECG-like), fp32; W=80 delta=3 n=15, 100 CWS hashes (K=10, L=10); one "
+             "launch per stage, autotuned sketch work item and series order, build captured in "
+             "a HIP graph",
+    N=200_000, lo=256, hi=8192, plain_sample=2000)
+
+
+def run_uneven(args):
+    """The batched index build of an uneven batch (paper_1610_07328_amd.batching): tuned,
+    graph-captured and replayed, against eager launches, the untuned default and the plain
+    per-series form."""
+    import torch
+
+    from paper_1610_07328_amd import datagen, ssh
+    from paper_1610_07328_amd.batching import TuneCache, UnevenBuild, autotune
+    from paper_1610_07328_amd.pipeline import HashBatch, Params
+
+    cfg = UNEVEN
+    seed = args.seed
+    p = Params(W=80, delta=3, n=15, K=10, L=10)
+    t0 = time.perf_counter()
+    x, off = datagen.ragged_series(cfg["N"], cfg["lo"], cfg["hi"], seed=seed)
+    N, samples = len(off) - 1, int(off[-1])
+    r = datagen.filter_r(p.W, seed=seed)
+    tables = ssh.CwsTables(*datagen.cws_draws(p.n, p.H, seed=seed), p.n)
+    log(f"uneven: {N} series ({samples} samples) generated in {time.perf_counter() - t0:.1f}s")
+    t1 = time.perf_counter()
+    cache = TuneCache()
+    choice, hit = autotune(x, off, p, tables, r, cache)
+    t_tune = time.perf_counter() - t1
+    _, hit_again = autotune(x, off, p, tables, r, TuneCache(cache.path))
+    log(f"uneven: tuner chose {choice['order']} / {choice['tile_rows']} rows "
+        f"({'cache' if hit else 'timed'}, {t_tune:.1f}s)")
+
+    def timed(fn, reps=10):
+        return event_ms(fn, reps)
+
+    b = UnevenBuild(x, off, p, tables, r, order=choice["order"], tile_rows=choice["tile_rows"])
+    t_eager = timed(b.run)
+    b.capture()
+    t_graph = timed(b.replay)
+    # hashing stages alone (the part a per-series form can do)
+    db = b.db
+
+    def hash_only():
+        ssh.sketch(db.x, db.x_off, r, p.W, p.delta, db.bwo, out=(db.bits, db.nbits, db.repair),
+                   tile_rows=b.tile_rows)
+        db.shingle()
+        db.cws_band_keys(tables)
+
+    t_hash = timed(hash_only)
+    hv_batch = b.hv().cpu().numpy()
+    del b, db
+    torch.cuda.empty_cache()
+    d = UnevenBuild(x, off, p, tables, r)
+    t_default = timed(d.run)
+    del d
+    torch.cuda.empty_cache()
+    # the plain per-series form: one launch sequence per series, on a sample
+    rng = np.random.default_rng(seed + 3)
+    pick = rng.choice(N, cfg["plain_sample"], replace=False)
+    singles = []
+    for s in pick:
+        hb = HashBatch(torch.as_tensor(x[off[s]:off[s + 1]]).cuda(),
+                       np.array([0, off[s + 1] - off[s]], np.int64), p)
+        singles.append(hb)
+    torch.cuda.synchronize()
+
+    def plain():
+        for hb in singles:
+            hb.run(r, tables)
+
+    t_plain = timed(plain, reps=2)
+    same = all(np.array_equal(hb.hv[0].cpu().numpy(), hv_batch[s]) for hb, s in zip(singles, pick))
+    plain_samples = int(sum(off[s + 1] - off[s] for s in pick))
+    del singles
+    torch.cuda.empty_cache()
+    out = {"config": {"workload": cfg["workload"], "n_series": N, "samples": samples,
+                      "W": p.W, "delta": p.delta, "n": p.n, "K": p.K, "L": p.L},
+           "tuner": {"order": choice["order"], "tile_rows": choice["tile_rows"],
+                     "build_ms_by_choice": choice["build_ms"], "seconds": t_tune,
+                     "cache_hit_first": hit, "cache_hit_second": hit_again, "cache": cache.path},
+           "graph_build_ms": t_graph, "eager_build_ms": t_eager, "default_build_ms": t_default,
+           "series_per_s": N / (t_graph / 1e3), "samples_per_s": samples / (t_graph / 1e3),
+           "batched_hash_ms": t_hash, "batched_hash_series_per_s": N / (t_hash / 1e3),
+           "plain_per_series": {"series": len(pick), "ms": t_plain,
+                                "series_per_s": len(pick) / (t_plain / 1e3),
+                                "samples_per_s": plain_samples / (t_plain / 1e3)},
+           "batched_over_plain": (N / (t_hash / 1e3)) / (len(pick) / (t_plain / 1e3)),
+           "plain_equals_batched": bool(same)}
+    log(f"uneven: graph build {t_graph:.2f} ms ({out['series_per_s']:.3e} series/s), "
+        f"plain per-series {out['plain_per_series']['series_per_s']:.3e} series/s")
+    del tables
+    torch.cuda.empty_cache()
+    return out
+
+
 SERVING = dict(
     workload="serving: Poisson stream at 2,000 queries/s of lengths 128, 512, 1024 and 2048 "
              "(noisy copies of stride-1 windows of one random-walk stream), against one "
@@ -670,6 +770,9 @@ def main():
     if args.serving_only:
         print(json.dumps({"serving": run_serving(args)}), flush=True)
         return
+    if args.uneven_only:
+        print(json.dumps({"uneven_batch": run_uneven(args)}), flush=True)
+        return
 
     res, cfg, Q = run_workload(args.workload, args, main=True)
     out = {
@@ -692,6 +795,8 @@ def main():
         other = "index" if args.workload == "large" else "large"
         extra, _, _ = run_workload(other, args, main=False)
         out["other_workload"] = extra
+    if not args.no_uneven:
+        out["uneven_batch"] = run_uneven(args)
     if not args.no_serving:
         out["serving"] = run_serving(args)
         out["query_latency_ms_served"] = out["serving"]["continuous_batching"]["latency_ms"]

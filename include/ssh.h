@@ -339,6 +339,18 @@ ssh_status ssh_sketch_generic(const float* x, const int64_t* x_off, int64_t N, c
                               const int64_t* bit_word_off, int32_t* nbits, uint64_t* repair_count,
                               void* stream);
 
+/* ssh_sketch with the size of the matrix-core path's work item chosen by the
+ * caller (Section 4.1; the same bits whatever the choice): an item is
+ * tile_rows rows of 16 windows of one series, tile_rows in {8, 12, 16, 20},
+ * for the (W, delta) shapes that have a matrix-core kernel: (80, 3), (64, 4),
+ * (128, 4), (30, 5).  Smaller items waste less of a series' last item, larger
+ * ones amortise more per item; ssh_sketch uses 20 rows for (80, 3) and 16
+ * otherwise.  Returns SSH_EUNSUPPORTED for any other shape or row count. */
+ssh_status ssh_sketch_tiled(const float* x, const int64_t* x_off, int64_t N, const float* r,
+                            int32_t W, int32_t delta, uint64_t* bits, const int64_t* bit_word_off,
+                            int32_t* nbits, uint64_t* repair_count, int32_t tile_rows,
+                            void* stream);
+
 /* [host] Synchronise the device and collect the error flags that kernels raise
  * for inconsistent device-side arguments since the last call (offsets whose
  * capacity is too small, candidate ids outside [0, N), a DTW band radius above

@@ -25,7 +25,9 @@ ssh_status check_launch(const char* what) {
 // kernels (other translation units)
 ssh_status sketch_launch(const float* x, const int64_t* x_off, int64_t N, const float* r, int W,
                          int delta, uint64_t* bits, const int64_t* bit_word_off, int32_t* nbits,
-                         uint64_t* repair_count, hipStream_t stream, bool force_generic);
+                         uint64_t* repair_count, hipStream_t stream, bool force_generic,
+                         int tile_rows);
+bool sketch_tile_supported(int W, int delta, int rows);
 ssh_status shingle_launch(const uint64_t* bits, const int64_t* bit_word_off, const int32_t* nbits,
                           int64_t N, int n, uint32_t* codes, uint32_t* counts,
                           const int64_t* hist_off, int32_t* n_distinct, hipStream_t stream);
@@ -136,7 +138,7 @@ ssh_status ssh_sketch(const float* x, const int64_t* x_off, int64_t N, const flo
   if (N == 0) return SSH_OK;
   SSH_REQUIRE(x && x_off && bits && bit_word_off && nbits, "ssh_sketch: null pointer");
   return sketch_launch(x, x_off, N, r, W, delta, bits, bit_word_off, nbits, repair_count,
-                       as_stream(stream), false);
+                       as_stream(stream), false, 0);
 }
 
 // Same as ssh_sketch but always through the generic kernel (any W, delta);
@@ -152,7 +154,24 @@ ssh_status ssh_sketch_generic(const float* x, const int64_t* x_off, int64_t N, c
   if (N == 0) return SSH_OK;
   SSH_REQUIRE(x && x_off && bits && bit_word_off && nbits, "ssh_sketch: null pointer");
   return sketch_launch(x, x_off, N, r, W, delta, bits, bit_word_off, nbits, repair_count,
-                       as_stream(stream), true);
+                       as_stream(stream), true, 0);
+}
+
+ssh_status ssh_sketch_tiled(const float* x, const int64_t* x_off, int64_t N, const float* r,
+                            int32_t W, int32_t delta, uint64_t* bits, const int64_t* bit_word_off,
+                            int32_t* nbits, uint64_t* repair_count, int32_t tile_rows,
+                            void* stream) {
+  SSH_REQUIRE(N >= 0 && N <= (int64_t)UINT32_MAX, "ssh_sketch_tiled: N out of [0, 2^32)");
+  SSH_REQUIRE(W >= 1 && W <= SSH_MAX_W, "ssh_sketch_tiled: W out of [1, SSH_MAX_W]");
+  SSH_REQUIRE(delta >= 1, "ssh_sketch_tiled: delta < 1");
+  SSH_REQUIRE(r, "ssh_sketch_tiled: null filter");
+  if (!sketch_tile_supported(W, delta, tile_rows))
+    return fail(SSH_EUNSUPPORTED, "ssh_sketch_tiled: no matrix-core work item of that many rows "
+                                  "for this (W, delta)");
+  if (N == 0) return SSH_OK;
+  SSH_REQUIRE(x && x_off && bits && bit_word_off && nbits, "ssh_sketch_tiled: null pointer");
+  return sketch_launch(x, x_off, N, r, W, delta, bits, bit_word_off, nbits, repair_count,
+                       as_stream(stream), false, tile_rows);
 }
 
 ssh_status ssh_shingle(const uint64_t* bits, const int64_t* bit_word_off, const int32_t* nbits,

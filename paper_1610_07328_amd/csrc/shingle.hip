@@ -12,8 +12,9 @@
 //      first token (16-bit), and the total is the number D of distinct tokens;
 //   3. each token's rank is its word's base plus the popcount of the lower
 //      bits of its word; runs of equal tokens inside a lane are counted once
-//      with their length (LDS atomic add, or a global one when D exceeds the
-//      LDS count buffer), and the token is written at its rank of `codes`,
+//      with their length (LDS atomic add on 16-bit halves, or a global one
+//      when D exceeds the LDS count buffer or the series has 2^16 shingles or
+//      more), and the token is written at its rank of `codes`,
 //      so tokens come out ascending without sorting;
 //   4. counts are copied out and the bitmap and counts are cleared.
 // Lane L's bitmap words sit in a padded per-lane run, read and cleared with
@@ -27,7 +28,10 @@
 
 namespace ssh {
 
-constexpr int kCountCap = 256;  // distinct tokens whose counts stay in LDS
+// Distinct tokens whose counts stay in LDS, two 16-bit counts per 32-bit word
+// (exact while the series has fewer than 2^16 shingles, the only case that
+// uses them: every count is at most the shingle count).
+constexpr int kCountCap = 512;
 constexpr int kShWaves = 1;     // wavefronts per workgroup
 
 __host__ __device__ inline int shingle_bitmap_words(int n) { return n > 5 ? 1 << (n - 5) : 1; }
@@ -49,7 +53,7 @@ __host__ __device__ inline size_t shingle_lds_bytes(int n) {
   const int wpl = shingle_wpl(n);
   const size_t bm = (size_t)kWave * shingle_bs(wpl) * 4;
   const size_t pre = ((size_t)shingle_pre_u16(wpl) * 2 + 15) & ~(size_t)15;
-  return bm + pre + (size_t)kCountCap * 4;
+  return bm + pre + (size_t)kCountCap * 2;
 }
 
 // 32 stream bits starting at bit b0 (bit j of the result is stream bit b0 + j),
@@ -97,7 +101,7 @@ __global__ __launch_bounds__(kShWaves * kWave) void shingle_kernel(
   uint32_t* mybm = bm + lane * BS;
   uint16_t* mypre = PAD ? reinterpret_cast<uint16_t*>(mybm + WPL) : pre + lane * WPL;
   for (int i = lane; i < kWave * BS; i += kWave) bm[i] = 0;
-  for (int i = lane; i < kCountCap; i += kWave) cnt[i] = 0;
+  for (int i = lane; i < kCountCap / 2; i += kWave) cnt[i] = 0;
   wave_sync_lds();
   const uint32_t mask = (1u << n) - 1u;  // n <= 16
   // slot of word wd, and the rank of its first token
@@ -208,7 +212,7 @@ __global__ __launch_bounds__(kShWaves * kWave) void shingle_kernel(
       if (own) mypre[0] = pv[0];
     }
     const uint32_t D = __builtin_amdgcn_readlane(incl, kWave - 1);
-    const bool in_lds = D <= (uint32_t)kCountCap;
+    const bool in_lds = D <= (uint32_t)kCountCap && S < 65536;
     if (!in_lds) {
       for (uint32_t i = lane; i < D; i += kWave) counts_s[i] = 0;
       // this wave's zero stores complete before its atomics below
@@ -225,7 +229,7 @@ __global__ __launch_bounds__(kShWaves * kWave) void shingle_kernel(
         const uint32_t wd = t >> 5;
         const uint32_t rank =
             word_rank(wd) + __builtin_popcount(bm[bslot(wd)] & ((1u << (t & 31)) - 1u));
-        if constexpr (LDS_COUNTS) atomicAdd(cnt + rank, run);
+        if constexpr (LDS_COUNTS) atomicAdd(cnt + (rank >> 1), run << ((rank & 1u) * 16u));
         else atomicAdd(counts_s + rank, run);
         codes_s[rank] = t;
       };
@@ -257,10 +261,9 @@ __global__ __launch_bounds__(kShWaves * kWave) void shingle_kernel(
 
     // 4. counts out; clear the bitmap words and counts that were used
     if (in_lds) {
-      for (uint32_t i = lane; i < D; i += kWave) {
-        counts_s[i] = cnt[i];
-        cnt[i] = 0;
-      }
+      for (uint32_t i = lane; i < D; i += kWave) counts_s[i] = (cnt[i >> 1] >> ((i & 1u) * 16u)) & 0xFFFFu;
+      wave_sync_lds();
+      for (uint32_t i = lane; i < (D + 1) / 2; i += kWave) cnt[i] = 0;
     }
     if constexpr (WPL >= 4) {
 #pragma unroll

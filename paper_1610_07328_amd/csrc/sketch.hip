@@ -601,9 +601,39 @@ static unsigned resident_grid(const void* kernel, int64_t N) {
   return grid_for(N, kWavesPerBlock, cap);
 }
 
+template <int WW, int DD, int RR>
+static void launch_fast(const FilterArgs& fa, const float* x, const int64_t* x_off, int64_t N,
+                        uint64_t* bits, const int64_t* bit_word_off, int32_t* nbits,
+                        unsigned long long* rc, int* err, hipStream_t stream) {
+  const dim3 blk(256);
+  if (fa.l1) {
+    const unsigned g = resident_grid(
+        reinterpret_cast<const void*>(&sketch_mfma_kernel<WW, DD, RR, true>), N);
+    sketch_mfma_kernel<WW, DD, RR, true><<<g, blk, 0, stream>>>(x, x_off, N, fa, bits,
+                                                                 bit_word_off, nbits, rc, err);
+  } else {
+    const unsigned g = resident_grid(
+        reinterpret_cast<const void*>(&sketch_mfma_kernel<WW, DD, RR, false>), N);
+    sketch_mfma_kernel<WW, DD, RR, false><<<g, blk, 0, stream>>>(x, x_off, N, fa, bits,
+                                                                  bit_word_off, nbits, rc, err);
+  }
+}
+
+// Work-item sizes (rows of 16 windows) offered on the matrix-core path, and
+// each shape's default: 20 rows hold the 315 windows of a 1024-sample series
+// (W = 80, delta = 3) in one item.
+bool sketch_tile_supported(int W, int delta, int rows) {
+  const bool fast = (W == 80 && delta == 3) || (W == 64 && delta == 4) ||
+                    (W == 128 && delta == 4) || (W == 30 && delta == 5);
+  return fast && (rows == 8 || rows == 12 || rows == 16 || rows == 20);
+}
+
+static int default_rows(int W, int delta) { return W == 80 && delta == 3 ? 20 : 16; }
+
 ssh_status sketch_launch(const float* x, const int64_t* x_off, int64_t N, const float* r, int W,
                          int delta, uint64_t* bits, const int64_t* bit_word_off, int32_t* nbits,
-                         uint64_t* repair_count, hipStream_t stream, bool force_generic) {
+                         uint64_t* repair_count, hipStream_t stream, bool force_generic,
+                         int tile_rows) {
   FilterArgs fa;
   ssh_status st = make_filter_args(r, W, delta, fa);
   if (st != SSH_OK) return st;
@@ -614,27 +644,21 @@ ssh_status sketch_launch(const float* x, const int64_t* x_off, int64_t N, const 
   unsigned long long* rc = reinterpret_cast<unsigned long long*>(repair_count);
   const unsigned grid = grid_for(N, kWavesPerBlock, 1 << 16);
   const dim3 blk(256);
-#define SSH_FAST(WW, DD, RR)                                                                   \
+  const int rows = tile_rows > 0 ? tile_rows : default_rows(W, delta);
+#define SSH_FAST(WW, DD)                                                                       \
   if (!force_generic && W == WW && delta == DD) {                                              \
-    if (fa.l1) {                                                                               \
-      const unsigned fgrid = resident_grid(reinterpret_cast<const void*>(                      \
-          &sketch_mfma_kernel<WW, DD, RR, true>), N);                                          \
-      sketch_mfma_kernel<WW, DD, RR, true><<<fgrid, blk, 0, stream>>>(                         \
-          x, x_off, N, fa, bits, bit_word_off, nbits, rc, err);                                \
-    } else {                                                                                   \
-      const unsigned fgrid = resident_grid(reinterpret_cast<const void*>(                      \
-          &sketch_mfma_kernel<WW, DD, RR, false>), N);                                         \
-      sketch_mfma_kernel<WW, DD, RR, false><<<fgrid, blk, 0, stream>>>(                        \
-          x, x_off, N, fa, bits, bit_word_off, nbits, rc, err);                                \
+    switch (rows) {                                                                            \
+      case 8: launch_fast<WW, DD, 8>(fa, x, x_off, N, bits, bit_word_off, nbits, rc, err, stream); break; \
+      case 12: launch_fast<WW, DD, 12>(fa, x, x_off, N, bits, bit_word_off, nbits, rc, err, stream); break; \
+      case 16: launch_fast<WW, DD, 16>(fa, x, x_off, N, bits, bit_word_off, nbits, rc, err, stream); break; \
+      default: launch_fast<WW, DD, 20>(fa, x, x_off, N, bits, bit_word_off, nbits, rc, err, stream); break; \
     }                                                                                          \
     return check_launch("ssh_sketch");                                                         \
   }
-  // rows of 16 windows per item: 20 rows hold the 315 windows of a 1024-sample
-  // series (W = 80, delta = 3) in one item
-  SSH_FAST(80, 3, 20)
-  SSH_FAST(64, 4, 16)
-  SSH_FAST(128, 4, 16)
-  SSH_FAST(30, 5, 16)
+  SSH_FAST(80, 3)
+  SSH_FAST(64, 4)
+  SSH_FAST(128, 4)
+  SSH_FAST(30, 5)
 #undef SSH_FAST
   const int XCAP = (kWave - 1) * delta + W + 2;
   const size_t per_wave = (size_t)XCAP * 4 + 2 * 2 * kWave * 4 + 2 * 4 + 4;

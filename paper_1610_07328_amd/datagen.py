@@ -75,18 +75,22 @@ def _ecg_block(ss: np.random.SeedSequence, rows: int, m: int) -> np.ndarray:
     t = np.arange(m, dtype=np.float64)
     out = np.empty((rows, m), dtype=np.float32)
     npulse = m // 180 + 3
+    lag = np.arange(81)
     for i in range(rows):
         tau0 = g.uniform(0.0, 200.0)
         gaps = g.uniform(180.0, 220.0, size=npulse)
         taus = tau0 + np.concatenate(([0.0], np.cumsum(gaps[:-1])))
         amps = g.uniform(0.8, 1.2, size=npulse)
         phi = g.uniform(0.0, 2.0 * np.pi)
+        # pulse p covers samples [max(0, tau - 40), min(m, tau + 41)); pulses are
+        # at least 180 samples apart, so no sample gets two of them
+        lo = np.maximum(0.0, taus - 40.0).astype(np.int64)
+        hi = np.minimum(float(m), taus + 41.0).astype(np.int64)
+        idx = lo[:, None] + lag[None, :]
+        keep = idx < hi[:, None]
+        pi, tt = np.nonzero(keep)[0], idx[keep]
         sig = np.zeros(m)
-        for tau, a in zip(taus, amps):
-            lo, hi = int(max(0, tau - 40)), int(min(m, tau + 41))
-            if lo < hi:
-                tt = t[lo:hi]
-                sig[lo:hi] += a * np.exp(-((tt - tau) ** 2) / (2.0 * 36.0))
+        sig[tt] = amps[pi] * np.exp(-((t[tt] - taus[pi]) ** 2) / (2.0 * 36.0))
         sig += 0.3 * np.sin(2.0 * np.pi * t / 2000.0 + phi)
         sig += g.normal(0.0, 0.05, size=m)
         out[i] = znorm(sig[None, :])[0].astype(np.float32)
@@ -150,20 +154,55 @@ def ecg_like(N: int, m: int, seed: int = 0, threads: int | None = None) -> np.nd
     return _blocks(seed, N, m, _ecg_block, threads)
 
 
-def ragged_series(N: int, m_lo: int, m_hi: int, seed: int = 0):
+def _ragged_fill(args):
+    """Worker of ragged_series: series [a, b) into the shared value array."""
+    from multiprocessing import shared_memory
+    name, total, seed, N, a, b, lens, offs = args
+    shm = shared_memory.SharedMemory(name=name)
+    try:
+        x = np.ndarray((total,), dtype=np.float32, buffer=shm.buf)
+        kids = _child(seed, _DATA).spawn(b)  # child i is the same whatever the count
+        for i in range(a, b):
+            fn = _rw_block if i % 2 == 0 else _ecg_block
+            x[offs[i - a]:offs[i - a] + lens[i - a]] = fn(kids[i], 1, int(lens[i - a]))[0]
+    finally:
+        shm.close()
+    return b - a
+
+
+def ragged_series(N: int, m_lo: int, m_hi: int, seed: int = 0, procs: int | None = None):
     """Series of lengths uniform in [m_lo, m_hi]; even ids random walk, odd ECG-like.
 
-    Returns (x: float32[sum m], x_off: int64[N + 1]).
+    Returns (x: float32[sum m], x_off: int64[N + 1]).  Large batches are drawn
+    by worker processes into shared memory (each series has its own stream,
+    so the result does not depend on how the work is split).
     """
     g = _rng(seed, _LENGTHS)
     lens = g.integers(m_lo, m_hi + 1, size=N).astype(np.int64)
     off = np.zeros(N + 1, dtype=np.int64)
     np.cumsum(lens, out=off[1:])
-    x = np.empty(int(off[-1]), dtype=np.float32)
-    kids = _child(seed, _DATA).spawn(N)
-    for i in range(N):
-        fn = _rw_block if i % 2 == 0 else _ecg_block
-        x[off[i]:off[i + 1]] = fn(kids[i], 1, int(lens[i]))[0]
+    total = int(off[-1])
+    procs = procs or min(16, os.cpu_count() or 1)
+    if N < 8192 or procs == 1:
+        x = np.empty(total, dtype=np.float32)
+        kids = _child(seed, _DATA).spawn(N)
+        for i in range(N):
+            fn = _rw_block if i % 2 == 0 else _ecg_block
+            x[off[i]:off[i + 1]] = fn(kids[i], 1, int(lens[i]))[0]
+        return x, off
+    import multiprocessing as mp
+    from multiprocessing import shared_memory
+    shm = shared_memory.SharedMemory(create=True, size=max(4 * total, 4))
+    try:
+        step = (N + 4 * procs - 1) // (4 * procs)
+        jobs = [(shm.name, total, seed, N, a, min(N, a + step), lens[a:a + step],
+                 off[a:a + step]) for a in range(0, N, step)]
+        with _fut.ProcessPoolExecutor(procs, mp_context=mp.get_context("spawn")) as ex:
+            assert sum(ex.map(_ragged_fill, jobs)) == N
+        x = np.ndarray((total,), dtype=np.float32, buffer=shm.buf).copy()
+    finally:
+        shm.close()
+        shm.unlink()
     return x, off
 
 

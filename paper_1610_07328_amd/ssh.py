@@ -52,6 +52,7 @@ SIGNATURES = {
     "ssh_plan": (_i32, [_vp, _i64, _i32, _i32, _i32, _vp, _vp, _vp]),
     "ssh_sketch": (_i32, [_vp, _vp, _i64, _vp, _i32, _i32, _vp, _vp, _vp, _vp, _vp]),
     "ssh_sketch_generic": (_i32, [_vp, _vp, _i64, _vp, _i32, _i32, _vp, _vp, _vp, _vp, _vp]),
+    "ssh_sketch_tiled": (_i32, [_vp, _vp, _i64, _vp, _i32, _i32, _vp, _vp, _vp, _vp, _i32, _vp]),
     "ssh_shingle": (_i32, [_vp, _vp, _vp, _i64, _i32, _vp, _vp, _vp, _vp, _vp]),
     "ssh_cws_prepare": (_i32, [ctypes.POINTER(_CwsTablesC), _vp]),
     "ssh_cws": (_i32, [_vp, _vp, _vp, _vp, _i64, ctypes.POINTER(_CwsTablesC), _vp, _vp]),
@@ -154,9 +155,19 @@ def check_device_errors() -> None:
 # --------------------------------------------------------------------------
 # pipeline stages
 # --------------------------------------------------------------------------
+SKETCH_TILES = (8, 12, 16, 20)
+_FAST_SHAPES = ((80, 3), (64, 4), (128, 4), (30, 5))
+
+
+def sketch_tile_supported(W: int, delta: int, rows: int) -> bool:
+    """Whether ssh_sketch_tiled offers `rows` for this (W, delta)."""
+    return (W, delta) in _FAST_SHAPES and rows in SKETCH_TILES
+
+
 def sketch(x: torch.Tensor, x_off: torch.Tensor, r: np.ndarray, W: int, delta: int,
-           bit_word_off: torch.Tensor, generic: bool = False, out=None):
-    """Returns (bits uint64 [words], nbits int32 [N], repaired uint64 [1])."""
+           bit_word_off: torch.Tensor, generic: bool = False, out=None, tile_rows: int = 0):
+    """Returns (bits uint64 [words], nbits int32 [N], repaired uint64 [1]).
+    tile_rows > 0 picks the matrix-core work item (ssh_sketch_tiled)."""
     N = x_off.numel() - 1
     dev = x.device
     total_words = int(bit_word_off[-1].item()) if out is None else None
@@ -169,11 +180,15 @@ def sketch(x: torch.Tensor, x_off: torch.Tensor, r: np.ndarray, W: int, delta: i
     r = np.ascontiguousarray(r, dtype=np.float32)
     if r.shape[0] != W:
         raise SSHError("filter length differs from W")
-    fn = lib().ssh_sketch_generic if generic else lib().ssh_sketch
-    _check(fn(_dev(x, torch.float32, "x"), _dev(x_off, torch.int64, "x_off"), N, r.ctypes.data,
-              W, delta, _dev(bits, torch.uint64, "bits"),
-              _dev(bit_word_off, torch.int64, "bit_word_off"), _dev(nbits, torch.int32, "nbits"),
-              _dev(rep, torch.uint64, "repair_count"), _stream()), "ssh_sketch")
+    args = [_dev(x, torch.float32, "x"), _dev(x_off, torch.int64, "x_off"), N, r.ctypes.data,
+            W, delta, _dev(bits, torch.uint64, "bits"),
+            _dev(bit_word_off, torch.int64, "bit_word_off"), _dev(nbits, torch.int32, "nbits"),
+            _dev(rep, torch.uint64, "repair_count")]
+    if tile_rows > 0:
+        _check(lib().ssh_sketch_tiled(*args, tile_rows, _stream()), "ssh_sketch_tiled")
+    else:
+        fn = lib().ssh_sketch_generic if generic else lib().ssh_sketch
+        _check(fn(*args, _stream()), "ssh_sketch")
     return bits, nbits[:N], rep
 
 

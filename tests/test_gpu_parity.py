@@ -187,6 +187,11 @@ def test_shingle_matches_oracle(ssh, n):
     # a stream from a real sketch (long runs)
     X = datagen.random_walks(3, 1024, seed=n)
     streams += list(oracle.sketch_batch(X, datagen.filter_r(80, seed=n), 80, 3))
+    # distinct-token counts around the LDS count buffer (512 tokens, 16-bit
+    # counts), and all-ones streams whose one token has 2^16 - 1 and 2^16
+    # occurrences (the second takes the global-count path)
+    streams += [(rng.random(L) < 0.5).astype(np.uint8) for L in (450, 520, 600)]
+    streams += [np.ones(65535 + n - 1, np.uint8), np.ones(65536 + n - 1, np.uint8)]
     words, bwo, nb = _pack_streams(streams)
     hist_off = np.zeros(len(streams) + 1, np.int64)
     np.cumsum([max(0, int(b) - n + 1) for b in nb], out=hist_off[1:])
