@@ -14,6 +14,7 @@
  *   ssh_wmh_int    weighted MinHash by integer replication, integer only
  *                  (Section 2, eq. CollProb; Section 4, one-pass hashing)
  *   ssh_table_build  the L hash tables                           (Algorithm 1)
+ *   ssh_table_insert / ssh_table_delete  the tables updated without a rebuild
  *   ssh_probe      retrieved set R of each query, ranked         (Algorithm 2)
  *   dtw_rerank     top-k of R by banded DTW distance             (Section 2.1,
  *                  last step of Algorithm 2)
@@ -229,6 +230,49 @@ size_t ssh_table_workspace_bytes(int64_t N, int32_t L);
 ssh_status ssh_table_build(const uint64_t* keys, int64_t N, int32_t L, uint64_t* tab_keys,
                            uint32_t* tab_ids, void* ws, size_t ws_bytes, void* stream);
 
+/* [host] Workspace bytes needed by ssh_table_insert for M new series. */
+size_t ssh_table_insert_workspace_bytes(int64_t M, int32_t L);
+
+/* Insert M new series into built tables (Algorithm 1's tables, updated in
+ * place of a rebuild: with data-independent hashing, Section 1, new series
+ * need no change to the hash functions or the other entries).  The new series
+ * get ids id_base .. id_base+M-1, above every id in the tables (id_base = N
+ * for tables that never lost a series); their band keys are new_keys
+ * (series-major [M * L], from ssh_band_keys or ssh_cws_band_keys).  The output
+ * tables are exactly what ssh_table_build writes for the N + M series when
+ * id_base = N: the new entries are sorted by themselves and merged.  The probe
+ * needs their keys and hash values at rows id_base .. of db_keys and db_hv.
+ *   tab_keys, tab_ids   [L * N] tables of N entries
+ *   out_keys, out_ids   [L * (N + M)] output tables, not aliasing the inputs
+ *   ws, ws_bytes        at least ssh_table_insert_workspace_bytes(M, L)
+ * Returns SSH_EUNSUPPORTED when N and N + M lie on different sides of 2^20
+ * (the tables' sort width changes there: build them again). */
+ssh_status ssh_table_insert(const uint64_t* tab_keys, const uint32_t* tab_ids, int64_t N,
+                            const uint64_t* new_keys, int64_t M, int32_t L, int64_t id_base,
+                            uint64_t* out_keys, uint32_t* out_ids, void* ws, size_t ws_bytes,
+                            void* stream);
+
+/* [host] Workspace bytes needed by ssh_table_delete for tables of N entries. */
+size_t ssh_table_delete_workspace_bytes(int64_t N, int32_t L);
+
+/* Delete series from built tables: every table keeps, in order, the entries
+ * whose id is not marked dead, so the result is the tables a build over the
+ * surviving series would give, with the surviving series keeping their ids
+ * (ids are not renumbered; the probe reads db_keys and db_hv by id, so their
+ * rows stay in place).  Probe the result with N = n_live.
+ *   tab_keys, tab_ids  [L * N] tables
+ *   dead               uint8 [id_bound]: 1 for a series to delete
+ *   n_live             number of entries every table keeps (N minus the
+ *                      number of deleted series present); a table that keeps
+ *                      another number raises a device flag
+ *   out_keys, out_ids  [L * n_live] output tables, not aliasing the inputs
+ *   ws, ws_bytes       at least ssh_table_delete_workspace_bytes(N, L)
+ * Returns SSH_EUNSUPPORTED when N and n_live lie on different sides of 2^20. */
+ssh_status ssh_table_delete(const uint64_t* tab_keys, const uint32_t* tab_ids, int64_t N, int32_t L,
+                            const uint8_t* dead, int64_t id_bound, int64_t n_live,
+                            uint64_t* out_keys, uint32_t* out_ids, void* ws, size_t ws_bytes,
+                            void* stream);
+
 /* [host] Workspace bytes needed by ssh_probe for nq queries, L tables and C
  * candidates. */
 size_t ssh_probe_workspace_bytes(int32_t nq, int32_t L, int32_t C);
@@ -355,7 +399,8 @@ ssh_status ssh_sketch_tiled(const float* x, const int64_t* x_off, int64_t N, con
  * for inconsistent device-side arguments since the last call (offsets whose
  * capacity is too small, candidate ids outside [0, N), a DTW band radius above
  * SSH_MAX_BAND, an undersized pruned re-rank workspace, CWS draws outside their
- * ranges).  The flags are cleared.  Returns SSH_OK when none was raised, else SSH_EINVAL with the
+ * ranges, table ids or live counts that do not match ssh_table_delete's
+ * arguments).  The flags are cleared.  Returns SSH_OK when none was raised, else SSH_EINVAL with the
  * detail in ssh_last_error(). */
 ssh_status ssh_check_device_errors(void);
 

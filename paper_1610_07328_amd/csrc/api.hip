@@ -39,7 +39,18 @@ ssh_status band_keys_launch(const uint64_t* hv, int64_t N, int K, int L, uint64_
                             uint64_t* keys, hipStream_t stream);
 size_t table_workspace_bytes(int64_t N, int L);
 ssh_status table_build_launch(const uint64_t* keys, int64_t N, int L, uint64_t* tab_keys,
-                              uint32_t* tab_ids, void* ws, size_t ws_bytes, hipStream_t stream);
+                              uint32_t* tab_ids, void* ws, size_t ws_bytes, hipStream_t stream,
+                              int sort_bits = 0);
+size_t table_insert_workspace_bytes(int64_t M, int L);
+ssh_status table_insert_launch(const uint64_t* tab_keys, const uint32_t* tab_ids, int64_t N,
+                               const uint64_t* new_keys, int64_t M, int L, int64_t id_base,
+                               uint64_t* out_keys, uint32_t* out_ids, void* ws, size_t ws_bytes,
+                               hipStream_t stream);
+size_t table_delete_workspace_bytes(int64_t N, int L);
+ssh_status table_delete_launch(const uint64_t* tab_keys, const uint32_t* tab_ids, int64_t N, int L,
+                               const uint8_t* dead, int64_t id_bound, int64_t n_live,
+                               uint64_t* out_keys, uint32_t* out_ids, void* ws, size_t ws_bytes,
+                               hipStream_t stream);
 ssh_status probe_launch(const uint64_t* tab_keys, const uint32_t* tab_ids, int64_t N, int L,
                         const uint64_t* db_keys, const uint64_t* db_hv, int H,
                         const uint64_t* q_keys, const uint64_t* q_hv, int nq, int C, int64_t* cand,
@@ -69,6 +80,7 @@ int take_sketch_err();
 int take_shingle_err();
 int take_cws_err();
 int take_dtw_err();
+int take_table_err();
 
 }  // namespace ssh
 
@@ -262,6 +274,48 @@ ssh_status ssh_table_build(const uint64_t* keys, int64_t N, int32_t L, uint64_t*
   return table_build_launch(keys, N, L, tab_keys, tab_ids, ws, ws_bytes, as_stream(stream));
 }
 
+size_t ssh_table_insert_workspace_bytes(int64_t M, int32_t L) {
+  if (M < 0 || L < 1) return 0;
+  return table_insert_workspace_bytes(M, L);
+}
+
+ssh_status ssh_table_insert(const uint64_t* tab_keys, const uint32_t* tab_ids, int64_t N,
+                            const uint64_t* new_keys, int64_t M, int32_t L, int64_t id_base,
+                            uint64_t* out_keys, uint32_t* out_ids, void* ws, size_t ws_bytes,
+                            void* stream) {
+  SSH_REQUIRE(N >= 0 && M >= 0 && N + M <= (int64_t)UINT32_MAX,
+              "ssh_table_insert: N + M out of [0, 2^32)");
+  SSH_REQUIRE(id_base >= N && id_base + M <= (int64_t)UINT32_MAX,
+              "ssh_table_insert: id_base below N or ids past 2^32 - 1");
+  SSH_REQUIRE(L >= 1, "ssh_table_insert: L < 1");
+  if (N + M == 0) return SSH_OK;
+  SSH_REQUIRE(out_keys && out_ids && ws, "ssh_table_insert: null pointer");
+  SSH_REQUIRE(N == 0 || (tab_keys && tab_ids), "ssh_table_insert: null table pointer");
+  SSH_REQUIRE(M == 0 || new_keys, "ssh_table_insert: null key pointer");
+  return table_insert_launch(tab_keys, tab_ids, N, new_keys, M, L, id_base, out_keys, out_ids, ws,
+                             ws_bytes, as_stream(stream));
+}
+
+size_t ssh_table_delete_workspace_bytes(int64_t N, int32_t L) {
+  if (N < 0 || L < 1) return 0;
+  return table_delete_workspace_bytes(N, L);
+}
+
+ssh_status ssh_table_delete(const uint64_t* tab_keys, const uint32_t* tab_ids, int64_t N, int32_t L,
+                            const uint8_t* dead, int64_t id_bound, int64_t n_live,
+                            uint64_t* out_keys, uint32_t* out_ids, void* ws, size_t ws_bytes,
+                            void* stream) {
+  SSH_REQUIRE(N >= 0 && N <= (int64_t)UINT32_MAX, "ssh_table_delete: N out of [0, 2^32)");
+  SSH_REQUIRE(L >= 1, "ssh_table_delete: L < 1");
+  SSH_REQUIRE(n_live >= 0 && n_live <= N, "ssh_table_delete: n_live out of [0, N]");
+  SSH_REQUIRE(id_bound >= 0, "ssh_table_delete: id_bound < 0");
+  if (N == 0 || n_live == 0) return SSH_OK;
+  SSH_REQUIRE(tab_keys && tab_ids && dead && out_keys && out_ids && ws,
+              "ssh_table_delete: null pointer");
+  return table_delete_launch(tab_keys, tab_ids, N, L, dead, id_bound, n_live, out_keys, out_ids, ws,
+                             ws_bytes, as_stream(stream));
+}
+
 size_t ssh_probe_workspace_bytes(int32_t nq, int32_t L, int32_t C) {
   if (nq < 0 || L < 1 || C < 1 || C > SSH_MAX_C) return 0;
   return probe_workspace_bytes(nq, L, C);
@@ -342,7 +396,9 @@ ssh_status dtw_rerank_lb(const float* q, const int64_t* q_off, int32_t nq, const
 ssh_status ssh_check_device_errors(void) {
   if (hipDeviceSynchronize() != hipSuccess) return fail(SSH_EDEVICE, "device synchronisation failed");
   const int a = take_sketch_err(), b = take_shingle_err(), c = take_cws_err(), d = take_dtw_err();
-  if (a < 0 || b < 0 || c < 0 || d < 0) return fail(SSH_EDEVICE, "cannot read device error flags");
+  const int t = take_table_err();
+  if (a < 0 || b < 0 || c < 0 || d < 0 || t < 0)
+    return fail(SSH_EDEVICE, "cannot read device error flags");
   std::string msg;
   if (a) msg += "ssh_sketch: bit_word_off capacity below ceil(N_B/64); ";
   if (b) msg += "ssh_shingle: hist_off or bit_word_off capacity too small; ";
@@ -352,6 +408,8 @@ ssh_status ssh_check_device_errors(void) {
   if (d & 2) msg += "dtw_rerank: a pair's band radius is above SSH_MAX_BAND (its distance is +inf); ";
   if (d & 4) msg += "dtw_rerank: a series or query length is negative or above 2^30; ";
   if (d & 8) msg += "dtw_rerank_lb: workspace holds fewer query values than q_off[nq] (bounds fell back to LB_Kim); ";
+  if (t & 1) msg += "ssh_table_delete: a table id is not below id_bound; ";
+  if (t & 2) msg += "ssh_table_delete: a table keeps a number of entries other than n_live; ";
   if (!msg.empty()) return fail(SSH_EINVAL, msg);
   return SSH_OK;
 }

@@ -341,7 +341,8 @@ size_t table_workspace_bytes(int64_t N, int L) {
 }
 
 ssh_status table_build_launch(const uint64_t* keys, int64_t N, int L, uint64_t* tab_keys,
-                              uint32_t* tab_ids, void* ws, size_t ws_bytes, hipStream_t stream) {
+                              uint32_t* tab_ids, void* ws, size_t ws_bytes, hipStream_t stream,
+                              int sort_bits) {
   if (N == 0) return SSH_OK;
   if (ws_bytes < table_workspace_bytes(N, L))
     return fail(SSH_EINVAL, "ssh_table_build: workspace too small");
@@ -366,7 +367,7 @@ ssh_status table_build_launch(const uint64_t* keys, int64_t N, int L, uint64_t* 
   // the last one writing tab.  With L <= kTrMaxL the keys are first
   // transposed into the buffer pass 0 does not write, so every pass reads
   // table-major; otherwise pass 0 reads the series-major keys.
-  const int passes = table_sort_bits(N) / 8;
+  const int passes = (sort_bits > 0 ? sort_bits : table_sort_bits(N)) / 8;
   auto to_tab = [&](int pass) { return (passes - 1 - pass) % 2 == 0; };
   const bool transposed = L <= kTrMaxL;
   uint64_t* tr = to_tab(0) ? alt_keys : tab_keys;
@@ -389,6 +390,220 @@ ssh_status table_build_launch(const uint64_t* keys, int64_t N, int L, uint64_t* 
     rs_scatter_kernel<<<grid, kRsThreads, 0, stream>>>(in, N, L, shift, nblk, hist, ok, oi);
   }
   return check_launch("ssh_table_build");
+}
+
+// ---------------------------------------------------------------------------
+// Updates of built tables (Algorithm 1's tables, kept and updated: Section 1,
+// data-independent hashing lets new series join without touching the others).
+// ---------------------------------------------------------------------------
+__device__ int g_table_err;
+
+int take_table_err() {
+  int v = 0, z = 0;
+  if (hipMemcpyFromSymbol(&v, HIP_SYMBOL(g_table_err), sizeof(int)) != hipSuccess) return -1;
+  if (hipMemcpyToSymbol(HIP_SYMBOL(g_table_err), &z, sizeof(int)) != hipSuccess) return -1;
+  return v;
+}
+
+// Entries of sorted run t (n entries) whose top bits are below (strict) or
+// at most (!strict) v.
+__device__ __forceinline__ int64_t count_below(const uint64_t* __restrict__ t, int64_t n, int sh,
+                                               uint64_t v, bool strict) {
+  int64_t a = 0, b = n;
+  while (a < b) {
+    const int64_t mid = (a + b) >> 1;
+    const uint64_t u = t[mid] >> sh;
+    if (strict ? u < v : u <= v) a = mid + 1;
+    else b = mid;
+  }
+  return a;
+}
+
+// Merge of table l's N old entries (A) and M new ones (B, ids 0..M-1 standing
+// for id_base..id_base+M-1, above every old id), both ordered by top bits
+// with ids ascending: an old entry
+// goes after the new ones with smaller top bits, a new one after the old ones
+// with smaller or equal top bits (all old ids are smaller), which is the order
+// a build over the N + M series gives.
+__global__ __launch_bounds__(256) void table_merge_kernel(
+    const uint64_t* __restrict__ a_keys, const uint32_t* __restrict__ a_ids, int64_t N,
+    const uint64_t* __restrict__ b_keys, const uint32_t* __restrict__ b_ids, int64_t M, int L,
+    int64_t id_base, int sh, uint64_t* __restrict__ out_keys, uint32_t* __restrict__ out_ids) {
+  const int64_t T = N + M;
+  const int64_t per = (T + 255) / 256 * 256;
+  for (int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x; g < per * L;
+       g += (int64_t)gridDim.x * 256) {
+    const int l = (int)(g / per);
+    const int64_t e = g - (int64_t)l * per;
+    if (e >= T) continue;
+    const uint64_t* ak = a_keys + (int64_t)l * N;
+    const uint64_t* bk = b_keys + (int64_t)l * M;
+    uint64_t key;
+    uint32_t id;
+    int64_t pos;
+    if (e < N) {
+      key = ak[e];
+      id = a_ids[(int64_t)l * N + e];
+      pos = e + count_below(bk, M, sh, key >> sh, true);
+    } else {
+      const int64_t j = e - N;
+      key = bk[j];
+      id = (uint32_t)(id_base + b_ids[(int64_t)l * M + j]);
+      pos = j + count_below(ak, N, sh, key >> sh, false);
+    }
+    out_keys[(int64_t)l * T + pos] = key;
+    out_ids[(int64_t)l * T + pos] = id;
+  }
+}
+
+size_t table_insert_workspace_bytes(int64_t M, int L) {
+  return align256((size_t)M * L * 8) + align256((size_t)M * L * 4) + table_workspace_bytes(M, L);
+}
+
+ssh_status table_insert_launch(const uint64_t* tab_keys, const uint32_t* tab_ids, int64_t N,
+                               const uint64_t* new_keys, int64_t M, int L, int64_t id_base,
+                               uint64_t* out_keys, uint32_t* out_ids, void* ws, size_t ws_bytes,
+                               hipStream_t stream) {
+  if (N > 0 && table_sort_bits(N) != table_sort_bits(N + M))
+    return fail(SSH_EUNSUPPORTED, "ssh_table_insert: the sort width changes at 2^20 series; "
+                                  "build the tables again");
+  if (ws_bytes < table_insert_workspace_bytes(M, L))
+    return fail(SSH_EINVAL, "ssh_table_insert: workspace too small");
+  if (N + M == 0) return SSH_OK;
+  const int B = table_sort_bits(N + M);
+  unsigned char* p = reinterpret_cast<unsigned char*>(ws);
+  uint64_t* bk = reinterpret_cast<uint64_t*>(p);
+  p += align256((size_t)M * L * 8);
+  uint32_t* bi = reinterpret_cast<uint32_t*>(p);
+  p += align256((size_t)M * L * 4);
+  if (M > 0) {
+    const ssh_status st = table_build_launch(new_keys, M, L, bk, bi, p, table_workspace_bytes(M, L),
+                                             stream, B);
+    if (st != SSH_OK) return st;
+  }
+  const int64_t total = ceil_div(N + M, 256) * 256 * L;
+  table_merge_kernel<<<grid_for(total, 256, 1 << 16), 256, 0, stream>>>(
+      tab_keys, tab_ids, N, bk, bi, M, L, id_base, 64 - B, out_keys, out_ids);
+  return check_launch("ssh_table_insert");
+}
+
+// Deletion: table l keeps, in order, its entries whose id is not marked dead.
+// Per (table, tile of kRsTile entries) live counts, then per table a scan
+// (which checks that n_live entries survive), then a stable scatter.
+__global__ __launch_bounds__(256) void table_live_count_kernel(
+    const uint32_t* __restrict__ ids, int64_t N, int L, const uint8_t* __restrict__ dead,
+    int64_t id_bound, int nblk, uint32_t* __restrict__ cnt, int* err) {
+  __shared__ uint32_t c;
+  const int l = blockIdx.y, b = blockIdx.x;
+  if (threadIdx.x == 0) c = 0;
+  __syncthreads();
+  uint32_t mine = 0;
+  for (int i = threadIdx.x; i < kRsTile; i += 256) {
+    const int64_t e = (int64_t)b * kRsTile + i;
+    if (e < N) {
+      const uint32_t id = ids[(int64_t)l * N + e];
+      if (id >= id_bound) atomicOr(err, 1);
+      else mine += dead[id] == 0;
+    }
+  }
+  atomicAdd(&c, mine);
+  __syncthreads();
+  if (threadIdx.x == 0) cnt[(int64_t)l * nblk + b] = c;
+}
+
+__global__ __launch_bounds__(256) void table_live_scan_kernel(uint32_t* __restrict__ cnt, int nblk,
+                                                              int64_t n_live, int* err) {
+  __shared__ uint32_t wsum[256 / kWave];
+  __shared__ int64_t carry;
+  const int l = blockIdx.x;
+  const int lane = lane_id(), w = threadIdx.x / kWave;
+  uint32_t* c = cnt + (int64_t)l * nblk;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (int b0 = 0; b0 < nblk; b0 += 256) {
+    const int b = b0 + threadIdx.x;
+    const uint32_t v = b < nblk ? c[b] : 0u;
+    const uint32_t incl = wave_incl_scan(v);
+    if (lane == kWave - 1) wsum[w] = incl;
+    __syncthreads();
+    uint32_t before = 0, tot = 0;
+    for (int i = 0; i < 256 / kWave; ++i) {
+      before += i < w ? wsum[i] : 0u;
+      tot += wsum[i];
+    }
+    if (b < nblk) c[b] = (uint32_t)(carry + before + incl - v);
+    __syncthreads();
+    if (threadIdx.x == 0) carry += tot;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && carry != n_live) atomicOr(err, 2);
+}
+
+__global__ __launch_bounds__(256) void table_live_scatter_kernel(
+    const uint64_t* __restrict__ keys, const uint32_t* __restrict__ ids, int64_t N, int L,
+    const uint8_t* __restrict__ dead, int64_t id_bound, int nblk, const uint32_t* __restrict__ off,
+    int64_t n_live, uint64_t* __restrict__ out_keys, uint32_t* __restrict__ out_ids) {
+  __shared__ uint32_t wc[256 / kWave];
+  __shared__ uint32_t run;
+  const int l = blockIdx.y, b = blockIdx.x;
+  const int lane = lane_id(), w = threadIdx.x / kWave;
+  if (threadIdx.x == 0) run = off[(int64_t)l * nblk + b];
+  __syncthreads();
+  for (int i0 = 0; i0 < kRsTile; i0 += 256) {
+    const int64_t e = (int64_t)b * kRsTile + i0 + threadIdx.x;
+    bool live = false;
+    uint64_t key = 0;
+    uint32_t id = 0;
+    if (e < N) {
+      id = ids[(int64_t)l * N + e];
+      key = keys[(int64_t)l * N + e];
+      live = id < id_bound && dead[id] == 0;
+    }
+    const uint64_t m = ballot64(live);
+    if (lane == 0) wc[w] = (uint32_t)__builtin_popcountll(m);
+    __syncthreads();
+    uint32_t before = 0, tot = 0;
+    for (int i = 0; i < 256 / kWave; ++i) {
+      before += i < w ? wc[i] : 0u;
+      tot += wc[i];
+    }
+    const uint32_t rank = (uint32_t)__builtin_popcountll(m & ((1ull << lane) - 1ull));
+    const int64_t dst = (int64_t)run + before + rank;
+    if (live && dst < n_live) {
+      out_keys[(int64_t)l * n_live + dst] = key;
+      out_ids[(int64_t)l * n_live + dst] = id;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) run += tot;
+    __syncthreads();
+  }
+}
+
+size_t table_delete_workspace_bytes(int64_t N, int L) {
+  return align256((size_t)L * ceil_div(N > 0 ? N : 1, kRsTile) * 4);
+}
+
+ssh_status table_delete_launch(const uint64_t* tab_keys, const uint32_t* tab_ids, int64_t N, int L,
+                               const uint8_t* dead, int64_t id_bound, int64_t n_live,
+                               uint64_t* out_keys, uint32_t* out_ids, void* ws, size_t ws_bytes,
+                               hipStream_t stream) {
+  if (n_live > 0 && table_sort_bits(N) != table_sort_bits(n_live))
+    return fail(SSH_EUNSUPPORTED, "ssh_table_delete: the sort width changes at 2^20 series; "
+                                  "build the tables again");
+  if (ws_bytes < table_delete_workspace_bytes(N, L))
+    return fail(SSH_EINVAL, "ssh_table_delete: workspace too small");
+  if (N == 0 || n_live == 0) return SSH_OK;
+  int* err = nullptr;
+  if (hipGetSymbolAddress((void**)&err, HIP_SYMBOL(g_table_err)) != hipSuccess)
+    return fail(SSH_EDEVICE, "ssh_table_delete: cannot resolve error flag");
+  const int nblk = (int)ceil_div(N, kRsTile);
+  uint32_t* cnt = reinterpret_cast<uint32_t*>(ws);
+  const dim3 grid(nblk, L);
+  table_live_count_kernel<<<grid, 256, 0, stream>>>(tab_ids, N, L, dead, id_bound, nblk, cnt, err);
+  table_live_scan_kernel<<<L, 256, 0, stream>>>(cnt, nblk, n_live, err);
+  table_live_scatter_kernel<<<grid, 256, 0, stream>>>(tab_keys, tab_ids, N, L, dead, id_bound, nblk,
+                                                      cnt, n_live, out_keys, out_ids);
+  return check_launch("ssh_table_delete");
 }
 
 }  // namespace ssh

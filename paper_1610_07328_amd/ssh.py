@@ -62,6 +62,10 @@ SIGNATURES = {
     "ssh_wmh_int": (_i32, [_vp, _vp, _vp, _vp, _i64, _i32, _u64, _vp, _vp]),
     "ssh_table_workspace_bytes": (_sz, [_i64, _i32]),
     "ssh_table_build": (_i32, [_vp, _i64, _i32, _vp, _vp, _vp, _sz, _vp]),
+    "ssh_table_insert_workspace_bytes": (_sz, [_i64, _i32]),
+    "ssh_table_insert": (_i32, [_vp, _vp, _i64, _vp, _i64, _i32, _i64, _vp, _vp, _vp, _sz, _vp]),
+    "ssh_table_delete_workspace_bytes": (_sz, [_i64, _i32]),
+    "ssh_table_delete": (_i32, [_vp, _vp, _i64, _i32, _vp, _i64, _i64, _vp, _vp, _vp, _sz, _vp]),
     "ssh_probe_workspace_bytes": (_sz, [_i32, _i32, _i32]),
     "ssh_probe": (_i32, [_vp, _vp, _i64, _i32, _vp, _vp, _i32, _vp, _vp, _i32, _i32, _vp, _vp,
                          _vp, _vp, _sz, _vp]),
@@ -294,6 +298,11 @@ def wmh_int(codes, counts, hist_off, n_distinct, H: int, seed: int, out=None):
     return hv.view(-1)[: N * H].view(N, H)
 
 
+def table_sort_bits(N: int) -> int:
+    """Top key bits the tables of N series are ordered by (the probe's search width)."""
+    return 24 if N <= (1 << 20) else 32
+
+
 def table_workspace_bytes(N: int, L: int) -> int:
     return int(lib().ssh_table_workspace_bytes(N, L))
 
@@ -315,6 +324,48 @@ def table_build(keys: torch.Tensor, ws: torch.Tensor | None = None, out=None):
                                  _dev(ti, torch.uint32, "tab_ids"), _dev(ws, torch.uint8, "ws"),
                                  ws.numel(), _stream()), "ssh_table_build")
     return tk[:, :N], ti[:, :N]
+
+
+def table_insert(tab_keys, tab_ids, new_keys, id_base: int | None = None, out=None, ws=None):
+    """Tables of N entries plus M new series with ids id_base..id_base+M-1 (default
+    N) -> (tab_keys [L, N+M], tab_ids)."""
+    L, N = tab_keys.shape
+    M = new_keys.shape[0]
+    dev = new_keys.device
+    if out is None:
+        out = (torch.empty((L, max(N + M, 1)), dtype=torch.uint64, device=dev),
+               torch.empty((L, max(N + M, 1)), dtype=torch.uint32, device=dev))
+    need = int(lib().ssh_table_insert_workspace_bytes(M, L))
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+    tk = tab_keys.contiguous() if N > 0 else tab_keys
+    ti = tab_ids.contiguous() if N > 0 else tab_ids
+    _check(lib().ssh_table_insert(
+        tk.data_ptr() if N > 0 else None, ti.data_ptr() if N > 0 else None, N,
+        _dev(new_keys, torch.uint64, "new_keys") if M > 0 else None, M, L,
+        N if id_base is None else id_base,
+        _dev(out[0], torch.uint64, "out_keys"), _dev(out[1], torch.uint32, "out_ids"),
+        _dev(ws, torch.uint8, "ws"), ws.numel(), _stream()), "ssh_table_insert")
+    return out[0][:, :N + M], out[1][:, :N + M]
+
+
+def table_delete(tab_keys, tab_ids, dead: torch.Tensor, n_live: int, out=None, ws=None):
+    """Tables without the series marked in dead (uint8 [id_bound]) -> [L, n_live] tables."""
+    L, N = tab_keys.shape
+    dev = tab_keys.device
+    if out is None:
+        out = (torch.empty((L, max(n_live, 1)), dtype=torch.uint64, device=dev),
+               torch.empty((L, max(n_live, 1)), dtype=torch.uint32, device=dev))
+    need = int(lib().ssh_table_delete_workspace_bytes(N, L))
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+    _check(lib().ssh_table_delete(
+        _dev(tab_keys.contiguous(), torch.uint64, "tab_keys"),
+        _dev(tab_ids.contiguous(), torch.uint32, "tab_ids"), N, L, _dev(dead, torch.uint8, "dead"),
+        dead.numel(), n_live, _dev(out[0], torch.uint64, "out_keys"),
+        _dev(out[1], torch.uint32, "out_ids"), _dev(ws, torch.uint8, "ws"), ws.numel(),
+        _stream()), "ssh_table_delete")
+    return out[0][:, :n_live], out[1][:, :n_live]
 
 
 def probe_workspace_bytes(nq: int, L: int, C: int) -> int:
