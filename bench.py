@@ -70,11 +70,11 @@ UPLOAD_ROWS = 1 << 18
 # kernel's source file still has the digest it was measured with.
 MEASURED_TRAFFIC = {
     # (kernel, workload): (source file, sha256 of it, FETCH_SIZE KiB, WRITE_SIZE KiB,
-    #                      fetch scale, write scale); the 1 GiB copy read 524306.6 KiB
+    #                      fetch scale, write scale); the 1 GiB copy read 524307.2 KiB
     #                      on FETCH_SIZE and 1048576 KiB on WRITE_SIZE
-    ("cws_kernel", "index"): ("paper_1610_07328_amd/csrc/cws.hip",
-                              "ccb9483ee387c2dfa4db072c851ec8119f7e73577ec1befb94fc91647033061b",
-                              3571453.9375, 903875.46875, 1048576.0 / 524306.5625, 1.0),
+    ("cws_kernel", "large"): ("paper_1610_07328_amd/csrc/cws.hip",
+                              "d677312186559da35dce2d1a05a5d055c060f07b8f3487b0062e1e562e75bcbe",
+                              163524676.0, 17240299.84375, 1048576.0 / 524307.1875, 1.0),
 }
 
 

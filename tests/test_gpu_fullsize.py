@@ -13,9 +13,11 @@ from the probe) in the re-rank's launch shape.
 
 Workloads: the batched index build (1,000,000 random walks x 1024, W=80,
 delta=3, n=15, K=L=10, 1,000 queries, C=50, 5 % band), the uneven batch (series
-of 256..8192 samples, random walk and ECG-like mixed) and the large
-configuration's per-series shape (length 2048, W=128, delta=4, n=15, K=10,
-L=20, C=200, 10 % band) on 100,000 series.
+of 256..8192 samples, random walk and ECG-like mixed), and the large
+configuration (length 2048, W=128, delta=4, n=15, K=10, L=20, C=200, 10 %
+band) on 100,000 series and at its full 10,000,000 series, whose 81.92 GB are
+generated and uploaded in chunks; its sampled series are drawn again on the
+host for the oracle.
 """
 import numpy as np
 import pytest
@@ -249,3 +251,99 @@ def test_large_config_shape_sampled(ssh):
     _check_sampled_hash(qh, qx, qoff, r, draws, p, qsel)
     _check_probe(qb, range(nq), p.C, p.H)
     _check_rerank(ssh, qh, db, qx, qoff, x, off, p, qsel, seed=2)
+
+
+class _LazyWalks:
+    """Host view of random_walks(N, m, seed) that draws a row only when it is
+    sliced (x[s m : (s + 1) m]), so a batch too large for host memory can feed
+    the per-series oracle checks."""
+
+    def __init__(self, m: int, seed: int):
+        self.m, self.seed = m, seed
+
+    def __getitem__(self, sl):
+        a, b = sl.start, sl.stop
+        assert a % self.m == 0 and b - a == self.m
+        s = a // self.m
+        return datagen.random_walk_rows(s, s + 1, self.m, seed=self.seed)[0]
+
+
+def _upload_walks(N: int, m: int, seed: int) -> torch.Tensor:
+    x = torch.empty(N * m, dtype=torch.float32, device="cuda")
+    step = 1 << 18
+    for lo in range(0, N, step):
+        hi = min(N, lo + step)
+        x[lo * m:hi * m].copy_(torch.from_numpy(datagen.random_walk_rows(lo, hi, m, seed).reshape(-1)))
+    return x
+
+
+def test_large_config_full_size_sampled(ssh):
+    """The large configuration at full size on one GPU: 10,000,000 x 2048 random
+    walks resident (81.92 GB), W=128, delta=4, H=200 (K=10, L=20), 64 queries,
+    C=200, 10 % band, in the benchmark's launches; sampled series, every table
+    and every query's candidates checked, and the re-rank of sampled queries on
+    seeded candidates against the oracle."""
+    _announce("large configuration 10,000,000 x 2048, sampled parity")
+    p = Params(W=128, delta=4, n=15, K=10, L=20, band_frac=0.10, C=200, k=10)
+    N, m, nq, seed = 10_000_000, 2048, 64, 5
+    xd = _upload_walks(N, m, seed)
+    off = np.arange(N + 1, dtype=np.int64) * m
+    first = datagen.random_walk_rows(0, 100_000, m, seed=seed)
+    Q, _ = datagen.perturbed_queries(first, nq, 0.1, seed=seed)
+    qx, qoff = datagen.csr(Q)
+    r = datagen.filter_r(p.W, seed=seed)
+    draws = datagen.cws_draws(p.n, p.H, seed=seed)
+    tables = ssh.CwsTables(*draws, p.n)
+    db = HashBatch(xd, off, p)
+    qh = HashBatch(torch.as_tensor(qx).cuda(), qoff, p)
+    ix = Index(db)
+    qb = QueryBatch(qh, ix)
+    db.sketch(r)
+    db.shingle()
+    db.cws_band_keys(tables)
+    ix.build()
+    qh.run(r, tables)
+    qb.probe()
+    qb.rerank()
+    torch.cuda.synchronize()
+    ssh.check_device_errors()
+    print("[case] built; checking samples", flush=True)
+    lazy = _LazyWalks(m, seed)
+    rng = np.random.default_rng(6)
+    sample = np.sort(np.concatenate([rng.choice(N, 24, replace=False), [0, N - 1]]))
+    _check_sampled_hash(db, lazy, off, r, draws, p, sample)
+    print("[case] tables", flush=True)
+    _check_tables(ix, N, p.L)
+    qsel = _query_sample(qb, rng, 6)
+    _check_sampled_hash(qh, qx, qoff, r, draws, p, qsel)
+    print("[case] probe", flush=True)
+    _check_probe(qb, range(nq), p.C, p.H)
+    # the re-rank on seeded candidates from eight blocks spread over the id
+    # range (the last one included, past 2^31 samples): the oracle gets only
+    # those rows, each block drawn once
+    print("[case] re-rank", flush=True)
+    blk = datagen.SERIES_BLOCK
+    nblk = (N + blk - 1) // blk
+    picks = np.unique(np.linspace(0, nblk - 1, 8).astype(np.int64))
+    rr = np.random.default_rng(2)
+    cand = (picks[rr.integers(0, len(picks), size=(len(qsel), p.C))] * blk +
+            rr.integers(0, blk, size=(len(qsel), p.C)))
+    cand = np.minimum(cand, N - 1).astype(np.int64)
+    ncand = np.full(len(qsel), p.C, np.int32)
+    qs = [qx[qoff[q]:qoff[q + 1]] for q in qsel]
+    sqoff = np.zeros(len(qsel) + 1, np.int64)
+    np.cumsum([len(v) for v in qs], out=sqoff[1:])
+    sqx = np.concatenate(qs).astype(np.float32)
+    ids, dist = ssh.dtw_rerank(torch.as_tensor(sqx).cuda(), torch.as_tensor(sqoff).cuda(), db.x,
+                               db.x_off, torch.as_tensor(cand).cuda(),
+                               torch.as_tensor(ncand).cuda(), p.band_frac, p.k)
+    torch.cuda.synchronize()
+    uniq, local = np.unique(cand, return_inverse=True)
+    blocks = {b: datagen.random_walk_rows(b * blk, min(N, (b + 1) * blk), m, seed=seed)
+              for b in np.unique(uniq // blk)}
+    rows = np.stack([blocks[u // blk][u - (u // blk) * blk] for u in uniq])
+    cx, coff = datagen.csr(rows)
+    oids, odist, all_d = oracle.rerank(sqx, sqoff, cx, coff, local.reshape(cand.shape), ncand,
+                                       p.band_frac, p.k)
+    oids = np.where(oids >= 0, uniq[np.maximum(oids, 0)], -1)
+    compare_rerank(ids.cpu().numpy(), dist.cpu().numpy(), oids, odist, all_d, cand, ncand)
