@@ -395,6 +395,46 @@ ssh_status ssh_sketch_tiled(const float* x, const int64_t* x_off, int64_t N, con
                             int32_t* nbits, uint64_t* repair_count, int32_t tile_rows,
                             void* stream);
 
+/* Sign sketches of F random filters at once (Section 4.1's sketch with F
+ * filters r_1 .. r_F in place of one).  Stream f of a series is exactly what
+ * ssh_sketch gives for filter r_f: bit i is 1 when r_f . x[i*delta ..
+ * i*delta + W) >= 0, the sign of the float64 sum of exact float32 products in
+ * ascending filter index.  The inner products of 256 windows with the filters
+ * form one matrix product (windows x taps times taps x filters) computed on
+ * the matrix cores in fp16 with fp32 accumulation; pairs within a proven
+ * margin of zero are recomputed in float64, so every bit is exact.
+ * Shapes: (W, delta) in {(80, 3), (64, 4), (128, 4), (30, 5)} and F in
+ * {16, 32, 48, 64}; anything else returns SSH_EUNSUPPORTED (shape) or
+ * SSH_EINVAL (F).
+ *
+ * ssh_sketch_multi_workspace_bytes: bytes of the prepared filter block.
+ *
+ * ssh_sketch_multi_prepare [host]: checks the filters and writes the block.
+ *   R            [host] float32 [F][W] filters, row-major; every entry finite
+ *                with |r| < 2^14, and none in fp16's subnormal range
+ *                (0 < |r| < 2^-14: SSH_EUNSUPPORTED)
+ *   ws           device memory of ws_bytes >= the size above; written on
+ *                `stream`, and the call returns after the copy completes
+ *
+ * ssh_sketch_multi: the streams.
+ *   x, x_off, N, W, delta, bit_word_off, nbits   as for ssh_sketch
+ *   ws           a block written by ssh_sketch_multi_prepare for the same F,
+ *                W and delta (read only; another block gives other bits)
+ *   bits         uint64 [F * total_words]: stream f of series s starts at
+ *                word f * total_words + bit_word_off[s]
+ *   total_words  bit_word_off[N] (or more)
+ *   repair_count uint64 [1] or NULL: incremented by the number of (window,
+ *                filter) pairs recomputed in float64
+ *   kdepth       taps per matrix instruction: 16, 32, or 0 for the default
+ *                (16); the bits do not depend on it */
+size_t ssh_sketch_multi_workspace_bytes(int32_t F, int32_t W);
+ssh_status ssh_sketch_multi_prepare(const float* R, int32_t F, int32_t W, int32_t delta, void* ws,
+                                    size_t ws_bytes, void* stream);
+ssh_status ssh_sketch_multi(const float* x, const int64_t* x_off, int64_t N, const void* ws,
+                            int32_t F, int32_t W, int32_t delta, uint64_t* bits,
+                            int64_t total_words, const int64_t* bit_word_off, int32_t* nbits,
+                            uint64_t* repair_count, int32_t kdepth, void* stream);
+
 /* [host] Synchronise the device and collect the error flags that kernels raise
  * for inconsistent device-side arguments since the last call (offsets whose
  * capacity is too small, candidate ids outside [0, N), a DTW band radius above

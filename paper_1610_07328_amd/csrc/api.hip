@@ -28,6 +28,14 @@ ssh_status sketch_launch(const float* x, const int64_t* x_off, int64_t N, const 
                          uint64_t* repair_count, hipStream_t stream, bool force_generic,
                          int tile_rows);
 bool sketch_tile_supported(int W, int delta, int rows);
+size_t sketch_multi_workspace_bytes(int F, int W);
+bool sketch_multi_supported(int W, int delta);
+ssh_status sketch_multi_prepare(const float* R, int F, int W, int delta, void* ws,
+                                size_t ws_bytes, hipStream_t stream);
+ssh_status sketch_multi_launch(const float* x, const int64_t* x_off, int64_t N, const void* ws,
+                               int F, int W, int delta, uint64_t* bits, int64_t total_words,
+                               const int64_t* bit_word_off, int32_t* nbits,
+                               uint64_t* repair_count, int kdepth, hipStream_t stream);
 ssh_status shingle_launch(const uint64_t* bits, const int64_t* bit_word_off, const int32_t* nbits,
                           int64_t N, int n, uint32_t* codes, uint32_t* counts,
                           const int64_t* hist_off, int32_t* n_distinct, hipStream_t stream);
@@ -184,6 +192,38 @@ ssh_status ssh_sketch_tiled(const float* x, const int64_t* x_off, int64_t N, con
   SSH_REQUIRE(x && x_off && bits && bit_word_off && nbits, "ssh_sketch_tiled: null pointer");
   return sketch_launch(x, x_off, N, r, W, delta, bits, bit_word_off, nbits, repair_count,
                        as_stream(stream), false, tile_rows);
+}
+
+size_t ssh_sketch_multi_workspace_bytes(int32_t F, int32_t W) {
+  if (F < 1 || F > 64 || W < 1 || W > SSH_MAX_W) return 0;
+  return sketch_multi_workspace_bytes(F, W);
+}
+
+ssh_status ssh_sketch_multi_prepare(const float* R, int32_t F, int32_t W, int32_t delta, void* ws,
+                                    size_t ws_bytes, void* stream) {
+  SSH_REQUIRE(W >= 1 && W <= SSH_MAX_W, "ssh_sketch_multi_prepare: W out of [1, SSH_MAX_W]");
+  SSH_REQUIRE(delta >= 1, "ssh_sketch_multi_prepare: delta < 1");
+  SSH_REQUIRE(R && ws, "ssh_sketch_multi_prepare: null pointer");
+  return sketch_multi_prepare(R, F, W, delta, ws, ws_bytes, as_stream(stream));
+}
+
+ssh_status ssh_sketch_multi(const float* x, const int64_t* x_off, int64_t N, const void* ws,
+                            int32_t F, int32_t W, int32_t delta, uint64_t* bits,
+                            int64_t total_words, const int64_t* bit_word_off, int32_t* nbits,
+                            uint64_t* repair_count, int32_t kdepth, void* stream) {
+  SSH_REQUIRE(N >= 0 && N <= (int64_t)UINT32_MAX, "ssh_sketch_multi: N out of [0, 2^32)");
+  SSH_REQUIRE(W >= 1 && W <= SSH_MAX_W, "ssh_sketch_multi: W out of [1, SSH_MAX_W]");
+  SSH_REQUIRE(delta >= 1, "ssh_sketch_multi: delta < 1");
+  SSH_REQUIRE(total_words >= 0, "ssh_sketch_multi: total_words < 0");
+  if (!sketch_multi_supported(W, delta))
+    return fail(SSH_EUNSUPPORTED, "ssh_sketch_multi: no matrix-core kernel for this (W, delta)");
+  SSH_REQUIRE(F >= 16 && F <= 64 && F % 16 == 0, "ssh_sketch_multi: F must be 16, 32, 48 or 64");
+  SSH_REQUIRE(kdepth == 0 || kdepth == 16 || kdepth == 32,
+              "ssh_sketch_multi: kdepth must be 0, 16 or 32");
+  if (N == 0) return SSH_OK;
+  SSH_REQUIRE(x && x_off && ws && bits && bit_word_off && nbits, "ssh_sketch_multi: null pointer");
+  return sketch_multi_launch(x, x_off, N, ws, F, W, delta, bits, total_words, bit_word_off, nbits,
+                             repair_count, kdepth, as_stream(stream));
 }
 
 ssh_status ssh_shingle(const uint64_t* bits, const int64_t* bit_word_off, const int32_t* nbits,

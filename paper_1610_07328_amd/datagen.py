@@ -21,7 +21,8 @@ and the result is stored as float32.  A constant series becomes all zeros.
 Random numbers that the method itself draws are produced here and passed
 to both implementations as inputs:
 
-* the sketch filter r ~ N(0, 1)^W (Section 4.1), float32;
+* the sketch filter r ~ N(0, 1)^W (Section 4.1), float32, and F such
+  filters at once for the multi-filter sketch;
 * for weighted MinHash by Ioffe's improved consistent weighted sampling
   (Section 4.3, cited work), one triple per (code, hash):
   r ~ Gamma(2, 1), ln c with c ~ Gamma(2, 1), and beta ~ U[0, 1),
@@ -39,7 +40,7 @@ import os
 import numpy as np
 
 # child-stream indices of SeedSequence(seed).spawn(...)
-_DATA, _FILTER, _CWS, _QUERY, _ARRIVAL, _LENGTHS = range(6)
+_DATA, _FILTER, _CWS, _QUERY, _ARRIVAL, _LENGTHS, _FILTERS = range(7)
 _N_CHILDREN = 8
 # series are drawn in blocks of this many, each block from its own stream,
 # so a sample of the first B series is identical whatever the total N is
@@ -224,6 +225,12 @@ def perturbed_queries(db: np.ndarray, nq: int, noise_std: float = 0.1, seed: int
 def filter_r(W: int, seed: int = 0) -> np.ndarray:
     """The sketch filter r ~ N(0, 1)^W as float32 (Section 4.1)."""
     return _rng(seed, _FILTER).standard_normal(W).astype(np.float32)
+
+
+def filters_R(F: int, W: int, seed: int = 0) -> np.ndarray:
+    """F independent sketch filters, [F, W] float32 with N(0, 1) entries (the
+    filter of Section 4.1 drawn F times, for the multi-filter sketch)."""
+    return _rng(seed, _FILTERS).standard_normal((F, W)).astype(np.float32)
 
 
 def cws_draws(n: int, H: int, seed: int = 0):

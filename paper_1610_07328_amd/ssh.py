@@ -53,6 +53,10 @@ SIGNATURES = {
     "ssh_sketch": (_i32, [_vp, _vp, _i64, _vp, _i32, _i32, _vp, _vp, _vp, _vp, _vp]),
     "ssh_sketch_generic": (_i32, [_vp, _vp, _i64, _vp, _i32, _i32, _vp, _vp, _vp, _vp, _vp]),
     "ssh_sketch_tiled": (_i32, [_vp, _vp, _i64, _vp, _i32, _i32, _vp, _vp, _vp, _vp, _i32, _vp]),
+    "ssh_sketch_multi_workspace_bytes": (_sz, [_i32, _i32]),
+    "ssh_sketch_multi_prepare": (_i32, [_vp, _i32, _i32, _i32, _vp, _sz, _vp]),
+    "ssh_sketch_multi": (_i32, [_vp, _vp, _i64, _vp, _i32, _i32, _i32, _vp, _i64, _vp, _vp, _vp,
+                                _i32, _vp]),
     "ssh_shingle": (_i32, [_vp, _vp, _vp, _i64, _i32, _vp, _vp, _vp, _vp, _vp]),
     "ssh_cws_prepare": (_i32, [ctypes.POINTER(_CwsTablesC), _vp]),
     "ssh_cws": (_i32, [_vp, _vp, _vp, _vp, _i64, ctypes.POINTER(_CwsTablesC), _vp, _vp]),
@@ -193,6 +197,49 @@ def sketch(x: torch.Tensor, x_off: torch.Tensor, r: np.ndarray, W: int, delta: i
     else:
         fn = lib().ssh_sketch_generic if generic else lib().ssh_sketch
         _check(fn(*args, _stream()), "ssh_sketch")
+    return bits, nbits[:N], rep
+
+
+class MultiFilter:
+    """F filters prepared for ssh_sketch_multi (a device block holding them
+    as the kernels read them, written once)."""
+
+    def __init__(self, R: np.ndarray, delta: int, device="cuda"):
+        R = np.ascontiguousarray(R, dtype=np.float32)
+        if R.ndim != 2:
+            raise SSHError("filters must be a [F, W] array")
+        self.F, self.W = R.shape
+        self.delta = delta
+        nbytes = lib().ssh_sketch_multi_workspace_bytes(self.F, self.W)
+        if nbytes == 0:
+            raise SSHError("F or W out of range")
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        _check(lib().ssh_sketch_multi_prepare(R.ctypes.data, self.F, self.W, delta,
+                                              self.ws.data_ptr(), nbytes, _stream()),
+               "ssh_sketch_multi_prepare")
+
+
+def sketch_multi(x: torch.Tensor, x_off: torch.Tensor, filters: MultiFilter,
+                 bit_word_off: torch.Tensor, kdepth: int = 0, out=None):
+    """Returns (bits uint64 [F, words], nbits int32 [N], repaired uint64 [1]):
+    row f of bits is the stream set of filter f, laid out as ssh_sketch's."""
+    N = x_off.numel() - 1
+    dev = x.device
+    total_words = int(bit_word_off[-1].item())
+    if out is None:
+        bits = torch.empty((filters.F, max(total_words, 1)), dtype=torch.uint64, device=dev)
+        nbits = torch.empty(max(N, 1), dtype=torch.int32, device=dev)
+        rep = torch.zeros(1, dtype=torch.uint64, device=dev)
+    else:
+        bits, nbits, rep = out
+    stride = bits.shape[1] if bits.dim() == 2 else total_words
+    _check(lib().ssh_sketch_multi(_dev(x, torch.float32, "x"), _dev(x_off, torch.int64, "x_off"),
+                                  N, filters.ws.data_ptr(), filters.F, filters.W, filters.delta,
+                                  _dev(bits, torch.uint64, "bits"), stride,
+                                  _dev(bit_word_off, torch.int64, "bit_word_off"),
+                                  _dev(nbits, torch.int32, "nbits"),
+                                  _dev(rep, torch.uint64, "repair_count"), kdepth, _stream()),
+           "ssh_sketch_multi")
     return bits, nbits[:N], rep
 
 

@@ -153,6 +153,43 @@ def test_validation_rejects_without_device_work(ssh):
     assert L.ssh_status_str(EUNSUP) == b"SSH_EUNSUPPORTED"
 
 
+def test_multi_filter_sketch_validation(ssh):
+    """ssh_sketch_multi and its prepare step refuse bad shapes, filter counts,
+    depths, filters and workspaces before any device work."""
+    L = ssh.lib()
+    EINVAL, EUNSUP = -1, -2
+    dummy = ctypes.c_void_p(16)
+    R = np.random.default_rng(3).standard_normal((32, 80)).astype(np.float32)
+    nbytes = L.ssh_sketch_multi_workspace_bytes(32, 80)
+    # float32 rows and fp16 rows padded to 96 taps, and two margin constants per filter
+    assert nbytes >= 32 * 96 * 6 + 32 * 8
+    assert L.ssh_sketch_multi_workspace_bytes(0, 80) == 0
+    assert L.ssh_sketch_multi_workspace_bytes(16, 0) == 0
+    # shapes without a matrix-core kernel, filter counts, depths
+    assert L.ssh_sketch_multi(dummy, dummy, 4, dummy, 32, 81, 3, dummy, 10, dummy, dummy, None,
+                              0, None) == EUNSUP
+    assert L.ssh_sketch_multi(dummy, dummy, 4, dummy, 24, 80, 3, dummy, 10, dummy, dummy, None,
+                              0, None) == EINVAL
+    assert L.ssh_sketch_multi(dummy, dummy, 4, dummy, 80, 80, 3, dummy, 10, dummy, dummy, None,
+                              0, None) == EINVAL
+    assert L.ssh_sketch_multi(dummy, dummy, 4, dummy, 32, 80, 3, dummy, 10, dummy, dummy, None,
+                              8, None) == EINVAL
+    assert L.ssh_sketch_multi(dummy, None, 4, dummy, 32, 80, 3, dummy, 10, dummy, dummy, None,
+                              0, None) == EINVAL
+    assert b"null pointer" in L.ssh_last_error()
+    assert L.ssh_sketch_multi(None, None, 0, None, 32, 80, 3, None, 0, None, None, None, 0,
+                              None) == 0
+    # prepare: workspace size, F, shape, and filter values fp16 cannot carry
+    assert L.ssh_sketch_multi_prepare(R.ctypes.data, 32, 80, 3, dummy, nbytes - 1, None) == EINVAL
+    assert b"workspace" in L.ssh_last_error()
+    assert L.ssh_sketch_multi_prepare(R.ctypes.data, 8, 80, 3, dummy, nbytes, None) == EINVAL
+    assert L.ssh_sketch_multi_prepare(R.ctypes.data, 32, 80, 4, dummy, nbytes, None) == EUNSUP
+    for v in (np.inf, np.nan, 16384.0):
+        bad = R.copy()
+        bad[31, 0] = v
+        assert L.ssh_sketch_multi_prepare(bad.ctypes.data, 32, 80, 3, dummy, nbytes, None) == EINVAL
+
+
 def test_workspace_sizes(ssh):
     assert ssh.table_workspace_bytes(1_000_000, 10) >= 1_000_000 * 10 * 12
     # distances, class bytes and class lists of every pair
