@@ -136,6 +136,8 @@ def parse():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run one device copy of BYTES bytes (counter calibration)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-multi", action="store_true", help="skip the multi-filter sketch run")
+    ap.add_argument("--multi-only", action="store_true", help="only the multi-filter sketch run")
     ap.add_argument("--seed", type=int, default=0)
     return ap.parse_args()
 
@@ -752,6 +754,75 @@ def run_serving(args):
     return out
 
 
+MULTI_SHAPES = [(80, 3), (128, 4)]
+MULTI_F = 64
+MULTI_N, MULTI_M = 1_000_000, 1024
+
+
+def run_multi(args):
+    """F = 64 sign sketches of the index configuration's series at once
+    (ssh_sketch_multi), for each matrix-core filter shape: time per call with
+    HIP events on the launching stream, the MFMA roofline of the product, the
+    float64 repair fraction, and the same 64 streams from 64 single-filter
+    launches (ssh_sketch) for comparison and as a bit-for-bit check."""
+    import numpy as np
+    import torch
+
+    from paper_1610_07328_amd import datagen, ssh
+    dev = torch.device("cuda")
+    N, m, F = (args.n_series or MULTI_N), MULTI_M, MULTI_F
+    x = upload_walks(N, m, args.seed, dev)
+    off = np.arange(N + 1, dtype=np.int64) * m
+    doff = torch.as_tensor(off).to(dev)
+    res = {}
+    for W, delta in MULTI_SHAPES:
+        p = ssh.plan(off, W, delta, 1)
+        dbwo = torch.as_tensor(p.bit_word_off).to(dev)
+        nwin = N * ssh.num_bits(m, W, delta)
+        R = datagen.filters_R(F, W, seed=args.seed)
+        filt = ssh.MultiFilter(R, delta)
+        out = ssh.sketch_multi(x, doff, filt, dbwo)
+        torch.cuda.synchronize()
+        ssh.check_device_errors()
+        out[2].zero_()
+        reps = 5
+        ms = event_ms(lambda: ssh.sketch_multi(x, doff, filt, dbwo, out=out), reps)
+        repaired = int(out[2].cpu().numpy()[0]) / (reps + 1)
+        # the same streams from F single-filter launches
+        single = ssh.sketch(x, doff, R[0], W, delta, dbwo)
+        ms1 = event_ms(lambda: ssh.sketch(x, doff, R[0], W, delta, dbwo, out=single), reps)
+        words = int(p.bit_word_off[-1])
+        same = True
+        for f in range(F):
+            b1, _, _ = ssh.sketch(x, doff, R[f], W, delta, dbwo)
+            same &= bool(torch.equal(b1[:words].view(torch.int64), out[0][f, :words].view(torch.int64)))
+        torch.cuda.synchronize()
+        flops = 2.0 * W * F * nwin
+        tfs = flops / (ms * 1e-3) / 1e12
+        hbm = (N * m * 4 * ((F + 31) // 32) + F * words * 8) / (ms * 1e-3) / 1e9
+        res[f"W{W}_delta{delta}"] = {
+            "config": {"workload": f"multi-filter sign sketch: {N:,} random-walk series x {m}, "
+                                   f"W={W} delta={delta}, F={F} Gaussian filters", "N": N, "m": m,
+                       "W": W, "delta": delta, "F": F},
+            "ms": ms, "windows": nwin, "pairs_per_s": F * nwin / (ms * 1e-3),
+            "roofline": {"bound": "mfma", "achieved": tfs, "peak": 2500.0, "unit": "TFLOP/s",
+                         "frac": tfs / 2500.0, "traffic": None, "kernel": "sketch_multi_kernel",
+                         "flops_per_call": flops},
+            "hbm_GBps": hbm,
+            "fp64_repaired_fraction": repaired / (F * nwin),
+            "single_filter_ms": ms1,
+            "speedup_over_single_filter_launches": F * ms1 / ms,
+            "streams_equal_single_filter": same,
+        }
+        log(f"multi: W={W} delta={delta} F={F}: {ms:.2f} ms ({tfs:.0f} TFLOP/s, "
+            f"{F * ms1 / ms:.2f}x {F} single-filter launches, streams equal: {same})")
+        del out, single, filt, dbwo
+        torch.cuda.empty_cache()
+    del x
+    torch.cuda.empty_cache()
+    return res
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -772,6 +843,9 @@ def main():
         return
     if args.uneven_only:
         print(json.dumps({"uneven_batch": run_uneven(args)}), flush=True)
+        return
+    if args.multi_only:
+        print(json.dumps({"multi_filter_sketch": run_multi(args)}), flush=True)
         return
 
     res, cfg, Q = run_workload(args.workload, args, main=True)
@@ -797,6 +871,8 @@ def main():
         out["other_workload"] = extra
     if not args.no_uneven:
         out["uneven_batch"] = run_uneven(args)
+    if not args.no_multi:
+        out["multi_filter_sketch"] = run_multi(args)
     if not args.no_serving:
         out["serving"] = run_serving(args)
         out["query_latency_ms_served"] = out["serving"]["continuous_batching"]["latency_ms"]

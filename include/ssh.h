@@ -426,7 +426,8 @@ ssh_status ssh_sketch_tiled(const float* x, const int64_t* x_off, int64_t N, con
  *   repair_count uint64 [1] or NULL: incremented by the number of (window,
  *                filter) pairs recomputed in float64
  *   kdepth       taps per matrix instruction: 16, 32, or 0 for the default
- *                (16); the bits do not depend on it */
+ *                (32 when W is a multiple of 32, else 16); the bits do not
+ *                depend on it */
 size_t ssh_sketch_multi_workspace_bytes(int32_t F, int32_t W);
 ssh_status ssh_sketch_multi_prepare(const float* R, int32_t F, int32_t W, int32_t delta, void* ws,
                                     size_t ws_bytes, void* stream);

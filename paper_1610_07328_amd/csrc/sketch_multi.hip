@@ -4,7 +4,8 @@
 //
 // Bit (f, i) of a series = [ r_f . x[i delta .. i delta + W) >= 0 ]: F sign
 // streams, stream f being exactly the single-filter sketch of filter r_f.  For
-// a work item of 256 consecutive windows of one series the inner products are
+// a work item of 128 or 256 consecutive windows of one series the inner
+// products are
 //     S[f][w] = sum_k R[f][k] X[k][w],  R[f][k] = r_f[k],  X[k][w] = x[w delta + k]
 // (filters x taps times taps x windows; taps padded to a multiple of the MFMA
 // depth with zero filter entries).  The filters are the A operand, held in
@@ -55,8 +56,6 @@ struct MultiArgs {
   int fbase;          // first filter of this launch
 };
 
-constexpr int kMtItem = 16;              // 16-window tiles per item
-constexpr int kSubMulti = 16 * kMtItem;  // windows per item
 constexpr int kQcapMulti = 512;          // queued (window, filter) pairs per item
 
 // Sign of the float64 sum of exact products r[k] x[k], k ascending.
@@ -90,11 +89,16 @@ __device__ __forceinline__ float sq2(uint32_t u, float acc) {
   return __builtin_amdgcn_fdot2(v, v, acc, false);
 }
 
-template <int W, int D, int KW, int NT>
-__global__ __launch_bounds__(256) void sketch_multi_kernel(
+// MT: 16-window tiles per work item (8 or 16); WPE: the waves per SIMD the
+// register budget is fitted to (the item size and the budget set how many
+// waves share a SIMD, through LDS and registers)
+template <int W, int D, int KW, int NT, int MT, int WPE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void sketch_multi_kernel(
     const float* __restrict__ x, const int64_t* __restrict__ x_off, int64_t N, MultiArgs ma,
     uint64_t* __restrict__ bits, int64_t total_words, const int64_t* __restrict__ bit_word_off,
     int32_t* __restrict__ nbits_out, unsigned long long* repair_count, int* err) {
+  constexpr int kMtItem = MT;                                // 16-window tiles per item
+  constexpr int kSubMulti = 16 * MT;                         // windows per item
   constexpr int WP = (W + KW - 1) / KW * KW;                // padded taps
   constexpr int KS = WP / KW;                                // k-steps
   constexpr int QL = KW / 16;                                // quads per lane per k-step
@@ -105,7 +109,8 @@ __global__ __launch_bounds__(256) void sketch_multi_kernel(
   constexpr int NQ = (NS + 3) / 4;                           // 4-sample groups staged
   constexpr int PF4 = (NS + 4 + 4 * kWave - 1) / (4 * kWave);  // 256-sample rows loaded
   constexpr int WPI = kMtItem / 2;                           // 32-bit words per filter per item
-  static_assert(FG <= 256 && kSubMulti <= 256, "queue entries are bytes");
+  static_assert(FG <= 256 && kSubMulti <= 256 && kSubMulti % 64 == 0,
+                "queue entries are bytes; items hold whole stream words");
 
   constexpr int RS = W | 1;  // odd row stride: the rows of one tap sit on distinct banks
   __shared__ float rs[FG][RS];  // the launch's filters, float32
@@ -123,7 +128,6 @@ __global__ __launch_bounds__(256) void sketch_multi_kernel(
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int lane = lane_id();
   const int n16 = lane & 15, g = lane >> 4;
-  const uint64_t lt_mask = (1ull << lane) - 1ull;
   uint32_t* bits32 = reinterpret_cast<uint32_t*>(bits);
   // pairs this wave recomputed in float64, added to the global count once at
   // the end (one atomic per item on a single address would serialise)
@@ -247,25 +251,46 @@ __global__ __launch_bounds__(256) void sketch_multi_kernel(
       // the signs of tile mt: one ballot per (filter block, element) gives
       // the 16-window fields of four filters at once
       auto extract = [&](int mt, const float4v (&S)[NT], float xn) {
-        const bool vwin = 16 * mt + n16 < nb_item;
+        const uint64_t vmask = __builtin_amdgcn_ballot_w64(16 * mt + n16 < nb_item);
+        uint64_t unt[NT][4];
+        uint64_t any = 0;
+        uint32_t mlo = 0, mhi = 0;  // lane 4 nt + i: the mask of (nt, i)
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) {
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
             const float sv = S[nt][i];
-            const bool trusted = __builtin_fabsf(sv) > __builtin_fmaf(kk[nt][i].x, xn, kk[nt][i].y);
-            const uint64_t ones = ballot64(vwin & trusted & (sv >= 0.0f));
-            const uint64_t untrusted = ballot64(vwin & !trusted);
-            if (lane == 0) bm[w][nt][i][mt] = ones;
-            // untrusted pairs, appended in lane order (a full queue drops
-            // them and the item goes down the exact path below)
-            if (untrusted) {
-              const int slot = qc + (int)__builtin_popcountll(untrusted & lt_mask);
-              if (vwin && !trusted && slot < kQcapMulti) {
-                qwin[w][slot] = (uint8_t)(16 * mt + n16);
-                qfil[w][slot] = (uint8_t)(16 * nt + 4 * g + i);
+            const uint64_t tr = __builtin_amdgcn_ballot_w64(
+                __builtin_fabsf(sv) > __builtin_fmaf(kk[nt][i].x, xn, kk[nt][i].y));
+            const uint64_t pos = __builtin_amdgcn_ballot_w64(sv >= 0.0f);
+            const uint64_t ones = tr & pos & vmask;
+            unt[nt][i] = vmask & ~tr;
+            any |= unt[nt][i];
+            const bool mine = lane == 4 * nt + i;
+            mlo = mine ? (uint32_t)ones : mlo;
+            mhi = mine ? (uint32_t)(ones >> 32) : mhi;
+          }
+        }
+        if (lane < 4 * NT)
+          bm[w][lane >> 2][lane & 3][mt] = ((uint64_t)mhi << 32) | mlo;
+        // untrusted pairs, appended in lane order (a full queue drops them
+        // and the item goes down the exact path below)
+        if (any) {
+#pragma unroll
+          for (int nt = 0; nt < NT; ++nt) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const uint64_t u = unt[nt][i];
+              if (u) {
+                const int slot = qc + (int)__builtin_amdgcn_mbcnt_hi(
+                                          (uint32_t)(u >> 32),
+                                          __builtin_amdgcn_mbcnt_lo((uint32_t)u, 0u));
+                if (((u >> lane) & 1ull) && slot < kQcapMulti) {
+                  qwin[w][slot] = (uint8_t)(16 * mt + n16);
+                  qfil[w][slot] = (uint8_t)(16 * nt + 4 * g + i);
+                }
+                qc += (int)__builtin_popcountll(u);
               }
-              qc += (int)__builtin_popcountll(untrusted);
             }
           }
         }
@@ -361,14 +386,25 @@ bool sketch_multi_supported(int W, int delta) {
          (W == 30 && delta == 5);
 }
 
+// Item size and register budget per shape, from timing on MI355X: windows of
+// (128, 4) fill 16-tile items at 3 waves per SIMD; the other shapes do best
+// with 8-tile items (half the LDS, so more workgroups per CU), at 4 waves
+// where the registers allow it.
+template <int W, int D>
+struct MultiTuning {
+  static constexpr int MT = (W == 128 && D == 4) ? 16 : 8;
+  static constexpr int WPE = (W == 128 && D == 4) || (W == 30 && D == 5) ? 3 : 4;
+};
+
 template <int W, int D, int KW, int NT>
 static void launch_multi(const MultiArgs& ma, const float* x, const int64_t* x_off, int64_t N,
                          uint64_t* bits, int64_t total_words, const int64_t* bit_word_off,
                          int32_t* nbits, unsigned long long* rc, int* err, hipStream_t stream) {
-  const unsigned grid =
-      resident_grid(reinterpret_cast<const void*>(&sketch_multi_kernel<W, D, KW, NT>), N);
-  sketch_multi_kernel<W, D, KW, NT><<<grid, 256, 0, stream>>>(x, x_off, N, ma, bits, total_words,
-                                                              bit_word_off, nbits, rc, err);
+  constexpr int MT = MultiTuning<W, D>::MT, WPE = MultiTuning<W, D>::WPE;
+  const unsigned grid = resident_grid(
+      reinterpret_cast<const void*>(&sketch_multi_kernel<W, D, KW, NT, MT, WPE>), N);
+  sketch_multi_kernel<W, D, KW, NT, MT, WPE><<<grid, 256, 0, stream>>>(
+      x, x_off, N, ma, bits, total_words, bit_word_off, nbits, rc, err);
 }
 
 template <int W, int D, int KW>
@@ -465,7 +501,9 @@ ssh_status sketch_multi_launch(const float* x, const int64_t* x_off, int64_t N, 
   if (N == 0) return SSH_OK;
   int* err = sketch_err_ptr();
   if (err == nullptr) return fail(SSH_EDEVICE, "ssh_sketch_multi: cannot resolve error flag");
-  const int KW = kdepth != 0 ? kdepth : 16;
+  // 32 taps per instruction where the filter fills them; else 16 (W = 80 would
+  // pad to 96 taps at 32)
+  const int KW = kdepth != 0 ? kdepth : (W % 32 == 0 ? 32 : 16);
   size_t o_rh, o_kst;
   multi_layout(F, W, o_rh, o_kst);
   const unsigned char* base = static_cast<const unsigned char*>(ws);
