@@ -70,11 +70,11 @@ UPLOAD_ROWS = 1 << 18
 # kernel's source file still has the digest it was measured with.
 MEASURED_TRAFFIC = {
     # (kernel, workload): (source file, sha256 of it, FETCH_SIZE KiB, WRITE_SIZE KiB,
-    #                      fetch scale, write scale); the 1 GiB copy read 524307.2 KiB
+    #                      fetch scale, write scale); the 1 GiB copy read 524307.6 KiB
     #                      on FETCH_SIZE and 1048576 KiB on WRITE_SIZE
     ("cws_kernel", "large"): ("paper_1610_07328_amd/csrc/cws.hip",
-                              "d677312186559da35dce2d1a05a5d055c060f07b8f3487b0062e1e562e75bcbe",
-                              163524676.0, 17240299.84375, 1048576.0 / 524307.1875, 1.0),
+                              "5254d84f8092a8e6ae7fe0cc253b9e16f94e044b656f1f5118de9338e5129d51",
+                              171063170.1875, 17838246.46875, 1048576.0 / 524307.5625, 1.0),
 }
 
 
@@ -389,7 +389,9 @@ def run_workload(name: str, args, main: bool):
     # the pruned re-rank on the step's own candidate lists
     ws_lbs = torch.empty(ssh.rerank_lb_workspace_bytes(nq, p.C, qb.x.numel()), dtype=torch.uint8,
                          device=dev)
-    t_step_plain = event_ms(qry.rerank, 5)
+    t_step_plain = event_ms(lambda: ssh.dtw_rerank(qb.x, qb.x_off, db.x, db.x_off, qry.cand[:nq],
+                                                   qry.ncand[:nq], p.band_frac, p.k, ws=ws_lbs,
+                                                   prune=False), 5)
     t_step_lb = event_ms(lambda: ssh.dtw_rerank(qb.x, qb.x_off, db.x, db.x_off, qry.cand[:nq],
                                                 qry.ncand[:nq], p.band_frac, p.k, ws=ws_lbs,
                                                 prune=True), 5)
@@ -445,6 +447,15 @@ def run_workload(name: str, args, main: bool):
                                                     for i in range(nq)]))}
         log(f"{name}: recall@10 {recall['recall_at_10']:.3f} on {recall['queries']} queries")
 
+    # the integer-replication weighted MinHash (with band keys) in place of
+    # CWS on the same weighted sets, after everything above has read the CWS
+    # hash values
+    t_wmh = event_ms(db.wmh_int_band_keys, 5)
+    wmh_pairs = N * max(int(db.plan.max_nbits) - p.n + 1, 0) * p.H  # equal lengths: every set
+    wmh = {"ms": t_wmh, "pairs": wmh_pairs, "pairs_per_s": wmh_pairs / (t_wmh / 1e3),
+           "cws_ms": per_stage["cws"]}
+    log(f"{name}: integer-replication MinHash {t_wmh:.2f} ms ({wmh['pairs_per_s']:.3g} pairs/s)")
+
     # dominant stage and its roofline
     dominant = max(["sketch", "shingle", "cws", "table_build", "rerank"], key=lambda k: per_stage[k])
     if dominant == "rerank":
@@ -474,11 +485,14 @@ def run_workload(name: str, args, main: bool):
         "config": {"workload": cfg["workload"], "n_series": N, "length": m, "W": p.W,
                    "delta": p.delta, "n": p.n, "K": p.K, "L": p.L, "queries": nq, "C": p.C,
                    "band_frac": p.band_frac, "k": p.k},
+        # the cells of every candidate pair's band over the re-rank stage's time
+        # (an effective rate when the step prunes: pruned pairs count too)
         "dtw_cells_per_s": step_cells / (per_stage["rerank"] / 1e3),
         "dtw_step_pairs": int(ncand.sum()),
         "dtw_full_batch": dtw_full,
         "rerank_step_candidates": {"plain_ms": t_step_plain, "pruned_ms": t_step_lb,
-                                   "speedup": t_step_plain / t_step_lb},
+                                   "speedup": t_step_plain / t_step_lb,
+                                   "step_uses": "pruned" if qry.prune else "plain"},
         "query_latency_ms": {"p50": float(np.percentile(lat, 50)),
                              "p99": float(np.percentile(lat, 99)),
                              "samples": int(lat.size), "batch": 1},
@@ -491,6 +505,7 @@ def run_workload(name: str, args, main: bool):
                           "queries_with_candidates": int((ncand > 0).sum())},
         "sketch_fp64_repaired_windows": repaired,
         "mean_distinct_shingles": sum_d / N,
+        "wmh_int": wmh,
         "roofline": roof,
     }
     # free the device state before anything else runs

@@ -207,7 +207,7 @@ ssh_status ssh_band_keys(const uint64_t* hv, int64_t N, int32_t K, int32_t L, ui
 /* ssh_cws and ssh_band_keys in one pass (Section 4.3, then Algorithm 1): hv
  * and keys are exactly what ssh_cws followed by ssh_band_keys(hv, N, K, L,
  * seed) write, with the keys folded from the hash values while the CWS kernel
- * still holds them, so hv is not read back.  Shapes with H > 640 run the two
+ * still holds them, so hv is not read back.  Shapes with H > 256 run the two
  * steps as separate kernels.  Arguments as for those two calls; additionally
  * returns SSH_EINVAL unless K * L == tab->H. */
 ssh_status ssh_cws_band_keys(const uint32_t* codes, const uint32_t* counts,
@@ -297,6 +297,17 @@ ssh_status ssh_probe(const uint64_t* tab_keys, const uint32_t* tab_ids, int64_t 
                      const uint64_t* q_keys, const uint64_t* q_hv, int32_t nq, int32_t C,
                      int64_t* cand, int32_t* ncand, int64_t* r_size, void* ws, size_t ws_bytes,
                      void* stream);
+
+/* ssh_probe for callers that want no silent truncation: the same outputs
+ * (cand truncated at C, r_size the full |R|), then the call synchronises
+ * `stream`, reads r_size back and returns SSH_ECAPACITY when some query
+ * retrieved more than C series (the count and the largest |R| are in
+ * ssh_last_error()); SSH_OK otherwise.  Blocks the host until the probe ends. */
+ssh_status ssh_probe_strict(const uint64_t* tab_keys, const uint32_t* tab_ids, int64_t N,
+                            int32_t L, const uint64_t* db_keys, const uint64_t* db_hv, int32_t H,
+                            const uint64_t* q_keys, const uint64_t* q_hv, int32_t nq, int32_t C,
+                            int64_t* cand, int32_t* ncand, int64_t* r_size, void* ws,
+                            size_t ws_bytes, void* stream);
 
 /* [host] Workspace bytes needed by dtw_rerank for nq queries of C candidates. */
 size_t ssh_rerank_workspace_bytes(int32_t nq, int32_t C);

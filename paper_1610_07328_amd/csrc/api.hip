@@ -2,6 +2,7 @@
 // and dispatch to the kernels.  Every entry point validates synchronously and
 // enqueues nothing when it rejects its arguments.
 #include <string>
+#include <vector>
 
 #include "common.hpp"
 
@@ -374,6 +375,33 @@ ssh_status ssh_probe(const uint64_t* tab_keys, const uint32_t* tab_ids, int64_t 
   SSH_REQUIRE(N == 0 || (tab_keys && tab_ids && db_keys && db_hv), "ssh_probe: null table pointer");
   return probe_launch(tab_keys, tab_ids, N, L, db_keys, db_hv, H, q_keys, q_hv, nq, C, cand, ncand,
                       r_size, ws, ws_bytes, as_stream(stream));
+}
+
+ssh_status ssh_probe_strict(const uint64_t* tab_keys, const uint32_t* tab_ids, int64_t N,
+                            int32_t L, const uint64_t* db_keys, const uint64_t* db_hv, int32_t H,
+                            const uint64_t* q_keys, const uint64_t* q_hv, int32_t nq, int32_t C,
+                            int64_t* cand, int32_t* ncand, int64_t* r_size, void* ws,
+                            size_t ws_bytes, void* stream) {
+  const ssh_status st = ssh_probe(tab_keys, tab_ids, N, L, db_keys, db_hv, H, q_keys, q_hv, nq, C,
+                                  cand, ncand, r_size, ws, ws_bytes, stream);
+  if (st != SSH_OK || nq == 0) return st;
+  std::vector<int64_t> rs((size_t)nq);
+  if (hipMemcpyAsync(rs.data(), r_size, (size_t)nq * sizeof(int64_t), hipMemcpyDeviceToHost,
+                     as_stream(stream)) != hipSuccess ||
+      hipStreamSynchronize(as_stream(stream)) != hipSuccess)
+    return fail(SSH_EDEVICE, "ssh_probe_strict: reading r_size back failed");
+  int64_t over = 0, worst = 0;
+  for (int32_t q = 0; q < nq; ++q) {
+    if (rs[(size_t)q] > C) {
+      ++over;
+      worst = rs[(size_t)q] > worst ? rs[(size_t)q] : worst;
+    }
+  }
+  if (over > 0)
+    return fail(SSH_ECAPACITY, "ssh_probe_strict: " + std::to_string(over) +
+                                   " queries retrieved more than C candidates (largest |R| = " +
+                                   std::to_string(worst) + ")");
+  return SSH_OK;
 }
 
 size_t ssh_rerank_workspace_bytes(int32_t nq, int32_t C) {

@@ -236,7 +236,7 @@ struct CwsDev {
 constexpr int kCwsWaves = 4;  // wavefronts per workgroup
 constexpr int kPassA = 16;     // keyed tokens whose keys are loaded together
 constexpr int kHeavyCap = 64; // heavy tokens listed per series in LDS
-constexpr int kBandLds = 640; // hash values kept per wave in LDS for the fused band keys
+constexpr int kBandLds = 256; // hash values kept per wave in LDS for the fused band keys
 constexpr int64_t kSplitN = 4096;  // below this many series, a workgroup per series
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 
@@ -280,7 +280,7 @@ struct BandOut {
 // so the merged pair is the pair pass A over all tokens gives), and wave 0
 // finishes the series: ties, pass B over the four heavy lists, output, keys.
 template <bool KEYS, bool SPLIT>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void cws_kernel(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void cws_kernel(
     const uint32_t* __restrict__ codes, const uint32_t* __restrict__ counts,
     const int64_t* __restrict__ hist_off, const int32_t* __restrict__ n_distinct, int64_t N,
     CwsDev t, uint64_t* __restrict__ hv, int* err, BandOut bo) {

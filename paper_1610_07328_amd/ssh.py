@@ -73,6 +73,8 @@ SIGNATURES = {
     "ssh_probe_workspace_bytes": (_sz, [_i32, _i32, _i32]),
     "ssh_probe": (_i32, [_vp, _vp, _i64, _i32, _vp, _vp, _i32, _vp, _vp, _i32, _i32, _vp, _vp,
                          _vp, _vp, _sz, _vp]),
+    "ssh_probe_strict": (_i32, [_vp, _vp, _i64, _i32, _vp, _vp, _i32, _vp, _vp, _i32, _i32, _vp,
+                                _vp, _vp, _vp, _sz, _vp]),
     "ssh_rerank_workspace_bytes": (_sz, [_i32, _i32]),
     "dtw_rerank": (_i32, [_vp, _vp, _i32, _vp, _vp, _i64, _vp, _vp, _i32, _f32, _i32, _vp,
                           _vp, _vp, _sz, _vp]),
@@ -419,8 +421,15 @@ def probe_workspace_bytes(nq: int, L: int, C: int) -> int:
     return int(lib().ssh_probe_workspace_bytes(nq, L, C))
 
 
-def probe(tab_keys, tab_ids, db_keys, db_hv, q_keys, q_hv, C: int, out=None, ws=None):
-    """Returns (cand int64 [nq, C], ncand int32 [nq], r_size int64 [nq])."""
+class CapacityError(SSHError):
+    """A strict probe retrieved more than C series for some query."""
+
+
+def probe(tab_keys, tab_ids, db_keys, db_hv, q_keys, q_hv, C: int, out=None, ws=None,
+          strict: bool = False):
+    """Returns (cand int64 [nq, C], ncand int32 [nq], r_size int64 [nq]).
+    strict=True calls ssh_probe_strict: it synchronises and raises CapacityError
+    when a query's retrieved set exceeds C (the outputs are still written)."""
     L, N = tab_keys.shape
     H = db_hv.shape[1]
     nq = q_keys.shape[0]
@@ -435,13 +444,15 @@ def probe(tab_keys, tab_ids, db_keys, db_hv, q_keys, q_hv, C: int, out=None, ws=
     else:
         cand, ncand, rs = out
     tk = tab_keys.contiguous() if N > 0 else tab_keys
-    _check(lib().ssh_probe(_dev(tk, torch.uint64, "tab_keys"),
-                           _dev(tab_ids.contiguous(), torch.uint32, "tab_ids"), N, L,
-                           _dev(db_keys, torch.uint64, "db_keys"), _dev(db_hv, torch.uint64, "db_hv"),
-                           H, _dev(q_keys, torch.uint64, "q_keys"), _dev(q_hv, torch.uint64, "q_hv"),
-                           nq, C, _dev(cand, torch.int64, "cand"), _dev(ncand, torch.int32, "ncand"),
-                           _dev(rs, torch.int64, "r_size"), _dev(ws, torch.uint8, "ws"),
-                           ws.numel(), _stream()), "ssh_probe")
+    fn = lib().ssh_probe_strict if strict else lib().ssh_probe
+    st = fn(_dev(tk, torch.uint64, "tab_keys"), _dev(tab_ids.contiguous(), torch.uint32, "tab_ids"),
+            N, L, _dev(db_keys, torch.uint64, "db_keys"), _dev(db_hv, torch.uint64, "db_hv"), H,
+            _dev(q_keys, torch.uint64, "q_keys"), _dev(q_hv, torch.uint64, "q_hv"), nq, C,
+            _dev(cand, torch.int64, "cand"), _dev(ncand, torch.int32, "ncand"),
+            _dev(rs, torch.int64, "r_size"), _dev(ws, torch.uint8, "ws"), ws.numel(), _stream())
+    if st == -4:  # SSH_ECAPACITY
+        raise CapacityError(lib().ssh_last_error().decode())
+    _check(st, "ssh_probe_strict" if strict else "ssh_probe")
     return cand[:nq], ncand[:nq], rs[:nq]
 
 

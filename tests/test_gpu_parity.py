@@ -497,8 +497,8 @@ def test_cws_key_rows_at_their_limits(ssh):
 def test_cws_band_keys_fused_exact(ssh, n, K, L):
     """CWS with the band keys folded in, against the oracle's CWS then band keys:
     H = 20 (one chunk of hash values), L = 130 (more tables than lanes), H = 200
-    and 300 (two and three chunks of 128), and H = 650 (beyond the kernel's LDS
-    copy: two kernels), with empty sets among ragged ones."""
+    (two chunks of 128), and H = 300 and 650 (beyond the kernel's LDS copy:
+    two kernels), with empty sets among ragged ones."""
     _announce(f"cws + band keys fused n={n} K={K} L={L}")
     H = K * L
     seed = 0xDEADBEEFCAFEBABE
@@ -741,6 +741,39 @@ def test_probe_large_retrieved_sets_with_ties(ssh, C):
         oc, orr = oracle.probe(keys, hv, qk[i], qh[i], C)
         assert rs[i] == orr and ncand[i] == len(oc)
         assert np.array_equal(cand[i, : ncand[i]], oc), i
+
+
+def test_probe_strict_reports_truncation(ssh):
+    """ssh_probe_strict writes what ssh_probe writes and returns SSH_ECAPACITY
+    exactly when some query's retrieved set exceeds C."""
+    _announce("probe strict capacity")
+    rng = np.random.default_rng(22)
+    N, L, H = 5000, 2, 8
+    hv = rng.integers(0, 4, size=(N, H), dtype=np.int64).astype(np.uint64)
+    keys = (rng.integers(0, 50, size=(N, L), dtype=np.int64).astype(np.uint64) *
+            np.uint64(0x9E3779B97F4A7C15))
+    qk, qh = keys[:4].copy(), hv[:4].copy()
+    tk, ti = ssh.table_build(to_dev(keys))
+    args = (tk, ti, to_dev(keys), to_dev(hv), to_dev(qk), to_dev(qh))
+    cand, ncand, rs = ssh.probe(*args, 50)
+    torch.cuda.synchronize()
+    cand, ncand, rs = to_np(cand), to_np(ncand), to_np(rs)
+    big = int(rs.max())
+    assert big > 50  # every query's buckets hold about 200 series
+    with pytest.raises(ssh.CapacityError, match="largest"):
+        ssh.probe(*args, 50, strict=True)
+    # the outputs of the refused call are the truncated ones
+    c2, n2, r2 = ssh.probe(*args, 50)
+    torch.cuda.synchronize()
+    assert np.array_equal(to_np(c2), cand) and np.array_equal(to_np(r2), rs)
+    # with C at least every |R| the strict call succeeds and equals the plain one
+    cs, ns, rss = ssh.probe(*args, big, strict=True)
+    cp, npl, rp = ssh.probe(*args, big)
+    torch.cuda.synchronize()
+    assert np.array_equal(to_np(cs), to_np(cp)) and np.array_equal(to_np(rss), rs)
+    for i in range(4):
+        oc, orr = oracle.probe(keys, hv, qk[i], qh[i], big)
+        assert to_np(rss)[i] == orr and np.array_equal(to_np(cs)[i, : to_np(ns)[i]], oc)
 
 
 # --------------------------------------------------------------------------
