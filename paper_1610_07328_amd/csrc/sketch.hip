@@ -81,7 +81,7 @@ __device__ __forceinline__ bool stage_chunk(float* X, int cap, const float* __re
 __device__ __forceinline__ void repair_round(const FilterArgs& fa, const float* __restrict__ x,
                              const int64_t* __restrict__ x_off, uint32_t* bits32,
                              const int64_t* __restrict__ bit_word_off, RepairQueue q,
-                             unsigned long long* repair_count) {
+                             unsigned long long& repaired) {
   const int lane = lane_id();
   int n = *q.count;
   int cnt = n < kWave ? n : kWave;
@@ -112,11 +112,16 @@ __device__ __forceinline__ void repair_round(const FilterArgs& fa, const float* 
       atomicOr(bits32 + 2 * word + ((wi >> 5) & 1), 1u << (wi & 31));
     }
   }
-  if (lane == 0) {
-    *q.count = start;
-    if (repair_count) atomicAdd(repair_count, (unsigned long long)cnt);
-  }
+  if (lane == 0) *q.count = start;
+  repaired += (unsigned long long)cnt;
   wave_sync_lds();
+}
+
+// The windows a wave recomputed, added to the global count once at its end
+// (an atomic per repair round on one address serialises across the grid).
+__device__ __forceinline__ void add_repaired(unsigned long long* repair_count,
+                                             unsigned long long repaired) {
+  if (lane_id() == 0 && repair_count && repaired) atomicAdd(repair_count, repaired);
 }
 
 template <int R>
@@ -195,6 +200,7 @@ __global__ __launch_bounds__(256) void sketch_mfma_kernel(
   const int lane = lane_id();
   const int col = lane & 15, grp = lane >> 4;
   RepairQueue q{qser[w], qwin[w], &qn[w]};
+  unsigned long long repaired = 0;  // windows this wave recomputed
   uint32_t* bits32 = reinterpret_cast<uint32_t*>(bits);
   if (lane == 0) qn[w] = 0;
 
@@ -301,10 +307,11 @@ __global__ __launch_bounds__(256) void sketch_mfma_kernel(
       if (wd < nwords)
         bits32[2 * (cur.wo + wd) + (lane & 1)] = reinterpret_cast<const uint32_t*>(bw[w])[lane];
     }
-    while (qn[w] >= kWave) repair_round(fa, x, x_off, bits32, bit_word_off, q, repair_count);
+    while (qn[w] >= kWave) repair_round(fa, x, x_off, bits32, bit_word_off, q, repaired);
     cur = nxt;
   }
-  while (qn[w] > 0) repair_round(fa, x, x_off, bits32, bit_word_off, q, repair_count);
+  while (qn[w] > 0) repair_round(fa, x, x_off, bits32, bit_word_off, q, repaired);
+  add_repaired(repair_count, repaired);
 }
 
 // ---------------------------------------------------------------------------
@@ -328,6 +335,7 @@ __global__ __launch_bounds__(256) void sketch_generic_kernel(
   uint32_t* bw = qs + 2 * QCAP;
   int* qcount = reinterpret_cast<int*>(bw + 2);
   RepairQueue q{qs, qs + QCAP, qcount};
+  unsigned long long repaired = 0;  // windows this wave recomputed
   uint32_t* bits32 = reinterpret_cast<uint32_t*>(bits);
   if (lane == 0) *qcount = 0;
   wave_sync_lds();
@@ -370,10 +378,11 @@ __global__ __launch_bounds__(256) void sketch_generic_kernel(
       }
       wave_sync_lds();
       if (lane < 2 && c < nwords) bits32[2 * (wo + c) + lane] = bw[lane];
-      while (*qcount >= kWave) repair_round(fa, x, x_off, bits32, bit_word_off, q, repair_count);
+      while (*qcount >= kWave) repair_round(fa, x, x_off, bits32, bit_word_off, q, repaired);
     }
   }
-  while (*qcount > 0) repair_round(fa, x, x_off, bits32, bit_word_off, q, repair_count);
+  while (*qcount > 0) repair_round(fa, x, x_off, bits32, bit_word_off, q, repaired);
+  add_repaired(repair_count, repaired);
 }
 
 // ---------------------------------------------------------------------------

@@ -17,7 +17,8 @@ of 256..8192 samples, random walk and ECG-like mixed), and the large
 configuration (length 2048, W=128, delta=4, n=15, K=10, L=20, C=200, 10 %
 band) on 100,000 series and at its full 10,000,000 series, whose 81.92 GB are
 generated and uploaded in chunks; its sampled series are drawn again on the
-host for the oracle.
+host for the oracle; and the multi-filter sketch's benchmark workload
+(1,000,000 x 1024, 64 filters, both timed shapes).
 """
 import numpy as np
 import pytest
@@ -347,3 +348,39 @@ def test_large_config_full_size_sampled(ssh):
                                        p.band_frac, p.k)
     oids = np.where(oids >= 0, uniq[np.maximum(oids, 0)], -1)
     compare_rerank(ids.cpu().numpy(), dist.cpu().numpy(), oids, odist, all_d, cand, ncand)
+
+
+@pytest.mark.parametrize("W,delta", [(80, 3), (128, 4)])
+def test_multi_filter_sketch_full_size_sampled(ssh, W, delta):
+    """The multi-filter sketch's benchmark workload: 1,000,000 random walks x 1024
+    resident, 64 filters (two launches of 32), the default MFMA depth; every
+    stream of sampled series against the oracle's single-filter sketch, and the
+    stream layout and bit counts of every series."""
+    _announce(f"multi-filter sketch 1M x 1024, 64 filters, W={W} delta={delta}, sampled parity")
+    N, m, F, seed = 1_000_000, 1024, 64, 0
+    xd = _upload_walks(N, m, seed)
+    off = np.arange(N + 1, dtype=np.int64) * m
+    R = datagen.filters_R(F, W, seed=seed)
+    plan = ssh.plan(off, W, delta, 1)
+    bits, nbits, rep = ssh.sketch_multi(xd, torch.as_tensor(off).cuda(), ssh.MultiFilter(R, delta),
+                                        torch.as_tensor(plan.bit_word_off).cuda())
+    torch.cuda.synchronize()
+    ssh.check_device_errors()
+    nb = oracle.num_bits(m, W, delta)
+    assert bool((nbits == nb).all())
+    print(f"[case] repaired {int(rep.cpu()[0])} of {F * N * nb} pairs", flush=True)
+    rng = np.random.default_rng(7)
+    sample = np.sort(np.concatenate([rng.choice(N, 10, replace=False), [0, N - 1]]))
+    lazy = _LazyWalks(m, seed)
+    bwo = plan.bit_word_off
+    nbh = np.full(N, nb, np.int32)
+    for s in sample:
+        rows = bits[:, bwo[s]:bwo[s + 1]].cpu().numpy()
+        xs = lazy[s * m:(s + 1) * m]
+        for f in range(F):
+            want = oracle.sketch_series(xs, R[f], W, delta)
+            got = unpack_bits(rows[f], np.array([0, bwo[s + 1] - bwo[s]]), nbh[s:s + 1], 0)
+            assert np.array_equal(got, want), (s, f)
+            if nb % 64:
+                assert int(rows[f][-1]) >> (nb % 64) == 0
+
