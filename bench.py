@@ -352,8 +352,8 @@ def run_workload(name: str, args, main: bool):
         "sketch": N * (4 * m + 8 * words + 4) + 16 * (N + 1),
         "shingle": N * (8 * words + 4 + 4) + 16 * (N + 1) + 8 * sum_d,
         "cws": 8 * sum_d + N * (8 * p.H + 4 + 8 + 8 * p.L),
-        # radix passes over the top 24 bits (N <= 2^20) or 32: keys and ids read twice, written once
-        "table_build": (3 if N <= (1 << 20) else 4) * N * p.L * (8 + 12 + 12),
+        # radix passes over the top 24 bits (N <= 2^24) or 32: keys and ids read twice, written once
+        "table_build": (3 if N <= (1 << 24) else 4) * N * p.L * (8 + 12 + 12),
     }
     stage_hbm = {k: {"GB/s": b / (per_stage[k] / 1e3) / 1e9,
                      "frac_hbm": b / (per_stage[k] / 1e3) / 1e9 / HBM_PEAK_GBS}

@@ -219,7 +219,7 @@ ssh_status ssh_cws_band_keys(const uint32_t* codes, const uint32_t* counts,
 size_t ssh_table_workspace_bytes(int64_t N, int32_t L);
 
 /* Hash tables (Algorithm 1).  Table l lists every (key, id) pair of the batch
- * ordered by the top B bits of the key, B = 24 when N <= 2^20 and 32
+ * ordered by the top B bits of the key, B = 24 when N <= 2^24 and 32
  * otherwise, ids ascending among equal top bits (a stable sort of ids
  * 0..N-1).  A bucket is the set of ids with one full key; ssh_probe finds it
  * inside the run of its top B bits.
@@ -245,7 +245,7 @@ size_t ssh_table_insert_workspace_bytes(int64_t M, int32_t L);
  *   tab_keys, tab_ids   [L * N] tables of N entries
  *   out_keys, out_ids   [L * (N + M)] output tables, not aliasing the inputs
  *   ws, ws_bytes        at least ssh_table_insert_workspace_bytes(M, L)
- * Returns SSH_EUNSUPPORTED when N and N + M lie on different sides of 2^20
+ * Returns SSH_EUNSUPPORTED when N and N + M lie on different sides of 2^24
  * (the tables' sort width changes there: build them again). */
 ssh_status ssh_table_insert(const uint64_t* tab_keys, const uint32_t* tab_ids, int64_t N,
                             const uint64_t* new_keys, int64_t M, int32_t L, int64_t id_base,
@@ -267,7 +267,7 @@ size_t ssh_table_delete_workspace_bytes(int64_t N, int32_t L);
  *                      another number raises a device flag
  *   out_keys, out_ids  [L * n_live] output tables, not aliasing the inputs
  *   ws, ws_bytes       at least ssh_table_delete_workspace_bytes(N, L)
- * Returns SSH_EUNSUPPORTED when N and n_live lie on different sides of 2^20. */
+ * Returns SSH_EUNSUPPORTED when N and n_live lie on different sides of 2^24. */
 ssh_status ssh_table_delete(const uint64_t* tab_keys, const uint32_t* tab_ids, int64_t N, int32_t L,
                             const uint8_t* dead, int64_t id_bound, int64_t n_live,
                             uint64_t* out_keys, uint32_t* out_ids, void* ws, size_t ws_bytes,

@@ -4,7 +4,7 @@
 // Keys: table l folds its K hash values with the SplitMix64 output function.
 // Tables: the keys [N][L] are first transposed to table-major [L][N]; then,
 // per table, a stable LSD radix sort of (key, id) on the top B bits of the
-// key (table_sort_bits: 24 for N <= 2^20, else 32), B / 8 digit passes: the
+// key (table_sort_bits: 24 for N <= 2^24, else 32), B / 8 digit passes: the
 // probe finds a bucket by the run of its top B bits, and 24 bits keep runs
 // short at that size.  Each pass is four launches over all tables at
 // once: per-tile digit histograms, a segmented reduce and then scan of the
@@ -465,7 +465,7 @@ ssh_status table_insert_launch(const uint64_t* tab_keys, const uint32_t* tab_ids
                                uint64_t* out_keys, uint32_t* out_ids, void* ws, size_t ws_bytes,
                                hipStream_t stream) {
   if (N > 0 && table_sort_bits(N) != table_sort_bits(N + M))
-    return fail(SSH_EUNSUPPORTED, "ssh_table_insert: the sort width changes at 2^20 series; "
+    return fail(SSH_EUNSUPPORTED, "ssh_table_insert: the sort width changes at 2^24 series; "
                                   "build the tables again");
   if (ws_bytes < table_insert_workspace_bytes(M, L))
     return fail(SSH_EINVAL, "ssh_table_insert: workspace too small");
@@ -588,7 +588,7 @@ ssh_status table_delete_launch(const uint64_t* tab_keys, const uint32_t* tab_ids
                                uint64_t* out_keys, uint32_t* out_ids, void* ws, size_t ws_bytes,
                                hipStream_t stream) {
   if (n_live > 0 && table_sort_bits(N) != table_sort_bits(n_live))
-    return fail(SSH_EUNSUPPORTED, "ssh_table_delete: the sort width changes at 2^20 series; "
+    return fail(SSH_EUNSUPPORTED, "ssh_table_delete: the sort width changes at 2^24 series; "
                                   "build the tables again");
   if (ws_bytes < table_delete_workspace_bytes(N, L))
     return fail(SSH_EINVAL, "ssh_table_delete: workspace too small");

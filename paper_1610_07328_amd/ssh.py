@@ -349,7 +349,7 @@ def wmh_int(codes, counts, hist_off, n_distinct, H: int, seed: int, out=None):
 
 def table_sort_bits(N: int) -> int:
     """Top key bits the tables of N series are ordered by (the probe's search width)."""
-    return 24 if N <= (1 << 20) else 32
+    return 24 if N <= (1 << 24) else 32
 
 
 def table_workspace_bytes(N: int, L: int) -> int:

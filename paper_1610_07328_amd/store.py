@@ -82,7 +82,7 @@ class DynamicIndex:
                                keys_new.view(torch.int64)]).view(torch.uint64)
         self.dead = torch.cat([self.dead, torch.zeros(M, dtype=torch.uint8, device=self.dev)])
         self.n_live += M
-        if rebuild:  # crossing 2^20 series without deletions: the same tables, built anew
+        if rebuild:  # crossing 2^24 series without deletions: the same tables, built anew
             self.tab_keys, self.tab_ids = ssh.table_build(self.keys)
         return np.arange(base, base + M, dtype=np.int64)
 

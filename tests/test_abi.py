@@ -108,13 +108,13 @@ def test_validation_rejects_without_device_work(ssh):
                                 dummy, dummy, None) == EINVAL
     # table updates: the sort width may not change, id_base may not reuse ids,
     # n_live within [0, N]; all refused before any device work
-    assert L.ssh_table_insert(dummy, dummy, (1 << 20) - 5, dummy, 10, 4, (1 << 20) - 5, dummy,
+    assert L.ssh_table_insert(dummy, dummy, (1 << 24) - 5, dummy, 10, 4, (1 << 24) - 5, dummy,
                               dummy, dummy, 1 << 30, None) == EUNSUP
     assert L.ssh_table_insert(dummy, dummy, 100, dummy, 10, 4, 99, dummy, dummy, dummy, 1 << 30,
                               None) == EINVAL
     assert L.ssh_table_delete(dummy, dummy, 100, 4, dummy, 100, 101, dummy, dummy, dummy,
                               1 << 20, None) == EINVAL
-    assert L.ssh_table_delete(dummy, dummy, (1 << 20) + 5, 4, dummy, (1 << 20) + 5, 1000, dummy,
+    assert L.ssh_table_delete(dummy, dummy, (1 << 24) + 5, 4, dummy, (1 << 24) + 5, 1000, dummy,
                               dummy, dummy, 1 << 30, None) == EUNSUP
     # the pruned re-rank validates the same way, and its workspace must be large enough
     assert L.dtw_rerank_lb(dummy, dummy, 1, dummy, dummy, 10, dummy, dummy, 8, 0.1, 9,

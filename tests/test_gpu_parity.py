@@ -627,11 +627,11 @@ def test_c1_hash_values_and_keys_exact(ssh, c1):
 
 
 @pytest.mark.parametrize("N,L,distinct", [(2000, 5, None), (10007, 3, 50), (4096, 2, 1),
-                                          (3000, 65, 40), (1 << 20, 2, 300),
-                                          ((1 << 20) + 1, 2, 300)])
+                                          (3000, 65, 40), (1 << 24, 1, 3000),
+                                          ((1 << 24) + 1, 1, 3000)])
 def test_table_build_exact(ssh, N, L, distinct):
     """Every bucket of Algorithm 1 read back from the device tables (three radix
-    passes for N <= 2^20, four above; L > 64 straight from the series-major keys)."""
+    passes for N <= 2^24, four above; L > 64 straight from the series-major keys)."""
     _announce(f"table build N={N} L={L}")
     rng = np.random.default_rng(N)
     if distinct is None:
@@ -644,7 +644,7 @@ def test_table_build_exact(ssh, N, L, distinct):
     tk, ti = ssh.table_build(to_dev(keys))
     torch.cuda.synchronize()
     assert_tables_match(to_np(tk), to_np(ti), keys, oracle.build_tables(keys))
-    if N > 1 << 20:  # the probe's search over the 32-bit order, against the brute-force oracle
+    if N > 1 << 24:  # the probe's search over the 32-bit order, against the brute-force oracle
         hv = rng.integers(0, 4, size=(N, 6), dtype=np.int64).astype(np.uint64)
         qs = [0, 1, 5, N - 1]
         cand, ncand, rs = ssh.probe(tk, ti, to_dev(keys), to_dev(hv), to_dev(keys[qs]),
