@@ -335,6 +335,25 @@ def test_cws_equal_keys_resolved_exactly(ssh):
         assert np.array_equal(hv[s], oracle.cws(c, k, r, lnc, beta, lnS)[2]), s
 
 
+@pytest.mark.parametrize("split", [True, False])
+@pytest.mark.parametrize("n,H", [(8, 200), (7, 300), (6, 132)])
+def test_cws_several_hash_passes_exact(ssh, n, H, split):
+    """H above 128: two or three passes of 128 hashes over the tokens, the
+    last one partial (H = 200 is the large workload's).  Random weighted
+    sets, light and heavy, and an empty one, against the oracle; split: fewer
+    than 4,096 series (a workgroup per series), else one wave per series."""
+    _announce(f"cws several hash passes n={n} H={H} split={split}")
+    rng = np.random.default_rng(H + n)
+    sets = [(np.zeros(0, np.uint32), np.zeros(0, np.uint32))]
+    for i in range(120):
+        D = int(rng.integers(1, min(200, 1 << n) + 1))
+        c = np.sort(rng.choice(1 << n, size=D, replace=False)).astype(np.uint32)
+        k = (rng.integers(1, 3, size=D) if i % 2 else rng.integers(1, 300, size=D)).astype(np.uint32)
+        sets.append((c, k))
+    reps = 1 if split else 4200 // len(sets) + 1
+    _cws_sets_exact(ssh, n, datagen.cws_draws(n, H, seed=n), sets * reps)
+
+
 def _tied_draws(n, H, a, b, seed, r0=50.0):
     """Tokens a and b get identical draw rows with r in [r0, r0 + 1) and
     beta < 0.8, so t = 0 for every weight w with ln w / r0 < 0.2 and their
@@ -373,15 +392,17 @@ def _cws_sets_exact(ssh, n, draws, sets, expect_k=None):
         assert np.array_equal(hv[s], checked[key]), s
 
 
+@pytest.mark.parametrize("H", [130, 132])
 @pytest.mark.parametrize("split", [True, False])
-def test_cws_exact_ties_go_to_the_smaller_token(ssh, split):
+def test_cws_exact_ties_go_to_the_smaller_token(ssh, split, H):
     """Two tokens with bit-identical ln a at the minimum, the smaller one wins:
     both keyed (pass A: equal keys, exact re-scan), keyed against heavy in
     either order (pass B's (ln a, k) comparison), and the two run codes at
     counts up to 4096 (keyed by their run rows).  split: fewer than 4,096
-    series (a workgroup per series), else one wave per series."""
-    _announce(f"cws exact ties split={split}")
-    n, H, a, b = 6, 130, 9, 41
+    series (a workgroup per series), else one wave per series.  H = 130 and
+    132: the second pass over the tokens holds one or two hashes per lane."""
+    _announce(f"cws exact ties split={split} H={H}")
+    n, a, b = 6, 9, 41
     rng = np.random.default_rng(31)
     weights = [(1, 1), (2, 2), (7, 3), (1, 10), (10, 1), (20, 100), (8, 8), (1, 7), (7, 8)]
     base = []
