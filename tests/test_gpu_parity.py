@@ -125,6 +125,29 @@ def test_sketch_adversarial_near_zero_windows(ssh, W, delta):
     assert rep > 0  # these windows must take the float64 path
 
 
+@pytest.mark.parametrize("W,delta", [(80, 3), (128, 4)])
+def test_sketch_filter_of_wide_dynamic_range(ssh, W, delta):
+    """Filter entries from 2^-13 to 2^10, all above fp16's subnormal range, so
+    the matrix path's L1 margin applies with weights over many binades; some
+    entries exactly representable in fp16.  Near-zero windows over many
+    scales, re-aimed at this filter, and random walks, against the oracle."""
+    _announce(f"sketch wide-range filter W={W}")
+    r, series = _near_zero_windows(W, 300, seed=W + 2)
+    rng = np.random.default_rng(W + 3)
+    r = r.astype(np.float64) * np.exp2(rng.uniform(-13, 10, size=W))
+    r = (np.where(r < 0, -1.0, 1.0) * np.maximum(np.abs(r), 2.0 ** -13)).astype(np.float32)
+    r[::7] = np.float16(r[::7]).astype(np.float32)  # no low part
+    assert np.all(np.abs(r) >= 2.0 ** -14)
+    rr = r.astype(np.float64)
+    for i, w in enumerate(series):  # re-aim the windows at the new filter
+        w = w.astype(np.float64)
+        w[-1] = -float(np.dot(rr[:-1], w[:-1])) / rr[-1]
+        series[i] = w.astype(np.float32)
+    series = series + list(datagen.random_walks(20, 1024, seed=W + 4))
+    x, off = ragged(series)
+    assert _assert_sketch_equal(ssh, x, off, r, W, delta) > 0
+
+
 @pytest.mark.parametrize("W,delta", [(80, 3), (64, 4)])
 def test_sketch_filter_with_subnormal_fp16_entry(ssh, W, delta):
     """A filter entry below 2^-14 (fp16's subnormal range) takes the fast path's
