@@ -245,6 +245,22 @@ def upload_walks(N: int, m: int, seed: int, dev):
     return x
 
 
+def hbm_copy_microbench(nbytes: int = 1 << 32, reps: int = 10) -> dict:
+    """A plain device-to-device copy of nbytes, timed with events: the HBM rate
+    a streaming kernel reaches on this GPU (bytes read plus bytes written),
+    beside the 8 TB/s datasheet peak the rooflines use."""
+    import torch
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda:0")
+    b = torch.empty_like(a)
+    a.fill_(1)
+    ms = event_ms(lambda: b.copy_(a), reps)
+    gbs = 2 * nbytes / (ms / 1e3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    return {"bytes_read_plus_written": 2 * nbytes, "ms": ms, "GB/s": gbs,
+            "frac_of_peak": gbs / HBM_PEAK_GBS}
+
+
 def event_ms(fn, reps: int) -> float:
     import torch
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -891,6 +907,8 @@ def main():
     if not args.no_serving:
         out["serving"] = run_serving(args)
         out["query_latency_ms_served"] = out["serving"]["continuous_batching"]["latency_ms"]
+    out["hbm_copy_microbench"] = hbm_copy_microbench()
+    log(f"HBM copy micro-benchmark: {out['hbm_copy_microbench']['GB/s']:.0f} GB/s")
     if not args.no_cpu_baseline:
         log("cpu baseline")
         out["cpu_baseline"] = cpu_baseline(cfg, args.seed, min(args.cpu_sample, cfg["N"]), Q)
