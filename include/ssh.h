@@ -134,7 +134,7 @@ ssh_status ssh_shingle(const uint64_t* bits, const int64_t* bit_word_off, const 
 /* Random numbers of consistent weighted sampling, one triple per (token k,
  * hash j), code-major: element [k * H + j] of each array.  They are inputs,
  * drawn by the caller: r ~ Gamma(2,1) (0 < r < 1e5), lnc = ln c with
- * c ~ Gamma(2,1), beta ~ U[0,1).  a1, lnS and k16 are scratch tables the
+ * c ~ Gamma(2,1), beta ~ U[0,1).  a1, lnS, k16 and rb are scratch tables the
  * caller allocates and fills once with ssh_cws_prepare. */
 typedef struct {
   int32_t n;          /* token length; tables have 2^n rows */
@@ -150,9 +150,12 @@ typedef struct {
                          (code, weight 1..SSH_CWS_KEY_WEIGHTS), then rows for
                          the codes 0 and 2^n - 1 at weights 1..SSH_CWS_RUN_CAP,
                          then one padding row; R * H2 * 2 must stay below 2^31 */
+  double* rb;         /* [2^n * H * 2] prepared: r and beta of (k, j) side by side at
+                         [2 (k * H + j)] and [2 (k * H + j) + 1], so that a winner's
+                         t takes one 16-byte read */
 } ssh_cws_tables;
 
-/* Fill tab->a1, tab->lnS and tab->k16 from the draws (device work on
+/* Fill tab->a1, tab->lnS, tab->k16 and tab->rb from the draws (device work on
  * `stream`).  tab is a [host] struct of device pointers.  A draw outside the
  * ranges above raises a device flag that ssh_check_device_errors reports.
  * Returns SSH_EINVAL for n outside 1..SSH_MAX_N, H < 1 or a null pointer. */

@@ -243,7 +243,7 @@ static ssh_status check_tables(const ssh_cws_tables* tab, const char* who) {
   if (!tab) return fail(SSH_EINVAL, std::string(who) + ": null tables");
   if (tab->n < 1 || tab->n > SSH_MAX_N) return fail(SSH_EINVAL, std::string(who) + ": n out of [1, SSH_MAX_N]");
   if (tab->H < 1) return fail(SSH_EINVAL, std::string(who) + ": H < 1");
-  if (!tab->r || !tab->lnc || !tab->beta || !tab->a1 || !tab->lnS || !tab->k16)
+  if (!tab->r || !tab->lnc || !tab->beta || !tab->a1 || !tab->lnS || !tab->k16 || !tab->rb)
     return fail(SSH_EINVAL, std::string(who) + ": null table pointer");
   return SSH_OK;
 }

@@ -179,7 +179,7 @@ __device__ __forceinline__ uint32_t key16(double la) {
 __global__ __launch_bounds__(256) void cws_prepare_kernel(
     const double* __restrict__ r, const double* __restrict__ lnc, const double* __restrict__ beta,
     int n, int H, int H2, double* __restrict__ a1, uint16_t* __restrict__ k16,
-    double* __restrict__ lnS, int* err) {
+    double* __restrict__ lnS, double2* __restrict__ rb, int* err) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t rows = key_rows(n);
   const int64_t cells = rows * H2;
@@ -207,8 +207,9 @@ __global__ __launch_bounds__(256) void cws_prepare_kernel(
     double tt;
     const double a = icws_ln_a(rr, bb, lc, ls, tt);
     k16[c] = (uint16_t)key16(a);
-    if (row < (1 << n)) {  // weight 1: the ln a table and the range checks of the draws
+    if (row < (1 << n)) {  // weight 1: the ln a and (r, beta) tables, range checks of the draws
       a1[i] = a;
+      rb[i] = make_double2(rr, bb);
       // r is bounded so that the float64 rounding of ln a stays far below the
       // pass-B slack (a Gamma(2,1) draw above 1e5 has probability ~e^-1e5)
       if (!(rr > 0.0) || !(rr < 1.0e5) || !(bb >= 0.0) || !(bb < 1.0) ||
@@ -224,12 +225,11 @@ __global__ __launch_bounds__(256) void cws_prepare_kernel(
 // main
 // ---------------------------------------------------------------------------
 struct CwsDev {
-  const double* r;
   const double* lnc;
-  const double* beta;
   const double* a1;
   const double* lnS;
   const uint16_t* k16;  // [key_rows(n)][H2] keys; the last row is padding
+  const double2* rb;    // [2^n][H] (r, beta)
   int H, H2, n;
 };
 
@@ -254,7 +254,8 @@ __device__ __forceinline__ double exact_ln_a(const CwsDev& t, uint32_t k, uint32
     tt = 0.0;
     return t.a1[i];
   }
-  return icws_ln_a(t.r[i], t.beta[i], t.lnc[i], lnS_of(t.lnS, c), tt);
+  const double2 q = t.rb[i];
+  return icws_ln_a(q.x, q.y, t.lnc[i], lnS_of(t.lnS, c), tt);
 }
 
 struct Best {
@@ -441,7 +442,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void c
             b[h].t = 0.0;
             if (c > 1u) {
               const int64_t i = (int64_t)b[h].k * H + (h ? j1 : j0);
-              b[h].t = __builtin_floor(lnS_of(t.lnS, c) / t.r[i] + t.beta[i]);
+              const double2 q = t.rb[i];  // one 16-byte read
+              b[h].t = __builtin_floor(lnS_of(t.lnS, c) / q.x + q.y);
             }
           }
           if (!any_heavy) done[h] = true;
@@ -506,7 +508,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void c
                 if (done[h]) continue;
                 const int j = h ? j1 : j0;
                 double tt;
-                const double la = icws_ln_a(t.r[row + j], t.beta[row + j], t.lnc[row + j], ls, tt);
+                const double2 q = t.rb[row + j];
+                const double la = icws_ln_a(q.x, q.y, t.lnc[row + j], ls, tt);
                 if (la < b[h].la || (la == b[h].la && k < b[h].k)) b[h] = Best{la, k, tt};
               }
             }
@@ -557,7 +560,8 @@ ssh_status cws_prepare_launch(const ssh_cws_tables* tab, hipStream_t stream) {
     return fail(SSH_EDEVICE, "ssh_cws_prepare: cannot resolve error flag");
   const int H2 = tab->H + (tab->H & 1);
   cws_prepare_kernel<<<grid_for(key_rows(tab->n) * H2, 256, 4096), 256, 0, stream>>>(
-      tab->r, tab->lnc, tab->beta, tab->n, tab->H, H2, tab->a1, tab->k16, tab->lnS, err);
+      tab->r, tab->lnc, tab->beta, tab->n, tab->H, H2, tab->a1, tab->k16, tab->lnS,
+      reinterpret_cast<double2*>(tab->rb), err);
   return check_launch("ssh_cws_prepare");
 }
 
@@ -577,7 +581,8 @@ ssh_status cws_launch(const uint32_t* codes, const uint32_t* counts, const int64
   // the key table is addressed by 32-bit byte offsets through a buffer resource
   if (key_rows(tab->n) * H2 * 2 >= (1ll << 31))
     return fail(SSH_EUNSUPPORTED, "ssh_cws: key table of 2 GiB or more");
-  CwsDev t{tab->r, tab->lnc, tab->beta, tab->a1, tab->lnS, tab->k16, tab->H, H2, tab->n};
+  CwsDev t{tab->lnc, tab->a1, tab->lnS, tab->k16,
+           reinterpret_cast<const double2*>(tab->rb), tab->H, H2, tab->n};
   const unsigned grid = grid_for(N, kCwsWaves, 1 << 16);
   const bool fused = keys != nullptr && tab->H <= kBandLds;
   // small batches (one series per wave would leave most of the GPU idle): a

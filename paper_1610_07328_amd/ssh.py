@@ -40,7 +40,7 @@ class SSHError(RuntimeError):
 
 class _CwsTablesC(ctypes.Structure):
     _fields_ = [("n", _i32), ("H", _i32), ("r", _vp), ("lnc", _vp), ("beta", _vp),
-                ("a1", _vp), ("lnS", _vp), ("k16", _vp)]
+                ("a1", _vp), ("lnS", _vp), ("k16", _vp), ("rb", _vp)]
 
 
 # name -> (restype, argtypes); mirrors include/ssh.h
@@ -267,7 +267,7 @@ def shingle(bits, bit_word_off, nbits, n: int, hist_off, out=None):
 
 
 class CwsTables:
-    """Device copies of the ICWS draws plus the prepared a1, lnS and key tables."""
+    """Device copies of the ICWS draws plus the prepared a1, lnS, key and (r, beta) tables."""
 
     def __init__(self, r: np.ndarray, lnc: np.ndarray, beta: np.ndarray, n: int,
                  device="cuda"):
@@ -283,8 +283,10 @@ class CwsTables:
         self.lnS = torch.empty(LNS_ENTRIES, **f64)
         rows = CWS_KEY_WEIGHTS * D + 2 * CWS_RUN_CAP + 1
         self.k16 = torch.empty((rows, H + (H & 1)), dtype=torch.int16, device=device)
+        self.rb = torch.empty((D, H, 2), **f64)
         self._c = _CwsTablesC(n, H, self.r.data_ptr(), self.lnc.data_ptr(), self.beta.data_ptr(),
-                              self.a1.data_ptr(), self.lnS.data_ptr(), self.k16.data_ptr())
+                              self.a1.data_ptr(), self.lnS.data_ptr(), self.k16.data_ptr(),
+                              self.rb.data_ptr())
         _check(lib().ssh_cws_prepare(ctypes.byref(self._c), _stream()), "ssh_cws_prepare")
 
 

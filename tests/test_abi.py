@@ -130,10 +130,14 @@ def test_validation_rejects_without_device_work(ssh):
     # empty batches are not errors
     assert L.ssh_sketch(None, None, 0, r.ctypes.data, 8, 1, None, None, None, None, None) == 0
     # CWS tables with n out of range
-    t = ssh._CwsTablesC(17, 4, 16, 16, 16, 16, 16, 16)
+    t = ssh._CwsTablesC(17, 4, 16, 16, 16, 16, 16, 16, 16)
     assert L.ssh_cws_prepare(ctypes.byref(t), None) == EINVAL
+    # a null scratch table is refused
+    t = ssh._CwsTablesC(4, 12, 16, 16, 16, 16, 16, 16, None)
+    assert L.ssh_cws_prepare(ctypes.byref(t), None) == EINVAL
+    assert b"null table" in L.ssh_last_error()
     # fused CWS + band keys: K * L must equal H, and no null output
-    t = ssh._CwsTablesC(4, 12, 16, 16, 16, 16, 16, 16)
+    t = ssh._CwsTablesC(4, 12, 16, 16, 16, 16, 16, 16, 16)
     assert L.ssh_cws_band_keys(dummy, dummy, dummy, dummy, 4, ctypes.byref(t), 5, 2, 7, dummy,
                                dummy, None) == EINVAL
     assert b"K * L" in L.ssh_last_error()
