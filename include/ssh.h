@@ -149,7 +149,9 @@ typedef struct {
                          prepared 16-bit monotone keys of ln a, one row per
                          (code, weight 1..SSH_CWS_KEY_WEIGHTS), then rows for
                          the codes 0 and 2^n - 1 at weights 1..SSH_CWS_RUN_CAP,
-                         then one padding row; R * H2 * 2 must stay below 2^31 */
+                         then one padding row; stored in column chunks of 128
+                         hashes (chunk by chunk, each row-major, the last one
+                         H2 - 128 q wide); R * H2 * 2 must stay below 2^31 */
   double* rb;         /* [2^n * H * 2] prepared: r and beta of (k, j) side by side at
                          [2 (k * H + j)] and [2 (k * H + j) + 1], so that a winner's
                          t takes one 16-byte read */

@@ -170,6 +170,23 @@ __device__ __forceinline__ uint32_t key_row(uint32_t code, uint32_t c, int n) {
   return kNoRow;
 }
 
+// The key table is stored in column chunks of kKeyChunk hashes, chunk-major:
+// chunk q holds the keys of hashes 128 q .. 128 q + w_q - 1 of every row, row
+// after row (w_q = min(128, H - 128 q) rounded up to even), so that one pass
+// of 128 hashes reads whole, contiguous row segments.  The chunks sum to H2
+// columns, H2 = H rounded up to even.
+constexpr int kKeyChunk = 128;
+static_assert(kKeyChunk == 2 * kWave, "one pass of the main kernel covers one key chunk");
+__host__ __device__ inline int key_chunk_width(int H, int q) {
+  const int w = H - kKeyChunk * q < kKeyChunk ? H - kKeyChunk * q : kKeyChunk;
+  return w + (w & 1);
+}
+// element index of key (row, hash j) among rows key rows
+__host__ __device__ inline int64_t key_index(int64_t rows, int H, int64_t row, int j) {
+  const int q = j / kKeyChunk;
+  return rows * kKeyChunk * q + row * key_chunk_width(H, q) + (j - kKeyChunk * q);
+}
+
 __device__ __forceinline__ uint32_t key16(double la) {
   const double q = __builtin_floor((la - kKeyLo) * kKeyScale);  // monotone steps
   const double c = q < 0.0 ? 0.0 : (q > 65534.0 ? 65534.0 : q);
@@ -187,8 +204,9 @@ __global__ __launch_bounds__(256) void cws_prepare_kernel(
   for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < cells; c += stride) {
     const int64_t row = c / H2;
     const int j = (int)(c - row * H2);
+    const int64_t kc = key_index(rows, H, row, j);
     if (j >= H || row == rows - 1) {  // padding column or row, never wins a minimum
-      k16[c] = 0xFFFF;
+      k16[kc] = 0xFFFF;
       continue;
     }
     uint32_t code, w;
@@ -206,7 +224,7 @@ __global__ __launch_bounds__(256) void cws_prepare_kernel(
     const double ls = w == 1u ? 0.0 : ln_integer((double)w);
     double tt;
     const double a = icws_ln_a(rr, bb, lc, ls, tt);
-    k16[c] = (uint16_t)key16(a);
+    k16[kc] = (uint16_t)key16(a);
     if (row < (1 << n)) {  // weight 1: the ln a and (r, beta) tables, range checks of the draws
       a1[i] = a;
       rb[i] = make_double2(rr, bb);
@@ -228,7 +246,7 @@ struct CwsDev {
   const double* lnc;
   const double* a1;
   const double* lnS;
-  const uint16_t* k16;  // [key_rows(n)][H2] keys; the last row is padding
+  const uint16_t* k16;  // key_rows(n) x H2 keys in column chunks; the last row is padding
   const double2* rb;    // [2^n][H] (r, beta)
   int H, H2, n;
 };
@@ -298,11 +316,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void c
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave-uniform
   const int lane = lane_id();
   const int H = t.H;
-  const uint32_t row_bytes = (uint32_t)t.H2 * 2u;
-  const uint32_t pad_row = (uint32_t)(key_rows(t.n) - 1) * row_bytes;
-  // bounds-checked view of the key table: a lane past H reads inside it
-  const __amdgpu_buffer_rsrc_t ktab = __builtin_amdgcn_make_buffer_rsrc(
-      (void*)t.k16, 0, (int)(pad_row + row_bytes), 0x00020000);
+  const uint32_t krows = (uint32_t)key_rows(t.n);  // the table is below 2^31 bytes
   uint2* klist2 = reinterpret_cast<uint2*>(klist[w]);
   const uint64_t lt_mask = (1ull << lane) - 1ull;
   const int64_t stride = SPLIT ? (int64_t)gridDim.x : (int64_t)gridDim.x * kCwsWaves;
@@ -344,7 +358,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void c
     for (int hb0 = 0; hb0 < H; hb0 += 2 * kWave) {
       const int j0 = hb0 + 2 * lane, j1 = j0 + 1;
       const bool v0 = j0 < H, v1 = j1 < H;
-      const uint32_t colb = (uint32_t)(v0 ? j0 : 0) * 2u;  // byte offset of the key pair
+      // this pass's key chunk: its first key, row stride and padding row (bytes),
+      // read through a bounds-checked view of the chunk (a lane past H reads
+      // inside it)
+      const int qk = hb0 / kKeyChunk;
+      const uint32_t row_bytes = (uint32_t)key_chunk_width(H, qk) * 2u;
+      const uint16_t* kchunk = t.k16 + (size_t)krows * (size_t)(kKeyChunk * qk);
+      const uint32_t pad_row = (krows - 1u) * row_bytes;
+      const __amdgpu_buffer_rsrc_t ktab = __builtin_amdgcn_make_buffer_rsrc(
+          (void*)kchunk, 0, (int)(krows * row_bytes), 0x00020000);
+      const uint32_t colb = (uint32_t)(v0 ? j0 - hb0 : 0) * 2u;  // byte offset in the row
       Best b[2] = {Best{INFINITY, 0u, 0.0}, Best{INFINITY, 0u, 0.0}};
       bool done[2] = {!v0, !v1};
       bool any_heavy = false;
@@ -462,7 +485,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void c
               const uint32_t c = counts_s[d];
               const uint32_t k = codes_s[d];
               const uint32_t krow = key_row(k, c, t.n);
-              if (krow == kNoRow || (uint32_t)t.k16[(int64_t)krow * t.H2 + j] != K) continue;
+              if (krow == kNoRow ||
+                  (uint32_t)kchunk[krow * (row_bytes >> 1) + (uint32_t)(j - hb0)] != K)
+                continue;
               double tt;
               const double la = exact_ln_a(t, k, c, j, tt);
               if (la < e.la) e = Best{la, k, tt};
