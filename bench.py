@@ -70,11 +70,11 @@ UPLOAD_ROWS = 1 << 18
 # kernel's source file still has the digest it was measured with.
 MEASURED_TRAFFIC = {
     # (kernel, workload): (source file, sha256 of it, FETCH_SIZE KiB, WRITE_SIZE KiB,
-    #                      fetch scale, write scale); the 1 GiB copy read 524307.0 KiB
+    #                      fetch scale, write scale); the 1 GiB copy read 524306.6 KiB
     #                      on FETCH_SIZE and 1048576 KiB on WRITE_SIZE
     ("cws_kernel", "large"): ("paper_1610_07328_amd/csrc/cws.hip",
-                              "ac92a074a6d2659b844a073e820932f584a931c45ac47fa21d226bb4bb9b6665",
-                              166218033.8125, 17818988.09375, 1048576.0 / 524307.0, 1.0),
+                              "161c9d0754081c051d81c4b047e2a5a33109b64541640399dfc13632f39f9c7d",
+                              149582199.3125, 17739821.375, 1048576.0 / 524306.625, 1.0),
 }
 
 
