@@ -144,18 +144,25 @@ typedef struct {
   const double* beta; /* [2^n * H] */
   double* a1;         /* [2^n * H] prepared: ln a of a token of weight 1 */
   double* lnS;        /* [SSH_LNS_ENTRIES] prepared: correctly rounded ln s */
-  uint16_t* k16;      /* [R * H2], H2 = H rounded up to even and
-                         R = SSH_CWS_KEY_WEIGHTS * 2^n + 2 * SSH_CWS_RUN_CAP + 1:
-                         prepared 16-bit monotone keys of ln a, one row per
-                         (code, weight 1..SSH_CWS_KEY_WEIGHTS), then rows for
-                         the codes 0 and 2^n - 1 at weights 1..SSH_CWS_RUN_CAP,
-                         then one padding row; stored in column chunks of 128
-                         hashes (chunk by chunk, each row-major, the last one
-                         H2 - 128 q wide); R * H2 * 2 must stay below 2^31 */
+  uint16_t* k16;      /* [ssh_cws_key_table_elems(n, H)]: prepared 16-bit
+                         monotone keys of ln a, R = SSH_CWS_KEY_WEIGHTS * 2^n +
+                         2 * SSH_CWS_RUN_CAP + 1 rows: one per (code, weight
+                         1..SSH_CWS_KEY_WEIGHTS), then the codes 0 and 2^n - 1 at
+                         weights 1..SSH_CWS_RUN_CAP, then one padding row; stored
+                         in column chunks of 128 hashes, chunk by chunk, each
+                         row-major (see ssh_cws_key_table_elems); the table must
+                         stay below 2^31 bytes */
   double* rb;         /* [2^n * H * 2] prepared: r and beta of (k, j) side by side at
                          [2 (k * H + j)] and [2 (k * H + j) + 1], so that a winner's
                          t takes one 16-byte read */
 } ssh_cws_tables;
+
+/* Elements (uint16) of the key table tab->k16 for token length n and H
+ * hashes: R rows times the chunks' widths, chunk q holding hashes
+ * 128 q .. min(128 (q + 1), H) - 1 at a row width of that count rounded up
+ * to even, or of 128 when that is above 96 (a row then starts on a 256-byte
+ * boundary of its chunk).  Returns 0 for n outside 1..SSH_MAX_N or H < 1. */
+int64_t ssh_cws_key_table_elems(int32_t n, int32_t H);
 
 /* Fill tab->a1, tab->lnS, tab->k16 and tab->rb from the draws (device work on
  * `stream`).  tab is a [host] struct of device pointers.  A draw outside the

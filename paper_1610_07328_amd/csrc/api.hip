@@ -41,6 +41,7 @@ ssh_status shingle_launch(const uint64_t* bits, const int64_t* bit_word_off, con
                           int64_t N, int n, uint32_t* codes, uint32_t* counts,
                           const int64_t* hist_off, int32_t* n_distinct, hipStream_t stream);
 ssh_status cws_prepare_launch(const ssh_cws_tables* tab, hipStream_t stream);
+int64_t cws_key_table_elems(int n, int H);
 ssh_status cws_launch(const uint32_t* codes, const uint32_t* counts, const int64_t* hist_off,
                       const int32_t* n_distinct, int64_t N, const ssh_cws_tables* tab, uint64_t* hv,
                       uint64_t* keys, int K, int L, uint64_t seed, hipStream_t stream);
@@ -247,6 +248,8 @@ static ssh_status check_tables(const ssh_cws_tables* tab, const char* who) {
     return fail(SSH_EINVAL, std::string(who) + ": null table pointer");
   return SSH_OK;
 }
+
+int64_t ssh_cws_key_table_elems(int32_t n, int32_t H) { return cws_key_table_elems(n, H); }
 
 ssh_status ssh_cws_prepare(const ssh_cws_tables* tab, void* stream) {
   ssh_status st = check_tables(tab, "ssh_cws_prepare");

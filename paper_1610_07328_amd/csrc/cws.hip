@@ -171,20 +171,21 @@ __device__ __forceinline__ uint32_t key_row(uint32_t code, uint32_t c, int n) {
 }
 
 // The key table is stored in column chunks of kKeyChunk hashes, chunk-major:
-// chunk q holds the keys of hashes 128 q .. 128 q + w_q - 1 of every row, row
-// after row (w_q = min(128, H - 128 q) rounded up to even), so that one pass
-// of 128 hashes reads whole, contiguous row segments.  The chunks sum to H2
-// columns, H2 = H rounded up to even.
+// chunk q holds the keys of hashes 128 q .. 128 q + c_q - 1 of every row, row
+// after row, at a row width w_q of c_q rounded up to even, or of 128 where c_q
+// is above 96: one pass of 128 hashes then reads whole, contiguous row
+// segments, and a row of 97 to 128 hashes starts on a 256-byte boundary
+// (2 cache lines per token, where a 200-byte stride averages 2.6).
 constexpr int kKeyChunk = 128;
 static_assert(kKeyChunk == 2 * kWave, "one pass of the main kernel covers one key chunk");
 __host__ __device__ inline int key_chunk_width(int H, int q) {
-  const int w = H - kKeyChunk * q < kKeyChunk ? H - kKeyChunk * q : kKeyChunk;
-  return w + (w & 1);
+  int w = H - kKeyChunk * q < kKeyChunk ? H - kKeyChunk * q : kKeyChunk;
+  w += w & 1;
+  return w > 96 ? kKeyChunk : w;
 }
-// element index of key (row, hash j) among rows key rows
-__host__ __device__ inline int64_t key_index(int64_t rows, int H, int64_t row, int j) {
-  const int q = j / kKeyChunk;
-  return rows * kKeyChunk * q + row * key_chunk_width(H, q) + (j - kKeyChunk * q);
+__host__ __device__ inline int key_table_cols(int H) {
+  const int nq = (H + kKeyChunk - 1) / kKeyChunk;
+  return kKeyChunk * (nq - 1) + key_chunk_width(H, nq - 1);
 }
 
 __device__ __forceinline__ uint32_t key16(double la) {
@@ -195,18 +196,21 @@ __device__ __forceinline__ uint32_t key16(double la) {
 
 __global__ __launch_bounds__(256) void cws_prepare_kernel(
     const double* __restrict__ r, const double* __restrict__ lnc, const double* __restrict__ beta,
-    int n, int H, int H2, double* __restrict__ a1, uint16_t* __restrict__ k16,
+    int n, int H, double* __restrict__ a1, uint16_t* __restrict__ k16,
     double* __restrict__ lnS, double2* __restrict__ rb, int* err) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t rows = key_rows(n);
-  const int64_t cells = rows * H2;
+  const int64_t cells = rows * key_table_cols(H);
   const uint32_t wrows = kKeyW << n;  // rows of the per-weight part
   for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < cells; c += stride) {
-    const int64_t row = c / H2;
-    const int j = (int)(c - row * H2);
-    const int64_t kc = key_index(rows, H, row, j);
+    // chunk q starts at element rows * 128 q; row and column inside it
+    const int q = (int)(c / (rows * kKeyChunk));
+    const int wq = key_chunk_width(H, q);
+    const int64_t e = c - rows * kKeyChunk * q;
+    const int64_t row = e / wq;
+    const int j = kKeyChunk * q + (int)(e - row * wq);
     if (j >= H || row == rows - 1) {  // padding column or row, never wins a minimum
-      k16[kc] = 0xFFFF;
+      k16[c] = 0xFFFF;
       continue;
     }
     uint32_t code, w;
@@ -224,7 +228,7 @@ __global__ __launch_bounds__(256) void cws_prepare_kernel(
     const double ls = w == 1u ? 0.0 : ln_integer((double)w);
     double tt;
     const double a = icws_ln_a(rr, bb, lc, ls, tt);
-    k16[kc] = (uint16_t)key16(a);
+    k16[c] = (uint16_t)key16(a);
     if (row < (1 << n)) {  // weight 1: the ln a and (r, beta) tables, range checks of the draws
       a1[i] = a;
       rb[i] = make_double2(rr, bb);
@@ -246,9 +250,9 @@ struct CwsDev {
   const double* lnc;
   const double* a1;
   const double* lnS;
-  const uint16_t* k16;  // key_rows(n) x H2 keys in column chunks; the last row is padding
+  const uint16_t* k16;  // key_rows(n) rows in column chunks; the last row is padding
   const double2* rb;    // [2^n][H] (r, beta)
-  int H, H2, n;
+  int H, n;
 };
 
 constexpr int kCwsWaves = 4;  // wavefronts per workgroup
@@ -579,13 +583,18 @@ int take_cws_err() {
   return v;
 }
 
+int64_t cws_key_table_elems(int n, int H) {
+  if (n < 1 || n > SSH_MAX_N || H < 1) return 0;
+  return key_rows(n) * key_table_cols(H);
+}
+
 ssh_status cws_prepare_launch(const ssh_cws_tables* tab, hipStream_t stream) {
   int* err = nullptr;
   if (hipGetSymbolAddress((void**)&err, HIP_SYMBOL(g_cws_err)) != hipSuccess)
     return fail(SSH_EDEVICE, "ssh_cws_prepare: cannot resolve error flag");
-  const int H2 = tab->H + (tab->H & 1);
-  cws_prepare_kernel<<<grid_for(key_rows(tab->n) * H2, 256, 4096), 256, 0, stream>>>(
-      tab->r, tab->lnc, tab->beta, tab->n, tab->H, H2, tab->a1, tab->k16, tab->lnS,
+  cws_prepare_kernel<<<grid_for(key_rows(tab->n) * key_table_cols(tab->H), 256, 4096), 256, 0,
+                       stream>>>(
+      tab->r, tab->lnc, tab->beta, tab->n, tab->H, tab->a1, tab->k16, tab->lnS,
       reinterpret_cast<double2*>(tab->rb), err);
   return check_launch("ssh_cws_prepare");
 }
@@ -602,12 +611,11 @@ ssh_status cws_launch(const uint32_t* codes, const uint32_t* counts, const int64
   int* err = nullptr;
   if (hipGetSymbolAddress((void**)&err, HIP_SYMBOL(g_cws_err)) != hipSuccess)
     return fail(SSH_EDEVICE, "ssh_cws: cannot resolve error flag");
-  const int H2 = tab->H + (tab->H & 1);
   // the key table is addressed by 32-bit byte offsets through a buffer resource
-  if (key_rows(tab->n) * H2 * 2 >= (1ll << 31))
+  if (key_rows(tab->n) * key_table_cols(tab->H) * 2 >= (1ll << 31))
     return fail(SSH_EUNSUPPORTED, "ssh_cws: key table of 2 GiB or more");
   CwsDev t{tab->lnc, tab->a1, tab->lnS, tab->k16,
-           reinterpret_cast<const double2*>(tab->rb), tab->H, H2, tab->n};
+           reinterpret_cast<const double2*>(tab->rb), tab->H, tab->n};
   const unsigned grid = grid_for(N, kCwsWaves, 1 << 16);
   const bool fused = keys != nullptr && tab->H <= kBandLds;
   // small batches (one series per wave would leave most of the GPU idle): a

@@ -58,6 +58,7 @@ SIGNATURES = {
     "ssh_sketch_multi": (_i32, [_vp, _vp, _i64, _vp, _i32, _i32, _i32, _vp, _i64, _vp, _vp, _vp,
                                 _i32, _vp]),
     "ssh_shingle": (_i32, [_vp, _vp, _vp, _i64, _i32, _vp, _vp, _vp, _vp, _vp]),
+    "ssh_cws_key_table_elems": (_i64, [_i32, _i32]),
     "ssh_cws_prepare": (_i32, [ctypes.POINTER(_CwsTablesC), _vp]),
     "ssh_cws": (_i32, [_vp, _vp, _vp, _vp, _i64, ctypes.POINTER(_CwsTablesC), _vp, _vp]),
     "ssh_band_keys": (_i32, [_vp, _i64, _i32, _i32, _u64, _vp, _vp]),
@@ -281,8 +282,10 @@ class CwsTables:
         self.beta = torch.as_tensor(np.ascontiguousarray(beta), **f64)
         self.a1 = torch.empty((D, H), **f64)
         self.lnS = torch.empty(LNS_ENTRIES, **f64)
-        rows = CWS_KEY_WEIGHTS * D + 2 * CWS_RUN_CAP + 1
-        self.k16 = torch.empty((rows, H + (H & 1)), dtype=torch.int16, device=device)
+        nkeys = int(lib().ssh_cws_key_table_elems(n, H))
+        if nkeys <= 0:
+            raise SSHError(f"no key table for n={n}, H={H}")
+        self.k16 = torch.empty(nkeys, dtype=torch.int16, device=device)
         self.rb = torch.empty((D, H, 2), **f64)
         self._c = _CwsTablesC(n, H, self.r.data_ptr(), self.lnc.data_ptr(), self.beta.data_ptr(),
                               self.a1.data_ptr(), self.lnS.data_ptr(), self.k16.data_ptr(),

@@ -129,6 +129,16 @@ def test_validation_rejects_without_device_work(ssh):
     assert L.ssh_sketch(dummy, dummy, 4, bad.ctypes.data, 3, 1, dummy, dummy, dummy, None, None) == EINVAL
     # empty batches are not errors
     assert L.ssh_sketch(None, None, 0, r.ctypes.data, 8, 1, None, None, None, None, None) == 0
+    # key-table sizes: chunks of 128 hashes, a chunk above 96 hashes padded to 128
+    rows = lambda n: 7 * (1 << n) + 2 * 4096 + 1
+    assert L.ssh_cws_key_table_elems(15, 100) == rows(15) * 128
+    assert L.ssh_cws_key_table_elems(15, 200) == rows(15) * (128 + 72)
+    assert L.ssh_cws_key_table_elems(15, 257) == rows(15) * (128 + 128 + 2)
+    assert L.ssh_cws_key_table_elems(4, 95) == rows(4) * 96
+    assert L.ssh_cws_key_table_elems(4, 96) == rows(4) * 96
+    assert L.ssh_cws_key_table_elems(4, 97) == rows(4) * 128
+    assert L.ssh_cws_key_table_elems(4, 3) == rows(4) * 4
+    assert L.ssh_cws_key_table_elems(0, 10) == 0 and L.ssh_cws_key_table_elems(4, 0) == 0
     # CWS tables with n out of range
     t = ssh._CwsTablesC(17, 4, 16, 16, 16, 16, 16, 16, 16)
     assert L.ssh_cws_prepare(ctypes.byref(t), None) == EINVAL
