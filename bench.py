@@ -70,11 +70,11 @@ UPLOAD_ROWS = 1 << 18
 # kernel's source file still has the digest it was measured with.
 MEASURED_TRAFFIC = {
     # (kernel, workload): (source file, sha256 of it, FETCH_SIZE KiB, WRITE_SIZE KiB,
-    #                      fetch scale, write scale); the 1 GiB copy read 524306.6 KiB
+    #                      fetch scale, write scale); the 1 GiB copy read 524307.1 KiB
     #                      on FETCH_SIZE and 1048576 KiB on WRITE_SIZE
     ("cws_kernel", "large"): ("paper_1610_07328_amd/csrc/cws.hip",
-                              "161c9d0754081c051d81c4b047e2a5a33109b64541640399dfc13632f39f9c7d",
-                              149582199.3125, 17739821.375, 1048576.0 / 524306.625, 1.0),
+                              "6ad3fe1afccc8b6957020ccd4a5088233ccf215c0980ac207f0582593ea865be",
+                              149563515.1875, 17739174.8125, 1048576.0 / 524307.0625, 1.0),
 }
 
 
