@@ -359,12 +359,14 @@ def test_cws_equal_keys_resolved_exactly(ssh):
 
 
 @pytest.mark.parametrize("split", [True, False])
-@pytest.mark.parametrize("n,H", [(8, 200), (7, 300), (6, 132)])
+@pytest.mark.parametrize("n,H", [(8, 200), (7, 300), (6, 132), (7, 230), (6, 97)])
 def test_cws_several_hash_passes_exact(ssh, n, H, split):
     """H above 128: two or three passes of 128 hashes over the tokens, the
-    last one partial (H = 200 is the large workload's).  Random weighted
-    sets, light and heavy, and an empty one, against the oracle; split: fewer
-    than 4,096 series (a workgroup per series), else one wave per series."""
+    last one partial (H = 200 is the large workload's); the key table's last
+    chunk is padded to 128 columns at H = 230 (102 hashes) and H = 97 (one
+    chunk, odd).  Random weighted sets, light and heavy, and an empty one,
+    against the oracle; split: fewer than 4,096 series (a workgroup per
+    series), else one wave per series."""
     _announce(f"cws several hash passes n={n} H={H} split={split}")
     rng = np.random.default_rng(H + n)
     sets = [(np.zeros(0, np.uint32), np.zeros(0, np.uint32))]
