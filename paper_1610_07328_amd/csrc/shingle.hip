@@ -22,6 +22,7 @@
 // holds the lane's rank bases, so the wave's LDS stays small (6 KB at n = 15)
 // and more waves fit a CU.
 // A token is the n bits in stream order read most significant first.
+#include <climits>
 #include <type_traits>
 
 #include "common.hpp"
@@ -30,8 +31,13 @@ namespace ssh {
 
 // Distinct tokens whose counts stay in LDS, two 16-bit counts per 32-bit word
 // (exact while the series has fewer than 2^16 shingles, the only case that
-// uses them: every count is at most the shingle count).
+// uses them: every count is at most the shingle count).  Series of at most
+// kCountCap shingles (so at most that many distinct tokens) run in one launch
+// with this buffer; longer ones in a second launch whose buffer holds
+// kCountCapLong, so that a long series' counts stay in LDS too without the
+// short series' launch giving up occupancy for it.
 constexpr int kCountCap = 512;
+constexpr int kCountCapLong = 2048;
 constexpr int kShWaves = 1;     // wavefronts per workgroup
 
 __host__ __device__ inline int shingle_bitmap_words(int n) { return n > 5 ? 1 << (n - 5) : 1; }
@@ -49,11 +55,11 @@ __host__ __device__ inline int shingle_pre_u16(int wpl) { return wpl >= 8 ? 0 : 
 
 // LDS bytes of one wave: bitmap (u32) and rank bases, separate bases (u16, to
 // 16 bytes), counts (u32)
-__host__ __device__ inline size_t shingle_lds_bytes(int n) {
+__host__ __device__ inline size_t shingle_lds_bytes(int n, int cap) {
   const int wpl = shingle_wpl(n);
   const size_t bm = (size_t)kWave * shingle_bs(wpl) * 4;
   const size_t pre = ((size_t)shingle_pre_u16(wpl) * 2 + 15) & ~(size_t)15;
-  return bm + pre + (size_t)kCountCap * 2;
+  return bm + pre + (size_t)cap * 2;
 }
 
 // 32 stream bits starting at bit b0 (bit j of the result is stream bit b0 + j),
@@ -79,12 +85,14 @@ __device__ __forceinline__ uint32_t wave_incl_scan_dpp(uint32_t v) {
   return v;
 }
 
-template <int WPL>
+// CAP: the LDS count capacity; the launch hashes the series whose shingle
+// count S lies in [s_lo, s_hi] (and records n_distinct only for those)
+template <int WPL, int CAP>
 __global__ __launch_bounds__(kShWaves * kWave) void shingle_kernel(
     const uint64_t* __restrict__ bits, const int64_t* __restrict__ bit_word_off,
     const int32_t* __restrict__ nbits, int64_t N, int n, uint32_t* __restrict__ codes,
     uint32_t* __restrict__ counts, const int64_t* __restrict__ hist_off,
-    int32_t* __restrict__ n_distinct, int* err) {
+    int32_t* __restrict__ n_distinct, int* err, int s_lo, int s_hi) {
   constexpr int BS = WPL + (WPL >= 8 ? 4 : 0);    // shingle_bs
   constexpr bool PAD = WPL >= 8;                  // rank bases in the padding words
   constexpr int GS = PAD ? WPL / 8 : 1;           // words per rank base
@@ -93,7 +101,7 @@ __global__ __launch_bounds__(kShWaves * kWave) void shingle_kernel(
   const int BW = shingle_bitmap_words(n);
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave-uniform
   const int lane = lane_id();
-  uint32_t* bm = smem32 + (shingle_lds_bytes(n) / 4) * w;
+  uint32_t* bm = smem32 + (shingle_lds_bytes(n, CAP) / 4) * w;
   uint16_t* pre = reinterpret_cast<uint16_t*>(bm + kWave * BS);  // separate bases (!PAD)
   uint32_t* cnt = bm + kWave * BS + ((shingle_pre_u16(WPL) * 2 + 15) & ~15) / 4;
   // this lane's words exist (WPL > 1: the bitmap is exactly 64 WPL words)
@@ -101,7 +109,7 @@ __global__ __launch_bounds__(kShWaves * kWave) void shingle_kernel(
   uint32_t* mybm = bm + lane * BS;
   uint16_t* mypre = PAD ? reinterpret_cast<uint16_t*>(mybm + WPL) : pre + lane * WPL;
   for (int i = lane; i < kWave * BS; i += kWave) bm[i] = 0;
-  for (int i = lane; i < kCountCap / 2; i += kWave) cnt[i] = 0;
+  for (int i = lane; i < CAP / 2; i += kWave) cnt[i] = 0;
   wave_sync_lds();
   const uint32_t mask = (1u << n) - 1u;  // n <= 16
   // slot of word wd, and the rank of its first token
@@ -130,6 +138,7 @@ __global__ __launch_bounds__(kShWaves * kWave) void shingle_kernel(
   for (int64_t s = (int64_t)blockIdx.x * kShWaves + w; s < N; s += (int64_t)gridDim.x * kShWaves) {
     const int nb = nbits[s];
     const int S = nb >= n ? nb - n + 1 : 0;
+    if (S < s_lo || S > s_hi) continue;  // the other launch's series
     const int64_t ho = hist_off[s];
     if (S == 0) {
       if (lane == 0) n_distinct[s] = 0;
@@ -212,7 +221,7 @@ __global__ __launch_bounds__(kShWaves * kWave) void shingle_kernel(
       if (own) mypre[0] = pv[0];
     }
     const uint32_t D = __builtin_amdgcn_readlane(incl, kWave - 1);
-    const bool in_lds = D <= (uint32_t)kCountCap && S < 65536;
+    const bool in_lds = D <= (uint32_t)CAP && S < 65536;
     if (!in_lds) {
       for (uint32_t i = lane; i < D; i += kWave) counts_s[i] = 0;
       // this wave's zero stores complete before its atomics below
@@ -221,7 +230,7 @@ __global__ __launch_bounds__(kShWaves * kWave) void shingle_kernel(
     wave_sync_lds();
 
     // 3. counts by rank (runs of equal tokens in a lane counted at once), codes
-    // at their ranks; counts in LDS or (more than kCountCap tokens) in memory,
+    // at their ranks; counts in LDS or (more than CAP tokens) in memory,
     // two copies of the loop so that each uses its own kind of atomic
     auto step3 = [&](auto lds_counts) {
       constexpr bool LDS_COUNTS = decltype(lds_counts)::value;
@@ -295,13 +304,19 @@ ssh_status shingle_launch(const uint64_t* bits, const int64_t* bit_word_off, con
   if (hipGetSymbolAddress((void**)&err, HIP_SYMBOL(g_shingle_err)) != hipSuccess)
     return fail(SSH_EDEVICE, "ssh_shingle: cannot resolve error flag");
   const int wpl = shingle_wpl(n);
-  const size_t shm = (size_t)kShWaves * shingle_lds_bytes(n);
   const unsigned grid = grid_for(N, kShWaves, 1 << 16);
   const dim3 block(kShWaves * kWave);
+  // series of up to kCountCap shingles, then the longer ones
+  const size_t shm = (size_t)kShWaves * shingle_lds_bytes(n, kCountCap);
+  const size_t shm_long = (size_t)kShWaves * shingle_lds_bytes(n, kCountCapLong);
 #define SSH_SHINGLE_CASE(V)                                                                     \
   case V:                                                                                       \
-    shingle_kernel<V><<<grid, block, shm, stream>>>(bits, bit_word_off, nbits, N, n, codes,      \
-                                                    counts, hist_off, n_distinct, err);          \
+    shingle_kernel<V, kCountCap><<<grid, block, shm, stream>>>(                                 \
+        bits, bit_word_off, nbits, N, n, codes, counts, hist_off, n_distinct, err, 0,           \
+        kCountCap);                                                                             \
+    shingle_kernel<V, kCountCapLong><<<grid, block, shm_long, stream>>>(                        \
+        bits, bit_word_off, nbits, N, n, codes, counts, hist_off, n_distinct, err,              \
+        kCountCap + 1, INT_MAX);                                                                \
     break;
   switch (wpl) {
     SSH_SHINGLE_CASE(1)
