@@ -61,7 +61,7 @@ typedef int32_t ssh_status;
 #define SSH_MAX_W 256            /* longest supported filter                */
 #define SSH_MAX_N 16             /* longest supported shingle               */
 #define SSH_LNS_ENTRIES 65536    /* entries of the prepared ln-count table  */
-#define SSH_CWS_KEY_WEIGHTS 7    /* weights keyed for every token code      */
+#define SSH_CWS_KEY_WEIGHTS 31   /* weights keyed for every token code      */
 #define SSH_CWS_RUN_CAP 4096     /* counts keyed for the codes 0 and 2^n-1  */
 #define SSH_MAX_C 4096           /* largest candidate cap of ssh_probe      */
 #define SSH_MAX_K 1024           /* largest k of dtw_rerank                 */

@@ -17,7 +17,7 @@
 // One wavefront hashes one series, each lane two hashes.  The exact argmin is
 // found in two passes whose combination equals the first minimum of the
 // ascending float64 scan, i.e. the lexicographic minimum of (ln a, k):
-//  A. keyed tokens (all of them in practice): tokens of weight 1..7, and
+//  A. keyed tokens (all of them in practice): tokens of weight 1..31, and
 //     the two run codes 0 and 2^n - 1 (which collect the constant stretches of
 //     the bit stream and alone reach large weights) up to weight 4096.  The
 //     prepare kernel stores, per (key row, hash), a 16-bit key that is a
@@ -194,10 +194,19 @@ __device__ __forceinline__ uint32_t key16(double la) {
   return (uint32_t)c;
 }
 
+// the lnS table: correctly rounded ln s for every s < SSH_LNS_ENTRIES
+__global__ __launch_bounds__(256) void cws_lns_kernel(double* __restrict__ lnS) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < SSH_LNS_ENTRIES; s += stride)
+    lnS[s] = s == 0 ? -INFINITY : ln_integer((double)s);
+}
+
+// the key rows, the weight-1 ln a and the (r, beta) table; ln w from the lnS
+// table written by cws_lns_kernel before it on the stream
 __global__ __launch_bounds__(256) void cws_prepare_kernel(
     const double* __restrict__ r, const double* __restrict__ lnc, const double* __restrict__ beta,
     int n, int H, double* __restrict__ a1, uint16_t* __restrict__ k16,
-    double* __restrict__ lnS, double2* __restrict__ rb, int* err) {
+    const double* __restrict__ lnS, double2* __restrict__ rb, int* err) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t rows = key_rows(n);
   const int64_t cells = rows * key_table_cols(H);
@@ -224,8 +233,7 @@ __global__ __launch_bounds__(256) void cws_prepare_kernel(
     }
     const int64_t i = (int64_t)code * H + j;
     const double rr = r[i], bb = beta[i], lc = lnc[i];
-    // the same correctly rounded logarithm as the lnS table entry w
-    const double ls = w == 1u ? 0.0 : ln_integer((double)w);
+    const double ls = lnS[w];  // the table's correctly rounded ln w (w <= SSH_CWS_RUN_CAP)
     double tt;
     const double a = icws_ln_a(rr, bb, lc, ls, tt);
     k16[c] = (uint16_t)key16(a);
@@ -239,8 +247,6 @@ __global__ __launch_bounds__(256) void cws_prepare_kernel(
         atomicOr(err, 2);
     }
   }
-  for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < SSH_LNS_ENTRIES; s += stride)
-    lnS[s] = s == 0 ? -INFINITY : ln_integer((double)s);
 }
 
 // ---------------------------------------------------------------------------
@@ -592,6 +598,7 @@ ssh_status cws_prepare_launch(const ssh_cws_tables* tab, hipStream_t stream) {
   int* err = nullptr;
   if (hipGetSymbolAddress((void**)&err, HIP_SYMBOL(g_cws_err)) != hipSuccess)
     return fail(SSH_EDEVICE, "ssh_cws_prepare: cannot resolve error flag");
+  cws_lns_kernel<<<grid_for(SSH_LNS_ENTRIES, 256, 4096), 256, 0, stream>>>(tab->lnS);
   cws_prepare_kernel<<<grid_for(key_rows(tab->n) * key_table_cols(tab->H), 256, 4096), 256, 0,
                        stream>>>(
       tab->r, tab->lnc, tab->beta, tab->n, tab->H, tab->a1, tab->k16, tab->lnS,

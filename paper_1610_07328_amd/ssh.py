@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(_HERE, "libssh_hip.so")
 HV_EMPTY = (1 << 64) - 1
 KEY_EMPTY = (1 << 64) - 1
 LNS_ENTRIES = 65536
-CWS_KEY_WEIGHTS = 7
+CWS_KEY_WEIGHTS = 31
 CWS_RUN_CAP = 4096
 MAX_C = 4096
 

@@ -130,7 +130,7 @@ def test_validation_rejects_without_device_work(ssh):
     # empty batches are not errors
     assert L.ssh_sketch(None, None, 0, r.ctypes.data, 8, 1, None, None, None, None, None) == 0
     # key-table sizes: chunks of 128 hashes, a chunk above 96 hashes padded to 128
-    rows = lambda n: 7 * (1 << n) + 2 * 4096 + 1
+    rows = lambda n: ssh.CWS_KEY_WEIGHTS * (1 << n) + 2 * ssh.CWS_RUN_CAP + 1
     assert L.ssh_cws_key_table_elems(15, 100) == rows(15) * 128
     assert L.ssh_cws_key_table_elems(15, 200) == rows(15) * (128 + 72)
     assert L.ssh_cws_key_table_elems(15, 257) == rows(15) * (128 + 128 + 2)
