@@ -135,155 +135,169 @@ __global__ __launch_bounds__(kShWaves * kWave) void shingle_kernel(
     }
   };
 
-  for (int64_t s = (int64_t)blockIdx.x * kShWaves + w; s < N; s += (int64_t)gridDim.x * kShWaves) {
-    const int nb = nbits[s];
-    const int S = nb >= n ? nb - n + 1 : 0;
-    if (S < s_lo || S > s_hi) continue;  // the other launch's series
-    const int64_t ho = hist_off[s];
-    if (S == 0) {
-      if (lane == 0) n_distinct[s] = 0;
-      continue;
-    }
-    const int64_t wo = bit_word_off[s];
-    const int nw = (nb + 63) / 64;
-    if (hist_off[s + 1] - ho < S || bit_word_off[s + 1] - wo < nw) {
-      if (lane == 0) {
-        atomicOr(err, 1);
-        n_distinct[s] = 0;
+  // The wave's series are s0 + k stride, k = 0, 1, ...  It reads the bit
+  // counts of 64 of them at once (one per lane) and takes, in order, those
+  // whose shingle count this launch handles, so skipping the other launch's
+  // series costs no chain of dependent loads.
+  const int64_t s0 = (int64_t)blockIdx.x * kShWaves + w;
+  const int64_t stride = (int64_t)gridDim.x * kShWaves;
+  for (int64_t k0 = 0; s0 + k0 * stride < N; k0 += kWave) {
+    const int64_t sl = s0 + (k0 + lane) * stride;
+    const int nbl = sl < N ? nbits[sl] : 0;
+    const int Sl = nbl >= n ? nbl - n + 1 : 0;
+    uint64_t todo = ballot64(sl < N && Sl >= s_lo && Sl <= s_hi);
+    while (todo) {
+      const int j = __builtin_ctzll(todo);
+      todo &= todo - 1;
+      const int64_t s = s0 + (k0 + j) * stride;
+      const int nb = __builtin_amdgcn_readlane(nbl, j);
+      const int S = nb >= n ? nb - n + 1 : 0;
+      const int64_t ho = hist_off[s];
+      if (S == 0) {
+        if (lane == 0) n_distinct[s] = 0;
+        continue;
       }
-      continue;
-    }
-    const __amdgpu_buffer_rsrc_t ws = __builtin_amdgcn_make_buffer_rsrc(
-        (void*)(bits + wo), 0, 8 * nw, 0x00020000);
-    uint32_t* const codes_s = codes + ho;
-    uint32_t* const counts_s = counts + ho;
-    int P = (S + kWave - 1) / kWave;
-    if (P > 33 - n) P = 33 - n;
-    const int per_round = kWave * P;
-
-    // 1. mark the tokens (the first round's stream window is kept for step 3)
-    uint32_t rev0 = 0;
-    for (int base = 0; base < S; base += per_round) {
-      const int b0 = base + lane * P;
-      if (b0 < S) {
-        const uint32_t rev = __builtin_bitreverse32(stream_window(ws, b0));
-        if (base == 0) rev0 = rev;
-        const int kend = S - b0 < P ? S - b0 : P;
-        uint32_t prev = 0xFFFFFFFFu;
-        for (int k = 0; k < kend; ++k) {
-          const uint32_t t = (rev >> (32 - n - k)) & mask;
-          if (t != prev) atomicOr(bm + bslot(t >> 5), 1u << (t & 31));
-          prev = t;
+      const int64_t wo = bit_word_off[s];
+      const int nw = (nb + 63) / 64;
+      if (hist_off[s + 1] - ho < S || bit_word_off[s + 1] - wo < nw) {
+        if (lane == 0) {
+          atomicOr(err, 1);
+          n_distinct[s] = 0;
         }
+        continue;
       }
-    }
-    wave_sync_lds();
+      const __amdgpu_buffer_rsrc_t ws = __builtin_amdgcn_make_buffer_rsrc(
+          (void*)(bits + wo), 0, 8 * nw, 0x00020000);
+      uint32_t* const codes_s = codes + ho;
+      uint32_t* const counts_s = counts + ho;
+      int P = (S + kWave - 1) / kWave;
+      if (P > 33 - n) P = 33 - n;
+      const int per_round = kWave * P;
 
-    // 2. rank of the first token of every bitmap word, and D
-    uint32_t wv[WPL];
-    if constexpr (WPL >= 4) {
-#pragma unroll
-      for (int q = 0; q < WPL / 4; ++q) {
-        const uint4 v = reinterpret_cast<const uint4*>(mybm)[q];
-        wv[4 * q] = v.x; wv[4 * q + 1] = v.y; wv[4 * q + 2] = v.z; wv[4 * q + 3] = v.w;
-      }
-    } else if constexpr (WPL == 2) {
-      const uint2 v = reinterpret_cast<const uint2*>(mybm)[0];
-      wv[0] = v.x; wv[1] = v.y;
-    } else {
-      wv[0] = own ? mybm[0] : 0u;
-    }
-    uint32_t c = 0;
-#pragma unroll
-    for (int j = 0; j < WPL; ++j) c += __builtin_popcount(wv[j]);
-    const uint32_t incl = wave_incl_scan_dpp(c);
-    uint32_t rk = incl - c;
-    uint16_t pv[WPL];
-#pragma unroll
-    for (int j = 0; j < WPL; ++j) {
-      pv[j] = (uint16_t)rk;
-      rk += __builtin_popcount(wv[j]);
-    }
-    if constexpr (PAD) {
-      // the bases of word groups 0, GS, 2 GS, ... into the padding words
-      uint4 v;
-      v.x = pv[0] | ((uint32_t)pv[GS] << 16);
-      v.y = pv[2 * GS] | ((uint32_t)pv[3 * GS] << 16);
-      v.z = pv[4 * GS] | ((uint32_t)pv[5 * GS] << 16);
-      v.w = pv[6 * GS] | ((uint32_t)pv[7 * GS] << 16);
-      reinterpret_cast<uint4*>(mypre)[0] = v;
-    } else if constexpr (WPL == 4) {
-      reinterpret_cast<uint2*>(mypre)[0] =
-          make_uint2(pv[0] | ((uint32_t)pv[1] << 16), pv[2] | ((uint32_t)pv[3] << 16));
-    } else if constexpr (WPL == 2) {
-      reinterpret_cast<uint32_t*>(mypre)[0] = pv[0] | ((uint32_t)pv[1] << 16);
-    } else {
-      if (own) mypre[0] = pv[0];
-    }
-    const uint32_t D = __builtin_amdgcn_readlane(incl, kWave - 1);
-    const bool in_lds = D <= (uint32_t)CAP && S < 65536;
-    if (!in_lds) {
-      for (uint32_t i = lane; i < D; i += kWave) counts_s[i] = 0;
-      // this wave's zero stores complete before its atomics below
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    }
-    wave_sync_lds();
-
-    // 3. counts by rank (runs of equal tokens in a lane counted at once), codes
-    // at their ranks; counts in LDS or (more than CAP tokens) in memory,
-    // two copies of the loop so that each uses its own kind of atomic
-    auto step3 = [&](auto lds_counts) {
-      constexpr bool LDS_COUNTS = decltype(lds_counts)::value;
-      auto flush = [&](uint32_t t, uint32_t run) {
-        const uint32_t wd = t >> 5;
-        const uint32_t rank =
-            word_rank(wd) + __builtin_popcount(bm[bslot(wd)] & ((1u << (t & 31)) - 1u));
-        if constexpr (LDS_COUNTS) atomicAdd(cnt + (rank >> 1), run << ((rank & 1u) * 16u));
-        else atomicAdd(counts_s + rank, run);
-        codes_s[rank] = t;
-      };
+      // 1. mark the tokens (the first round's stream window is kept for step 3)
+      uint32_t rev0 = 0;
       for (int base = 0; base < S; base += per_round) {
         const int b0 = base + lane * P;
         if (b0 < S) {
-          const uint32_t rev =
-              base == 0 ? rev0 : __builtin_bitreverse32(stream_window(ws, b0));
+          const uint32_t rev = __builtin_bitreverse32(stream_window(ws, b0));
+          if (base == 0) rev0 = rev;
           const int kend = S - b0 < P ? S - b0 : P;
-          uint32_t prev = (rev >> (32 - n)) & mask;
-          uint32_t run = 1;
-          for (int k = 1; k < kend; ++k) {
+          uint32_t prev = 0xFFFFFFFFu;
+          for (int k = 0; k < kend; ++k) {
             const uint32_t t = (rev >> (32 - n - k)) & mask;
-            if (t == prev) {
-              ++run;
-              continue;
-            }
-            flush(prev, run);
+            if (t != prev) atomicOr(bm + bslot(t >> 5), 1u << (t & 31));
             prev = t;
-            run = 1;
           }
-          flush(prev, run);
         }
       }
-    };
-    if (in_lds) step3(std::true_type{});
-    else step3(std::false_type{});
-    wave_sync_lds();
-
-    // 4. counts out; clear the bitmap words and counts that were used
-    if (in_lds) {
-      for (uint32_t i = lane; i < D; i += kWave) counts_s[i] = (cnt[i >> 1] >> ((i & 1u) * 16u)) & 0xFFFFu;
       wave_sync_lds();
-      for (uint32_t i = lane; i < (D + 1) / 2; i += kWave) cnt[i] = 0;
+
+      // 2. rank of the first token of every bitmap word, and D
+      uint32_t wv[WPL];
+      if constexpr (WPL >= 4) {
+  #pragma unroll
+        for (int q = 0; q < WPL / 4; ++q) {
+          const uint4 v = reinterpret_cast<const uint4*>(mybm)[q];
+          wv[4 * q] = v.x; wv[4 * q + 1] = v.y; wv[4 * q + 2] = v.z; wv[4 * q + 3] = v.w;
+        }
+      } else if constexpr (WPL == 2) {
+        const uint2 v = reinterpret_cast<const uint2*>(mybm)[0];
+        wv[0] = v.x; wv[1] = v.y;
+      } else {
+        wv[0] = own ? mybm[0] : 0u;
+      }
+      uint32_t c = 0;
+  #pragma unroll
+      for (int j = 0; j < WPL; ++j) c += __builtin_popcount(wv[j]);
+      const uint32_t incl = wave_incl_scan_dpp(c);
+      uint32_t rk = incl - c;
+      uint16_t pv[WPL];
+  #pragma unroll
+      for (int j = 0; j < WPL; ++j) {
+        pv[j] = (uint16_t)rk;
+        rk += __builtin_popcount(wv[j]);
+      }
+      if constexpr (PAD) {
+        // the bases of word groups 0, GS, 2 GS, ... into the padding words
+        uint4 v;
+        v.x = pv[0] | ((uint32_t)pv[GS] << 16);
+        v.y = pv[2 * GS] | ((uint32_t)pv[3 * GS] << 16);
+        v.z = pv[4 * GS] | ((uint32_t)pv[5 * GS] << 16);
+        v.w = pv[6 * GS] | ((uint32_t)pv[7 * GS] << 16);
+        reinterpret_cast<uint4*>(mypre)[0] = v;
+      } else if constexpr (WPL == 4) {
+        reinterpret_cast<uint2*>(mypre)[0] =
+            make_uint2(pv[0] | ((uint32_t)pv[1] << 16), pv[2] | ((uint32_t)pv[3] << 16));
+      } else if constexpr (WPL == 2) {
+        reinterpret_cast<uint32_t*>(mypre)[0] = pv[0] | ((uint32_t)pv[1] << 16);
+      } else {
+        if (own) mypre[0] = pv[0];
+      }
+      const uint32_t D = __builtin_amdgcn_readlane(incl, kWave - 1);
+      const bool in_lds = D <= (uint32_t)CAP && S < 65536;
+      if (!in_lds) {
+        for (uint32_t i = lane; i < D; i += kWave) counts_s[i] = 0;
+        // this wave's zero stores complete before its atomics below
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+      }
+      wave_sync_lds();
+
+      // 3. counts by rank (runs of equal tokens in a lane counted at once), codes
+      // at their ranks; counts in LDS or (more than CAP tokens) in memory,
+      // two copies of the loop so that each uses its own kind of atomic
+      auto step3 = [&](auto lds_counts) {
+        constexpr bool LDS_COUNTS = decltype(lds_counts)::value;
+        auto flush = [&](uint32_t t, uint32_t run) {
+          const uint32_t wd = t >> 5;
+          const uint32_t rank =
+              word_rank(wd) + __builtin_popcount(bm[bslot(wd)] & ((1u << (t & 31)) - 1u));
+          if constexpr (LDS_COUNTS) atomicAdd(cnt + (rank >> 1), run << ((rank & 1u) * 16u));
+          else atomicAdd(counts_s + rank, run);
+          codes_s[rank] = t;
+        };
+        for (int base = 0; base < S; base += per_round) {
+          const int b0 = base + lane * P;
+          if (b0 < S) {
+            const uint32_t rev =
+                base == 0 ? rev0 : __builtin_bitreverse32(stream_window(ws, b0));
+            const int kend = S - b0 < P ? S - b0 : P;
+            uint32_t prev = (rev >> (32 - n)) & mask;
+            uint32_t run = 1;
+            for (int k = 1; k < kend; ++k) {
+              const uint32_t t = (rev >> (32 - n - k)) & mask;
+              if (t == prev) {
+                ++run;
+                continue;
+              }
+              flush(prev, run);
+              prev = t;
+              run = 1;
+            }
+            flush(prev, run);
+          }
+        }
+      };
+      if (in_lds) step3(std::true_type{});
+      else step3(std::false_type{});
+      wave_sync_lds();
+
+      // 4. counts out; clear the bitmap words and counts that were used
+      if (in_lds) {
+        for (uint32_t i = lane; i < D; i += kWave) counts_s[i] = (cnt[i >> 1] >> ((i & 1u) * 16u)) & 0xFFFFu;
+        wave_sync_lds();
+        for (uint32_t i = lane; i < (D + 1) / 2; i += kWave) cnt[i] = 0;
+      }
+      if constexpr (WPL >= 4) {
+  #pragma unroll
+        for (int q = 0; q < WPL / 4; ++q) reinterpret_cast<uint4*>(mybm)[q] = make_uint4(0u, 0u, 0u, 0u);
+      } else if constexpr (WPL == 2) {
+        reinterpret_cast<uint2*>(mybm)[0] = make_uint2(0u, 0u);
+      } else {
+        if (own) mybm[0] = 0u;
+      }
+      wave_sync_lds();
+      if (lane == 0) n_distinct[s] = (int32_t)D;
     }
-    if constexpr (WPL >= 4) {
-#pragma unroll
-      for (int q = 0; q < WPL / 4; ++q) reinterpret_cast<uint4*>(mybm)[q] = make_uint4(0u, 0u, 0u, 0u);
-    } else if constexpr (WPL == 2) {
-      reinterpret_cast<uint2*>(mybm)[0] = make_uint2(0u, 0u);
-    } else {
-      if (own) mybm[0] = 0u;
-    }
-    wave_sync_lds();
-    if (lane == 0) n_distinct[s] = (int32_t)D;
   }
 }
 
