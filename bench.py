@@ -73,8 +73,8 @@ MEASURED_TRAFFIC = {
     #                      fetch scale, write scale); the 1 GiB copy read 524307.1 KiB
     #                      on FETCH_SIZE and 1048576 KiB on WRITE_SIZE
     ("cws_kernel", "large"): ("paper_1610_07328_amd/csrc/cws.hip",
-                              "6ad3fe1afccc8b6957020ccd4a5088233ccf215c0980ac207f0582593ea865be",
-                              149563515.1875, 17739174.8125, 1048576.0 / 524307.0625, 1.0),
+                              "25f92e0afb0880325583d2ea1fa427aac3b8de18fbe3b2218d76023454334d74",
+                              147839075.125, 17735884.4375, 1048576.0 / 524307.0625, 1.0),
 }
 
 
