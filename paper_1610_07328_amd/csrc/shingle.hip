@@ -99,7 +99,9 @@ __global__ __launch_bounds__(kShWaves * kWave) void shingle_kernel(
   constexpr int LW = WPL == 1 ? 0 : (WPL == 2 ? 1 : (WPL == 4 ? 2 : (WPL == 8 ? 3 : (WPL == 16 ? 4 : 5))));
   extern __shared__ __attribute__((aligned(16))) uint32_t smem32[];
   const int BW = shingle_bitmap_words(n);
-  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave-uniform
+  // wave-uniform; a constant 0 for one-wave workgroups, so LDS addresses
+  // fold their base into instruction offsets
+  const int w = kShWaves == 1 ? 0 : __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int lane = lane_id();
   uint32_t* bm = smem32 + (shingle_lds_bytes(n, CAP) / 4) * w;
   uint16_t* pre = reinterpret_cast<uint16_t*>(bm + kWave * BS);  // separate bases (!PAD)
@@ -249,8 +251,20 @@ __global__ __launch_bounds__(kShWaves * kWave) void shingle_kernel(
         constexpr bool LDS_COUNTS = decltype(lds_counts)::value;
         auto flush = [&](uint32_t t, uint32_t run) {
           const uint32_t wd = t >> 5;
-          const uint32_t rank =
-              word_rank(wd) + __builtin_popcount(bm[bslot(wd)] & ((1u << (t & 31)) - 1u));
+          uint32_t rank;
+          if constexpr (GS == 2) {
+            // the token's word and its group partner are one aligned 64-bit
+            // pair; t's bit sits at position t mod 64 of the pair and is set,
+            // so shifting it to the top leaves it and the lower bits
+            const uint32_t* run_w = bm + (wd >> LW) * BS;
+            const uint32_t g = (wd & (WPL - 1)) >> 1;
+            const uint2 pr = reinterpret_cast<const uint2*>(run_w)[g];
+            const uint32_t base = reinterpret_cast<const uint16_t*>(run_w + WPL)[g];
+            const uint64_t v = ((uint64_t)pr.y << 32 | pr.x) << ((t ^ 63u) & 63u);
+            rank = base + (uint32_t)__builtin_popcountll(v) - 1u;
+          } else {
+            rank = word_rank(wd) + __builtin_popcount(bm[bslot(wd)] & ((1u << (t & 31)) - 1u));
+          }
           if constexpr (LDS_COUNTS) atomicAdd(cnt + (rank >> 1), run << ((rank & 1u) * 16u));
           else atomicAdd(counts_s + rank, run);
           codes_s[rank] = t;
