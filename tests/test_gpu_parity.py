@@ -148,6 +148,42 @@ def test_sketch_filter_of_wide_dynamic_range(ssh, W, delta):
     assert _assert_sketch_equal(ssh, x, off, r, W, delta) > 0
 
 
+@pytest.mark.parametrize("W,delta", [(80, 3), (128, 4)])
+def test_sketch_l1_margin_items_with_and_without_tiny_samples(ssh, W, delta):
+    """The matrix path's L1 margin at the edge of fp16's normal range: windows
+    whose samples sit just above 2^-14 (the coarsest relative rounding) aimed
+    at a zero sum, the same windows with one sample moved into (0, 2^-14)
+    (subnormal or flushed in fp16: the margin's absolute term), and both
+    planted in random walks of 1024 samples (items of many windows), against
+    the oracle."""
+    _announce(f"sketch L1 margin with and without tiny samples W={W}")
+    rng = np.random.default_rng(W + 5)
+    r = datagen.filter_r(W, seed=W + 5)
+    rr = r.astype(np.float64)
+
+    def aimed(w):
+        w = w.copy()
+        w[-1] = -float(np.dot(rr[:-1], w[:-1])) / rr[-1]
+        return w.astype(np.float32)
+
+    series = []
+    walks = datagen.random_walks(200, 1024, seed=W + 6)
+    for i in range(200):
+        w = rng.choice([-1.0, 1.0], size=W) * 2.0 ** -14 * (1 + 3 * rng.random(W))
+        clean = aimed(w)
+        w[rng.integers(0, W - 1)] = 2.0 ** -16 * (1 + rng.random())
+        tiny = aimed(w)
+        series += [clean, tiny]
+        host = walks[i].copy()
+        at = delta * int(rng.integers(0, (1024 - W) // delta))
+        host[at:at + W] = clean if i % 2 else tiny
+        series.append(host)
+    assert any(np.any((w != 0) & (np.abs(w) < 2.0 ** -14)) for w in series)
+    assert any(not np.any((w != 0) & (np.abs(w) < 2.0 ** -14)) for w in series[::3])
+    x, off = ragged(series)
+    assert _assert_sketch_equal(ssh, x, off, r, W, delta) > 0
+
+
 @pytest.mark.parametrize("W,delta", [(80, 3), (64, 4)])
 def test_sketch_filter_with_subnormal_fp16_entry(ssh, W, delta):
     """A filter entry below 2^-14 (fp16's subnormal range) takes the fast path's
