@@ -50,16 +50,15 @@ __host__ __device__ inline int shingle_wpl(int n) {  // bitmap words per lane
 // fall on distinct LDS banks.  With WPL >= 8 the four padding words hold the
 // lane's rank bases: 8 u16, one per group of WPL / 8 words.  With fewer words
 // per lane the bases (one per word) sit in an array of their own.
-__host__ __device__ inline int shingle_bs(int wpl) { return wpl + (wpl >= 8 ? 4 : 0); }
-__host__ __device__ inline int shingle_pre_u16(int wpl) { return wpl >= 8 ? 0 : kWave * wpl; }
+__host__ __device__ constexpr int shingle_bs(int wpl) { return wpl + (wpl >= 8 ? 4 : 0); }
+__host__ __device__ constexpr int shingle_pre_u16(int wpl) { return wpl >= 8 ? 0 : kWave * wpl; }
 
-// LDS bytes of one wave: bitmap (u32) and rank bases, separate bases (u16, to
-// 16 bytes), counts (u32)
-__host__ __device__ inline size_t shingle_lds_bytes(int n, int cap) {
-  const int wpl = shingle_wpl(n);
-  const size_t bm = (size_t)kWave * shingle_bs(wpl) * 4;
-  const size_t pre = ((size_t)shingle_pre_u16(wpl) * 2 + 15) & ~(size_t)15;
-  return bm + pre + (size_t)cap * 2;
+// LDS bytes of one wave (set by the words per lane: every n <= 11 has one):
+// bitmap (u32) and rank bases, separate bases (u16, to 16 bytes), counts
+// (u16).  The kernel's LDS is a static array of this size, so its addresses
+// are constants the instructions fold in.
+__host__ __device__ constexpr int shingle_lds_bytes(int wpl, int cap) {
+  return kWave * shingle_bs(wpl) * 4 + ((shingle_pre_u16(wpl) * 2 + 15) & ~15) + cap * 2;
 }
 
 // 32 stream bits starting at bit b0 (bit j of the result is stream bit b0 + j),
@@ -97,13 +96,13 @@ __global__ __launch_bounds__(kShWaves * kWave) void shingle_kernel(
   constexpr bool PAD = WPL >= 8;                  // rank bases in the padding words
   constexpr int GS = PAD ? WPL / 8 : 1;           // words per rank base
   constexpr int LW = WPL == 1 ? 0 : (WPL == 2 ? 1 : (WPL == 4 ? 2 : (WPL == 8 ? 3 : (WPL == 16 ? 4 : 5))));
-  extern __shared__ __attribute__((aligned(16))) uint32_t smem32[];
+  __shared__ __attribute__((aligned(16))) uint32_t smem32[kShWaves * shingle_lds_bytes(WPL, CAP) / 4];
   const int BW = shingle_bitmap_words(n);
   // wave-uniform; a constant 0 for one-wave workgroups, so LDS addresses
   // fold their base into instruction offsets
   const int w = kShWaves == 1 ? 0 : __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int lane = lane_id();
-  uint32_t* bm = smem32 + (shingle_lds_bytes(n, CAP) / 4) * w;
+  uint32_t* bm = smem32 + (shingle_lds_bytes(WPL, CAP) / 4) * w;
   uint16_t* pre = reinterpret_cast<uint16_t*>(bm + kWave * BS);  // separate bases (!PAD)
   uint32_t* cnt = bm + kWave * BS + ((shingle_pre_u16(WPL) * 2 + 15) & ~15) / 4;
   // this lane's words exist (WPL > 1: the bitmap is exactly 64 WPL words)
@@ -335,14 +334,12 @@ ssh_status shingle_launch(const uint64_t* bits, const int64_t* bit_word_off, con
   const unsigned grid = grid_for(N, kShWaves, 1 << 16);
   const dim3 block(kShWaves * kWave);
   // series of up to kCountCap shingles, then the longer ones
-  const size_t shm = (size_t)kShWaves * shingle_lds_bytes(n, kCountCap);
-  const size_t shm_long = (size_t)kShWaves * shingle_lds_bytes(n, kCountCapLong);
 #define SSH_SHINGLE_CASE(V)                                                                     \
   case V:                                                                                       \
-    shingle_kernel<V, kCountCap><<<grid, block, shm, stream>>>(                                 \
+    shingle_kernel<V, kCountCap><<<grid, block, 0, stream>>>(                                   \
         bits, bit_word_off, nbits, N, n, codes, counts, hist_off, n_distinct, err, 0,           \
         kCountCap);                                                                             \
-    shingle_kernel<V, kCountCapLong><<<grid, block, shm_long, stream>>>(                        \
+    shingle_kernel<V, kCountCapLong><<<grid, block, 0, stream>>>(                               \
         bits, bit_word_off, nbits, N, n, codes, counts, hist_off, n_distinct, err,              \
         kCountCap + 1, INT_MAX);                                                                \
     break;
