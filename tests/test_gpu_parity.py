@@ -266,6 +266,57 @@ def test_shingle_matches_oracle(ssh, n):
         assert np.array_equal(counts[o:o + nd[s]], wn), s
 
 
+def _de_bruijn_bits(n):
+    """A binary de Bruijn cycle of order n (every n-bit word once as a cyclic
+    window), by the Fredricksen-Kessler-Maiorana concatenation of Lyndon words."""
+    a = [0] * (n + 1)
+    seq = []
+
+    def gen(t, p):
+        if t > n:
+            if n % p == 0:
+                seq.extend(a[1:p + 1])
+            return
+        a[t] = a[t - p]
+        gen(t + 1, p)
+        if a[t - p] == 0:
+            a[t] = 1
+            gen(t + 1, t)
+
+    gen(1, 1)
+    return np.array(seq, np.uint8)
+
+
+@pytest.mark.parametrize("n", [12, 15, 16])
+def test_shingle_every_code_present(ssh, n):
+    """Streams holding every one of the 2^n tokens: the bitmap is full, so the
+    rank bases reach D - 1 (2^16 - 1 at n = 16, the largest 16-bit base) and
+    every rank reads whole words.  Each token once, twice (two cycles), and
+    after a long run of ones; exact against the oracle."""
+    _announce(f"shingle every code n={n}")
+    cyc = _de_bruijn_bits(n)
+    assert len(cyc) == 1 << n
+    once = np.concatenate([cyc, cyc[:n - 1]])
+    twice = np.concatenate([cyc, cyc, cyc[:n - 1]])
+    after_run = np.concatenate([np.ones(3 * n, np.uint8), once])
+    streams = [once, twice, after_run]
+    words, bwo, nb = _pack_streams(streams)
+    hist_off = np.zeros(len(streams) + 1, np.int64)
+    np.cumsum([max(0, int(b) - n + 1) for b in nb], out=hist_off[1:])
+    codes, counts, nd = ssh.shingle(to_dev(words), to_dev(bwo), to_dev(nb), n, to_dev(hist_off))
+    torch.cuda.synchronize()
+    ssh.check_device_errors()
+    codes, counts, nd = to_np(codes), to_np(counts), to_np(nd)
+    for s, b in enumerate(streams):
+        wc, wn = oracle.shingle(b, n)
+        assert len(wc) == 1 << n
+        assert nd[s] == len(wc), (s, nd[s], len(wc))
+        o = hist_off[s]
+        assert np.array_equal(codes[o:o + nd[s]], wc), s
+        assert np.array_equal(counts[o:o + nd[s]], wn), s
+    assert np.all(counts[hist_off[1]:hist_off[1] + nd[1]] == 2)
+
+
 # --------------------------------------------------------------------------
 # weighted MinHash
 # --------------------------------------------------------------------------
