@@ -463,6 +463,61 @@ def run_workload(name: str, args, main: bool):
                                                     for i in range(nq)]))}
         log(f"{name}: recall@10 {recall['recall_at_10']:.3f} on {recall['queries']} queries")
 
+    def hash_agreement(hv, src_ids):
+        """Mean share of a query's hash values equal to its source series' ones."""
+        mine = hv.view(torch.int64)
+        theirs = db.hv.view(torch.int64)[torch.as_tensor(src_ids, device=dev)]
+        return float((mine == theirs).float().mean())
+
+    # query noise sweep: fresh perturbed copies at lower noise through the same
+    # index (hash, probe, re-rank), so the share of queries that find their
+    # source shows where near duplicates survive the sketch's sign bits
+    noise_sweep = []
+    if nrec > 0:
+        t_s = time.perf_counter()
+        nq_s = min(nq, 1024)
+        n_rec_s = max(1, nrec // 2)
+        noise_sweep.append({"noise_std": 0.1, "queries": nq,
+                            "hash_agreement_with_source": hash_agreement(qb.hv[:nq], src),
+                            "source_in_top10": recall["source_in_top10"],
+                            "queries_with_candidates": int((ncand > 0).sum()) / nq,
+                            "recall_at_10": recall["recall_at_10"],
+                            "recall_queries": recall["queries"]})
+        for li, sd in enumerate((0.03, 0.01)):
+            Qs, srcs = datagen.perturbed_queries(first, nq_s, sd, seed=seed + 11 + li)
+            qs, qsoff = datagen.csr(Qs)
+            hbs = HashBatch(torch.as_tensor(qs).to(dev), qsoff, p)
+            qys = QueryBatch(hbs, index)
+            hbs.run(r, tables)
+            qys.probe()
+            qys.rerank()
+            torch.cuda.synchronize()
+            ssh.check_device_errors()
+            ids_s = qys.ids[:nq_s].cpu().numpy()
+            nc_s = qys.ncand[:nq_s].cpu().numpy()
+            pick_s = np.sort(np.random.default_rng(seed + 21 + li).choice(nq_s, n_rec_s,
+                                                                          replace=False))
+            hits, tot = 0, 0
+            for i in pick_s:
+                ex_id, _ = exhaustive_topk(hbs.x[qsoff[i]:qsoff[i + 1]], db.x, db.x_off,
+                                           p.band_frac, p.k)
+                want = set(ex_id.cpu().numpy().tolist()) - {-1}
+                hits += len(want & (set(ids_s[i].tolist()) - {-1}))
+                tot += len(want)
+            noise_sweep.append({
+                "noise_std": sd, "queries": nq_s,
+                "hash_agreement_with_source": hash_agreement(hbs.hv[:nq_s], srcs),
+                "source_in_top10": float(np.mean([srcs[i] in set(ids_s[i].tolist())
+                                                  for i in range(nq_s)])),
+                "queries_with_candidates": float((nc_s > 0).mean()),
+                "recall_at_10": hits / max(tot, 1), "recall_queries": int(len(pick_s))})
+            log(f"{name}: noise {sd}: source in top 10 for "
+                f"{noise_sweep[-1]['source_in_top10']:.3f} of {nq_s} queries, recall@10 "
+                f"{noise_sweep[-1]['recall_at_10']:.3f} on {len(pick_s)}")
+            del hbs, qys
+        recall["noise_sweep"] = noise_sweep
+        recall["noise_sweep_seconds"] = time.perf_counter() - t_s
+
     # the integer-replication weighted MinHash (with band keys) in place of
     # CWS on the same weighted sets, after everything above has read the CWS
     # hash values
