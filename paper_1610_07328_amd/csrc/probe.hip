@@ -30,7 +30,10 @@ constexpr int kPrThreads = 256;
 constexpr int kMaxL = 64;
 constexpr int kMaxH = 1024;
 constexpr int kTieCap = 1024;     // tied ids of one part sorted in LDS; more take the radix select
-constexpr int kScoreCap = 4096;   // entries of one part whose scores are kept in LDS
+// Entries of one part whose scores are kept in LDS (32 KB).  A larger part
+// scores its members again in every pass over them, so the cap covers the
+// parts of queries whose buckets sum to about 130,000 entries.
+constexpr int kScoreCap = 16384;
 constexpr int kMergeCap = 4096;   // keys one merge sorts in LDS
 constexpr int kMaxParts = 8;
 constexpr uint16_t kNotMember = 0xFFFFu;

@@ -853,13 +853,17 @@ def test_c1_wmh_int_pipeline_probe_exact(ssh, c1):
         db.run(r, method="minhash")
 
 
-@pytest.mark.parametrize("C", [1, 7, 100, 600, 4096])
-def test_probe_large_retrieved_sets_with_ties(ssh, C):
+@pytest.mark.parametrize("N,C", [(20000, 1), (20000, 7), (20000, 100), (20000, 600),
+                                  (20000, 4096), (150000, 7), (150000, 600)])
+def test_probe_large_retrieved_sets_with_ties(ssh, N, C):
     """|R| far above C, a tie level larger than a part's in-LDS tie buffer, and
-    every split of a query's entries (8 parts for small C down to 1 for C = 4096)."""
-    _announce(f"probe large R with ties C={C}")
+    every split of a query's entries (8 parts for small C down to 1 for C = 4096).
+    Parts of more entries than the in-LDS score cache holds (16,384) score their
+    members again in each pass: the single part at C = 4096, and every part at
+    N = 150,000."""
+    _announce(f"probe large R with ties N={N} C={C}")
     rng = np.random.default_rng(21)
-    N, L, H = 20000, 2, 8
+    L, H = 2, 8
     hv = rng.integers(0, 2, size=(N, H), dtype=np.int64).astype(np.uint64)
     keys = np.stack([np.where(rng.random(N) < 0.5, np.uint64(11), np.uint64(22)),
                      np.where(rng.random(N) < 0.5, np.uint64(33), np.uint64(44))], 1).astype(np.uint64)
